@@ -1,0 +1,209 @@
+"""Pins of the prox and of FISTA (Algorithm 1): closed forms, one-step exactness,
+objective decrease, the O(1/k^2) rate, KKT at convergence, and brute-force
+minimisers of tiny problems (exhaustive sign / active-set enumeration and an
+independent bound-constrained quasi-Newton solve)."""
+import itertools
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import synth
+from synth.generator import tiny
+from oracle import objectives, fista, lipschitz, conv
+
+
+def test_soft_threshold_closed_form():
+    z = np.array([-3.0, -1.0, -0.5, 0.0, 0.5, 1.0, 3.0])
+    np.testing.assert_array_equal(fista.soft_threshold(z, 1.0), [-2, 0, 0, 0, 0, 0, 2])
+    np.testing.assert_array_equal(fista.prox(z, 1.0, True), [0, 0, 0, 0, 0, 0, 2])
+
+
+def test_prox_minimises_its_objective():
+    rng = np.random.default_rng(0)
+    z = rng.normal(size=200)
+    t = 0.4
+    for pos in (False, True):
+        p = fista.prox(z, t, pos)
+        base = 0.5 * (p - z) ** 2 + t * np.abs(p)
+        for d in (1e-3, -1e-3):
+            q = p + d
+            if pos:
+                q = np.maximum(q, 0)
+            assert np.all(0.5 * (q - z) ** 2 + t * np.abs(q) >= base - 1e-15)
+
+
+def test_momentum_weights():
+    assert fista.momentum(1) == 0.0
+    assert fista.momentum(2) == pytest.approx(0.25)
+    assert fista.momentum(10) == pytest.approx(9 / 12)
+
+
+def _delta_psf(P):
+    psf = np.zeros((P, P))
+    psf[P // 2, P // 2] = 1.0
+    return psf
+
+
+def test_identity_psf_one_step_exact():
+    """H = I, mu = 1/2: one prox step lands on tau_{lambda/2}(y), the minimiser."""
+    n = 8
+    y = np.random.default_rng(1).normal(size=(n, n))
+    s1 = objectives.Step1(y, _delta_psf(2 * n))
+    lam = 0.7
+    for pos in (False, True):
+        b, _ = fista.fista(s1.grad, np.zeros((n, n)), 0.5, lam, 1, positivity=pos)
+        np.testing.assert_allclose(b, fista.prox(y, lam / 2, pos), atol=1e-15)
+        b5, _ = fista.fista(s1.grad, np.zeros((n, n)), 0.5, lam, 5, positivity=pos)
+        np.testing.assert_allclose(b5, fista.prox(y, lam / 2, pos), atol=1e-15)
+
+
+def test_large_lambda_gives_zero():
+    pr = synth.make_problem(tiny(16, seed=5))
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    g0 = s1.grad(np.zeros((16, 16)))  # = -2 H^T y
+    lam = 1.0001 * np.max(np.abs(g0))
+    th, _, _ = lipschitz.power_iteration(s1.normal, 16)
+    b, _ = fista.fista(s1.grad, np.zeros((16, 16)), 1 / (1.01 * th), lam, 50)
+    assert np.all(b == 0)
+
+
+@pytest.fixture(scope="module")
+def small():
+    pr = synth.make_problem(tiny(16, seed=7))
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    th, _, _ = lipschitz.power_iteration(s1.normal, 16, max_iter=2000, rtol=1e-12)
+    return pr, s1, 1.01 * th
+
+
+def test_ista_monotone(small):
+    pr, s1, th = small
+    lam = 0.05 * np.linalg.norm(pr.dirty_L)
+    vals = []
+    fista.fista(s1.grad, np.zeros((16, 16)), 1 / th, lam, 60, momentum_on=False,
+                callback=lambda k, b: vals.append(s1.objective(b, lam)[0]))
+    assert np.all(np.diff(vals) <= 1e-9 * abs(vals[0]))
+
+
+def test_fista_rate(small):
+    pr, s1, th = small
+    lam = 0.05 * np.linalg.norm(pr.dirty_L)
+    for pos in (False, True):
+        vals = []
+        x0 = np.zeros((16, 16))
+        fista.fista(s1.grad, x0, 1 / th, lam, 400, positivity=pos,
+                    callback=lambda k, b: vals.append(s1.objective(b, lam)[0]))
+        xs, _ = fista.fista(s1.grad, x0, 1 / th, lam, 4000, positivity=pos)
+        Fs = s1.objective(xs, lam)[0]
+        assert min(vals) >= Fs - 1e-9 * abs(Fs)
+        dist2 = float(np.sum((x0 - xs) ** 2))
+        for k in (10, 50, 100, 400):
+            # (F(x_k) - F*) (k+1)^2 <= 2 theta ||x0 - x*||^2 for the (k-1)/(k+2) momentum
+            assert (vals[k - 1] - Fs) * (k + 1) ** 2 <= 2 * th * dist2 * 1.0001
+
+
+def _well_conditioned(n, seed):
+    """A point-symmetric PSF whose operator H is far from singular."""
+    P = 2 * n
+    rng = np.random.default_rng(seed)
+    psf = 0.15 * rng.normal(size=(P, P))
+    psf = 0.5 * (psf + np.roll(np.flip(psf, (0, 1)), 1, axis=(0, 1)))
+    psf[P // 2, P // 2] = 1.0
+    y = rng.normal(size=(n, n))
+    return psf, y
+
+
+def test_kkt_and_fixed_point_at_convergence():
+    n = 8
+    psf, y = _well_conditioned(n, 3)
+    s1 = objectives.Step1(y, psf)
+    th = 1.01 * lipschitz.power_iteration(s1.normal, n, max_iter=5000, rtol=1e-13)[0]
+    lam = 0.5
+    for pos in (False, True):
+        xs, _ = fista.fista(s1.grad, np.zeros((n, n)), 1 / th, lam, 5000, positivity=pos)
+        g = s1.grad(xs)
+        nz = xs != 0
+        assert 0 < nz.sum() < n * n
+        if pos:
+            assert np.all(np.abs(g[nz] + lam) <= 1e-9 * lam)
+            assert np.all(g[~nz] >= -lam * (1 + 1e-9))
+        else:
+            assert np.all(np.abs(g[nz] + lam * np.sign(xs[nz])) <= 1e-9 * lam)
+            assert np.all(np.abs(g[~nz]) <= lam * (1 + 1e-9))
+        fp = fista.prox(xs - g / th, lam / th, pos)
+        assert np.max(np.abs(fp - xs)) <= 1e-12 * max(1.0, np.max(np.abs(xs)))
+
+
+def _lasso_objective(M, y, lam, x):
+    r = M @ x - y
+    return float(r @ r + lam * np.sum(np.abs(x)))
+
+
+def _enumerate_minimiser(M, y, lam, positive):
+    """Exact minimiser of ||y - M x||^2 + lam ||x||_1 (+ x >= 0) by enumerating
+    sign patterns (or active sets) and solving each restricted stationarity system."""
+    n = M.shape[1]
+    best, bestx = np.inf, None
+    choices = (0, 1) if positive else (-1, 0, 1)
+    for pattern in itertools.product(choices, repeat=n):
+        s = np.array(pattern, dtype=float)
+        S = s != 0
+        x = np.zeros(n)
+        if S.any():
+            A = M[:, S]
+            # 2 A^T (A x - y) + lam s = 0
+            try:
+                xs = np.linalg.solve(A.T @ A, A.T @ y - 0.5 * lam * s[S])
+            except np.linalg.LinAlgError:
+                continue
+            if np.any(np.sign(xs) != s[S]):
+                continue
+            x[S] = xs
+        val = _lasso_objective(M, y, lam, x)
+        if val < best:
+            best, bestx = val, x
+    return best, bestx
+
+
+@pytest.mark.parametrize("positive", [False, True])
+def test_brute_force_minimiser_n2(positive):
+    """N = 2 (4 unknowns): exhaustive enumeration vs FISTA run to convergence."""
+    n, P = 2, 4
+    rng = np.random.default_rng(11 if positive else 10)
+    psf = rng.uniform(0.1, 1.0, size=(P, P))
+    psf[P // 2, P // 2] = 2.0
+    y = rng.normal(size=(n, n))
+    s1 = objectives.Step1(y, psf)
+    M = np.stack([conv.conv_brute(e.reshape(n, n), psf).ravel() for e in np.eye(n * n)], axis=1)
+    lam = 0.3
+    best, bx = _enumerate_minimiser(M, y.ravel(), lam, positive)
+    th = 2 * np.linalg.eigvalsh(M.T @ M).max()
+    xf, _ = fista.fista(s1.grad, np.zeros((n, n)), 1 / th, lam, 20000, positivity=positive)
+    assert s1.objective(xf, lam)[0] == pytest.approx(best, rel=1e-10)
+    np.testing.assert_allclose(xf.ravel(), bx, atol=1e-7)
+
+
+def test_quasi_newton_split_variables_n8():
+    """An independent solve of the LASSO for N = 8 via x = u - v, u, v >= 0 (L-BFGS-B)."""
+    n = 8
+    psf, y2 = _well_conditioned(n, 17)
+    s1 = objectives.Step1(y2, psf)
+    lam = 0.5
+    M = np.stack([conv.conv_fft(e.reshape(n, n), psf).ravel() for e in np.eye(n * n)], axis=1)
+    y = y2.ravel()
+
+    def f(z):
+        u, v = z[: n * n], z[n * n :]
+        r = M @ (u - v) - y
+        g = 2 * M.T @ r
+        return float(r @ r + lam * np.sum(u + v)), np.concatenate([g + lam, -g + lam])
+
+    res = minimize(f, np.zeros(2 * n * n), jac=True, method="L-BFGS-B",
+                   bounds=[(0, None)] * (2 * n * n),
+                   options={"maxiter": 50000, "maxfun": 100000, "ftol": 1e-16, "gtol": 1e-13})
+    th = 2 * np.linalg.eigvalsh(M.T @ M).max()
+    xf, _ = fista.fista(s1.grad, np.zeros((n, n)), 1 / th, lam, 5000)
+    Ff = s1.objective(xf, lam)[0]
+    assert Ff == pytest.approx(res.fun, rel=1e-8)
+    xq = res.x[: n * n] - res.x[n * n :]
+    np.testing.assert_allclose(xf.ravel(), xq, atol=1e-5)

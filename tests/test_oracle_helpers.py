@@ -1,0 +1,67 @@
+"""Pins of the parameter helpers (Sect. 4.3, Sect. 5, App. A.2) and of the
+two-step driver."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth.generator import tiny
+from oracle import helpers, twostep, objectives
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_sigma2_hat_iid_expectation():
+    """For iid N(0, s^2) pixels a 25-pixel population variance has mean (24/25) s^2."""
+    rng = np.random.default_rng(0)
+    s = 0.3
+    vals = [helpers.sigma2_hat(rng.normal(0, s, (128, 128))) for _ in range(8)]
+    assert np.mean(vals) == pytest.approx(24 / 25 * s * s, rel=5e-3)
+
+
+def test_sigma2_hat_brute_force_windows():
+    img = np.random.default_rng(1).normal(size=(9, 7))
+    acc = []
+    for i in range(9 - 4):
+        for j in range(7 - 4):
+            w = img[i : i + 5, j : j + 5].ravel()
+            acc.append(np.mean((w - w.mean()) ** 2))
+    assert helpers.sigma2_hat(img) == pytest.approx(np.mean(acc), rel=1e-13)
+
+
+def test_eta2_ratio_matches_table2():
+    """Table 2: eta2_hat = 1e-3 sigma2_hat in every row except Sgr B2, ell = 20
+    (printed 2.2e-7 for sigma2_hat = 2.2e-5, a factor 10 off the stated rule)."""
+    rows = np.loadtxt(os.path.join(GOLD, "table2_sigma_eta.txt"), comments="#")
+    hits = 0
+    for ds, ell, s2, s2h, e2, e2h in rows:
+        if helpers.eta2_hat(s2h) == pytest.approx(e2h, rel=1e-9):
+            hits += 1
+        else:
+            assert (ds, ell) == (1, 20)
+    assert hits == 8
+
+
+def test_default_lambda_schedule():
+    d = np.full((4, 4), 0.5)  # ||d||_2 = 2
+    assert helpers.default_lambda(d, 0.05) == pytest.approx(0.1)
+    assert helpers.default_lambda(d, 0.05, cycle=3) == pytest.approx(0.4)
+    assert helpers.default_lambda(d, 0.01) == pytest.approx(0.02)
+
+
+def test_psnr():
+    t = np.zeros((4, 4))
+    t[0, 0] = 10.0
+    x = t + 0.1
+    assert helpers.psnr(x, t) == pytest.approx(20 * np.log10(10 / 0.1))
+
+
+def test_two_step_runs_and_improves():
+    pr = synth.make_problem(tiny(32, seed=2))
+    r = twostep.two_step(pr.dirty_L, pr.psf_L, pr.dirty_H, pr.psf_H, pr.ell, pr.delta, 60, 60,
+                         positivity=True)
+    assert r["eta2"] == pytest.approx(1e-3 * r["sigma2"])
+    s2 = objectives.Step2(pr.dirty_H, pr.psf_H, r["i_L"], pr.ell, pr.delta, r["sigma2"], r["eta2"])
+    assert s2.objective(r["beta2"], r["lambda2"])[0] < s2.objective(np.zeros((32, 32)), r["lambda2"])[0]
+    assert np.all(r["beta2"] >= 0)
