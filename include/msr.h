@@ -1,0 +1,186 @@
+/*
+ * msr.h -- C ABI of libmsr, the MI355X (gfx950) minor-cycle solver of the
+ * two-step radio-interferometric reconstruction of Wang, Prunet, Mignot and
+ * Ferrari, "Multi-Step Reconstruction of Radio-Interferometric Images".
+ *
+ * The library solves, with the dictionary W = I,
+ *   step 1 (Eq. 4):  min_x ||i_L - H_L x||^2 + lambda_L ||x||_1
+ *   step 2 (Eq. 5):  min_x ||G_H (i_H - H_H x)||^2 + ||G_L (l - x)||^2 + lambda_H ||x||_1
+ * with FISTA (Algorithm 1: momentum (k-1)/(k+2), soft threshold at mu*lambda),
+ * the gradients of Eqs. 11-12, the filters of Eqs. 6-10 and the step size
+ * mu = 1/theta, theta = 2 lambda_max of the normal operator (Sect. 3.4).
+ *
+ * Discretisation.  H x = E^T F^-1[h_hat . F(E x)]: E zero-embeds the N x N
+ * image into a P x P grid, F is the P x P DFT, h_hat = F(ifftshift(PSF)).
+ * With pad = 2 (P = 2N) this is the exact linear convolution of the image
+ * with the PSF; with pad = 1 (P = N) it is circular.  G = C_g E: the filter
+ * multiplies the spectrum of the zero-embedded image and its norm is taken
+ * over the whole P x P grid.  The filter radius r of a DFT cell is its
+ * distance from the origin in cells of the P grid (signed indices), and
+ * ell, delta are given in the same unit.
+ *
+ * Conventions.
+ *   - Every call returns msr_status; no C++ exception crosses the ABI.
+ *     msr_last_error() returns a text for the last failed call on a context.
+ *   - Images are float32, row-major, contiguous, device pointers, N x N
+ *     (PSFs: P x P with the phase centre at (P/2, P/2)).  They stay owned by
+ *     the caller; the library keeps no pointer to them after a call returns.
+ *   - All device memory the library uses is one workspace the caller
+ *     allocates (size from msr_workspace_bytes) and hands over with
+ *     msr_set_workspace; the library itself never allocates device memory.
+ *   - Work is ordered on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL is the default stream).  Calls that return scalars
+ *     synchronise that stream before returning.
+ *   - A context is not thread safe; separate contexts are independent.
+ */
+#ifndef MSR_H
+#define MSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSR_ABI_VERSION 1
+
+typedef enum msr_status {
+    MSR_OK = 0,
+    MSR_ERR_INVALID = 1,     /* bad argument, shape or PSF */
+    MSR_ERR_OOM = 2,         /* workspace missing or too small */
+    MSR_ERR_HIP = 3,         /* a HIP runtime call failed (text in msr_last_error) */
+    MSR_ERR_STATE = 4,       /* calls out of order (e.g. step 2 before its PSF or filters) */
+    MSR_ERR_NUMERIC = 5,     /* NaN/Inf in an objective; msr_result.iters says where */
+    MSR_ERR_UNSUPPORTED = 6  /* a combination the library does not implement */
+} msr_status;
+
+typedef struct msr_ctx msr_ctx;
+
+typedef struct msr_config {
+    int32_t n;           /* image side N: a power of two, 8 <= N <= 8192 */
+    int32_t pad;         /* 2: zero padding to P = 2N (linear convolution); 1: circular, P = N */
+    int32_t positivity;  /* 0: l1 prox (the paper); 1: l1 plus the constraint x >= 0 */
+    int32_t device;      /* HIP device ordinal */
+    uint64_t seed;       /* power-iteration start vector seed (SplitMix64 counter) */
+    double prune_tol;    /* spectral columns k_x whose |h_hat| stays below prune_tol * max|h_hat|
+                            are treated as zero; 0 keeps every column */
+} msr_config;
+
+typedef struct msr_solve {
+    double lambda;       /* regularisation weight lambda of Eq. 4 / Eq. 5 */
+    int32_t max_iters;   /* number of FISTA prox steps K */
+    int32_t check_every; /* evaluate F(beta_k) exactly every m steps (0: only at the end) */
+    double tol;          /* stop once (F(beta_k) - f_ref) / |f_ref| <= tol (needs f_ref != 0, check_every > 0) */
+    double f_ref;        /* reference objective F* for the stopping rule (0: no rule) */
+} msr_solve;
+
+typedef struct msr_result {
+    int32_t iters;       /* prox steps done */
+    int32_t converged;   /* 1 if the tol rule stopped the loop */
+    double objective;    /* F(beta) at the end (FP64 reductions) */
+    double data_term;    /* the data term(s) of F */
+    double l1_norm;      /* ||beta||_1 */
+    double theta;        /* Lipschitz constant used (mu = 1/theta) */
+    double elapsed_ms;   /* device time of the iteration loop, objective checks included */
+    double time_to_tol_ms; /* device time until the tol rule held (-1 if never) */
+} msr_result;
+
+/* Returns MSR_ABI_VERSION. */
+int msr_abi_version(void);
+
+/* Validates cfg and creates a context on cfg->device.  Returns MSR_ERR_INVALID
+ * for an unsupported n or pad.  *out is set to NULL on failure. */
+msr_status msr_init(const msr_config* cfg, msr_ctx** out);
+
+/* Destroys a context (NULL is allowed).  The workspace stays the caller's. */
+void msr_destroy(msr_ctx* ctx);
+
+/* Text of the last error on ctx (never NULL; "" when there was none). */
+const char* msr_last_error(const msr_ctx* ctx);
+
+/* Bytes of device workspace a context with this configuration needs (0 for an
+ * invalid configuration). */
+size_t msr_workspace_bytes(const msr_config* cfg);
+
+/* Hands the library its workspace: dev must be device memory of at least
+ * msr_workspace_bytes bytes, 256-byte aligned, and must outlive the context's
+ * use of it.  Invalidates everything computed before. */
+msr_status msr_set_workspace(msr_ctx* ctx, void* dev, size_t bytes);
+
+/* Sets the dirty image i_s and the PSF of step s (1 = short baselines, L;
+ * 2 = long baselines, H) -- the inputs of Eq. 4 / Eq. 5.  Computes and caches
+ * h_hat = Re F(ifftshift(PSF)) (Sect. 3.2-3.3, "the convolution by the PSF").
+ * Fails with MSR_ERR_INVALID if PSF[P/2][P/2] differs from 1 by more than
+ * 1e-5, or if max|Im h_hat| > 1e-4 max|h_hat| (a PSF that is not point
+ * symmetric).  dirty: N x N; psf: P x P.  Invalidates that step's theta. */
+msr_status msr_set_dirty_psf(msr_ctx* ctx, int step, const float* dirty, const float* psf, void* stream);
+
+/* The filters of Eqs. 6-10 for step 2: centre ell and half-width delta of the
+ * overlap band (grid cells), and the noise variances sigma^2 (of i_H) and
+ * eta^2 (of the low-resolution image).  Requires delta > 0, sigma2 > 0,
+ * eta2 > 0.  Invalidates step 2's theta. */
+msr_status msr_set_filters(msr_ctx* ctx, double ell, double delta, double sigma2, double eta2);
+
+/* theta_s = 2 lambda_max of the step's normal operator by power iteration
+ * (Sect. 3.4), started from v0[n] = splitmix64_mix(seed + n) * 2^-64 - 1/2,
+ * stopped when |theta_j - theta_{j-1}| <= rtol * theta_j or after max_iter
+ * applications.  Writes the estimate to *theta and the number of operator
+ * applications to *iters (either may be NULL).  The solver then uses
+ * margin * estimate as its Lipschitz constant (margin 1.01, see
+ * msr_set_lipschitz to override). */
+msr_status msr_lipschitz(msr_ctx* ctx, int step, int max_iter, double rtol, double* theta, int* iters, void* stream);
+
+/* Overrides the Lipschitz constant theta used by step s (mu = 1/theta). */
+msr_status msr_set_lipschitz(msr_ctx* ctx, int step, double theta);
+
+/* Step 1: FISTA on Eq. 4 from x0 (NULL: zeros).  Writes beta_K to model_out
+ * (N x N).  If image_out is not NULL it receives the low-resolution image
+ * i_L = beta_K + (i_L~ - H_L beta_K) (Sect. 3.2, one major cycle).  Computes
+ * theta by power iteration first if none is cached.  Fills *res (may be
+ * NULL).  Blocks until the results are written. */
+msr_status msr_step1_low_res(msr_ctx* ctx, const msr_solve* opt, const float* x0,
+                             float* model_out, float* image_out, msr_result* res, void* stream);
+
+/* Step 2: FISTA on Eq. 5 with the constraint image l = low_res (N x N), from
+ * x0 (NULL: zeros; any warm start may be passed here).  Requires
+ * msr_set_dirty_psf(step 2) and msr_set_filters, else MSR_ERR_STATE. */
+msr_status msr_step2_full_res(msr_ctx* ctx, const msr_solve* opt, const float* low_res, const float* x0,
+                              float* model_out, msr_result* res, void* stream);
+
+/* Exact objective of step s at x: out[0] = F(x), out[1] = data term(s),
+ * out[2] = ||x||_1 (FP64 accumulation).  low_res is required for step 2. */
+msr_status msr_objective(msr_ctx* ctx, int step, double lambda, const float* x, const float* low_res,
+                         double out[3], void* stream);
+
+/* Gradient of the smooth part of step s at x (Eq. 11 or Eq. 12), N x N. */
+msr_status msr_gradient(msr_ctx* ctx, int step, const float* x, const float* low_res, float* grad_out,
+                        void* stream);
+
+/* H_s x (N x N in, N x N out): the PSF convolution of step s alone. */
+msr_status msr_apply_psf(msr_ctx* ctx, int step, const float* x, float* out, void* stream);
+
+/* Copies the cached h_hat of step s to host memory as P x (P/2 + 1) doubles
+ * (rfft half plane, row = k_y, column = k_x), pruned columns as zeros, and
+ * writes the number of kept columns to *kept (may be NULL). */
+msr_status msr_get_spectrum(msr_ctx* ctx, int step, double* host_out, int* kept, void* stream);
+
+/* sigma2_hat of Sect. 4.3 on an N x N device image: the mean over all 5 x 5
+ * windows inside the image of the window's population variance (FP64). */
+msr_status msr_estimate_sigma2(msr_ctx* ctx, const float* dirty, double* sigma2, void* stream);
+
+/* Default regularisation weight: c * ||i_s~||_2 * 2^(cycle - 1) (Sect. 5 and
+ * App. A.2), from the dirty image set for step s. */
+msr_status msr_default_lambda(msr_ctx* ctx, int step, int cycle, double c, double* lambda, void* stream);
+
+/* Runs one kernel of the iteration `reps` times back to back on `stream` and
+ * returns its mean device time in milliseconds, plus the algorithmic bytes one
+ * launch moves.  which: 0 = column convolution pass, 1 = residual row pass,
+ * 2 = fused update row pass (step 1 shapes, current state).  For measurement. */
+msr_status msr_time_pass(msr_ctx* ctx, int which, int reps, double* ms, double* bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSR_H */

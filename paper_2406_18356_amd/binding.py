@@ -1,0 +1,263 @@
+"""ctypes binding of libmsr (argument marshalling only).
+
+Names follow the C ABI in ``include/msr.h``.  Tensors must be float32,
+contiguous and on the context's device; their ``data_ptr()`` and the current
+stream's handle are passed through unchanged.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libmsr.so"
+
+OK, ERR_INVALID, ERR_OOM, ERR_HIP, ERR_STATE, ERR_NUMERIC, ERR_UNSUPPORTED = range(7)
+_STATUS = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "STATE", 5: "NUMERIC", 6: "UNSUPPORTED"}
+
+
+class MsrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"msr error {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32),
+        ("pad", C.c_int32),
+        ("positivity", C.c_int32),
+        ("device", C.c_int32),
+        ("seed", C.c_uint64),
+        ("prune_tol", C.c_double),
+    ]
+
+
+class SolveOptions(C.Structure):
+    _fields_ = [
+        ("lam", C.c_double),
+        ("max_iters", C.c_int32),
+        ("check_every", C.c_int32),
+        ("tol", C.c_double),
+        ("f_ref", C.c_double),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32),
+        ("converged", C.c_int32),
+        ("objective", C.c_double),
+        ("data_term", C.c_double),
+        ("l1_norm", C.c_double),
+        ("theta", C.c_double),
+        ("elapsed_ms", C.c_double),
+        ("time_to_tol_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# exported symbol -> (restype, argtypes)
+_P = C.c_void_p
+_ST = C.c_int
+SYMBOLS = {
+    "msr_abi_version": (C.c_int, []),
+    "msr_init": (_ST, [C.POINTER(Config), C.POINTER(_P)]),
+    "msr_destroy": (None, [_P]),
+    "msr_last_error": (C.c_char_p, [_P]),
+    "msr_workspace_bytes": (C.c_size_t, [C.POINTER(Config)]),
+    "msr_set_workspace": (_ST, [_P, _P, C.c_size_t]),
+    "msr_set_dirty_psf": (_ST, [_P, C.c_int, _P, _P, _P]),
+    "msr_set_filters": (_ST, [_P, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "msr_lipschitz": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int), _P]),
+    "msr_set_lipschitz": (_ST, [_P, C.c_int, C.c_double]),
+    "msr_step1_low_res": (_ST, [_P, C.POINTER(SolveOptions), _P, _P, _P, C.POINTER(Result), _P]),
+    "msr_step2_full_res": (_ST, [_P, C.POINTER(SolveOptions), _P, _P, _P, C.POINTER(Result), _P]),
+    "msr_objective": (_ST, [_P, C.c_int, C.c_double, _P, _P, C.POINTER(C.c_double), _P]),
+    "msr_gradient": (_ST, [_P, C.c_int, _P, _P, _P, _P]),
+    "msr_apply_psf": (_ST, [_P, C.c_int, _P, _P, _P]),
+    "msr_get_spectrum": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _P]),
+    "msr_estimate_sigma2": (_ST, [_P, _P, C.POINTER(C.c_double), _P]),
+    "msr_default_lambda": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), _P]),
+    "msr_time_pass": (_ST, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]),
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.environ.get("MSR_LIBRARY", os.path.join(HERE, _LIB_NAME))
+
+
+def lib() -> C.CDLL:
+    """Loads libmsr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} not found: build it with `python -m paper_2406_18356_amd.build`")
+        L = C.CDLL(path)
+        for name, (res, args) in SYMBOLS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def abi_version() -> int:
+    return lib().msr_abi_version()
+
+
+def _cfg(n, pad=2, positivity=False, device=0, seed=0, prune_tol=1e-6) -> Config:
+    return Config(int(n), int(pad), int(bool(positivity)), int(device), int(seed), float(prune_tol))
+
+
+def workspace_bytes(n, pad=2, positivity=False, seed=0, prune_tol=1e-6) -> int:
+    c = _cfg(n, pad, positivity, 0, seed, prune_tol)
+    return int(lib().msr_workspace_bytes(C.byref(c)))
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+
+    if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("tensors must be contiguous float32 on the GPU")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One libmsr context with a torch-owned workspace.
+
+    >>> s = Solver(n=256, positivity=True)
+    >>> s.set_dirty_psf(1, dirty_L, psf_L); s.set_dirty_psf(2, dirty_H, psf_H)
+    >>> beta1, i_L, r1 = s.step1(lam1, iters=200, image=True)
+    >>> s.set_filters(ell, delta, sigma2, eta2)
+    >>> beta2, r2 = s.step2(lam2, i_L, iters=200)
+    """
+
+    def __init__(self, n: int, pad: int = 2, positivity: bool = False, device: int = 0, seed: int = 0,
+                 prune_tol: float = 1e-6):
+        import torch
+
+        self._lib = lib()
+        self.n = n
+        self.P = pad * n
+        self.device = torch.device("cuda", device)
+        cfg = _cfg(n, pad, positivity, device, seed, prune_tol)
+        h = C.c_void_p()
+        st = self._lib.msr_init(C.byref(cfg), C.byref(h))
+        if st != OK:
+            raise MsrError(st, "msr_init rejected the configuration")
+        self._h = h
+        nbytes = int(self._lib.msr_workspace_bytes(C.byref(cfg)))
+        # 256-byte aligned workspace owned by torch
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(self._lib.msr_set_workspace(self._h, C.c_void_p(aligned), nbytes))
+        self.workspace_bytes = nbytes
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.msr_destroy(h)
+            self._h = None
+
+    def _check(self, st):
+        if st != OK:
+            msg = self._lib.msr_last_error(self._h)
+            raise MsrError(st, msg.decode() if msg else "")
+
+    def _img(self):
+        import torch
+
+        return torch.empty((self.n, self.n), dtype=torch.float32, device=self.device)
+
+    # -- setup ------------------------------------------------------------------
+    def set_dirty_psf(self, step: int, dirty, psf, stream=None):
+        self._check(self._lib.msr_set_dirty_psf(self._h, step, _ptr(dirty), _ptr(psf), _stream(stream)))
+
+    def set_filters(self, ell, delta, sigma2, eta2):
+        self._check(self._lib.msr_set_filters(self._h, float(ell), float(delta), float(sigma2), float(eta2)))
+
+    def lipschitz(self, step: int, max_iter: int = 200, rtol: float = 1e-6, stream=None):
+        th = C.c_double()
+        it = C.c_int()
+        self._check(self._lib.msr_lipschitz(self._h, step, max_iter, rtol, C.byref(th), C.byref(it), _stream(stream)))
+        return th.value, it.value
+
+    def set_lipschitz(self, step: int, theta: float):
+        self._check(self._lib.msr_set_lipschitz(self._h, step, float(theta)))
+
+    # -- solves -----------------------------------------------------------------
+    def step1(self, lam, iters, x0=None, image=False, check_every=0, tol=0.0, f_ref=0.0, out=None, stream=None):
+        opt = SolveOptions(float(lam), int(iters), int(check_every), float(tol), float(f_ref))
+        res = Result()
+        beta = out if out is not None else self._img()
+        img = self._img() if image else None
+        self._check(self._lib.msr_step1_low_res(self._h, C.byref(opt), _ptr(x0), _ptr(beta), _ptr(img),
+                                                C.byref(res), _stream(stream)))
+        return (beta, img, res) if image else (beta, res)
+
+    def step2(self, lam, low_res, iters, x0=None, check_every=0, tol=0.0, f_ref=0.0, out=None, stream=None):
+        opt = SolveOptions(float(lam), int(iters), int(check_every), float(tol), float(f_ref))
+        res = Result()
+        beta = out if out is not None else self._img()
+        self._check(self._lib.msr_step2_full_res(self._h, C.byref(opt), _ptr(low_res), _ptr(x0), _ptr(beta),
+                                                 C.byref(res), _stream(stream)))
+        return beta, res
+
+    # -- single operators ------------------------------------------------------
+    def objective(self, step, lam, x, low_res=None, stream=None):
+        out = (C.c_double * 3)()
+        self._check(self._lib.msr_objective(self._h, step, float(lam), _ptr(x), _ptr(low_res), out, _stream(stream)))
+        return tuple(out)
+
+    def gradient(self, step, x, low_res=None, stream=None):
+        g = self._img()
+        self._check(self._lib.msr_gradient(self._h, step, _ptr(x), _ptr(low_res), _ptr(g), _stream(stream)))
+        return g
+
+    def apply_psf(self, step, x, stream=None):
+        y = self._img()
+        self._check(self._lib.msr_apply_psf(self._h, step, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def spectrum(self, step, stream=None):
+        import numpy as np
+
+        out = np.zeros((self.P, self.P // 2 + 1), dtype=np.float64)
+        kept = C.c_int()
+        self._check(self._lib.msr_get_spectrum(self._h, step, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                               C.byref(kept), _stream(stream)))
+        return out, kept.value
+
+    def estimate_sigma2(self, dirty, stream=None):
+        v = C.c_double()
+        self._check(self._lib.msr_estimate_sigma2(self._h, _ptr(dirty), C.byref(v), _stream(stream)))
+        return v.value
+
+    def default_lambda(self, step, cycle=1, c=0.05, stream=None):
+        v = C.c_double()
+        self._check(self._lib.msr_default_lambda(self._h, step, cycle, float(c), C.byref(v), _stream(stream)))
+        return v.value
+
+    def time_pass(self, which, reps=20, stream=None):
+        ms = C.c_double()
+        by = C.c_double()
+        self._check(self._lib.msr_time_pass(self._h, which, reps, C.byref(ms), C.byref(by), _stream(stream)))
+        return ms.value, by.value

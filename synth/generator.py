@@ -260,7 +260,8 @@ def _dirty_from_weights(sky: np.ndarray, w: np.ndarray, noise_rel: float, rng) -
     return clean + rng.normal(0.0, sd, clean.shape)
 
 
-def make_problem(cfg: ProblemConfig) -> Problem:
+def make_problem(cfg: ProblemConfig, with_full: bool = True) -> Problem:
+    """Builds the problem; ``with_full=False`` skips the all-baseline PSF/dirty image."""
     n, P = cfg.n, cfg.P
     if n < 4 or (n & (n - 1)):
         raise ValueError("n must be a power of two >= 4")
@@ -277,11 +278,14 @@ def make_problem(cfg: ProblemConfig) -> Problem:
     w_full, w_L, w_H, counts = grid_weights(xyz, cfg.array, P, cfg.uv_fill, ell, delta)
     psf_L = _psf_from_weights(w_L)
     psf_H = _psf_from_weights(w_H)
-    psf_full = _psf_from_weights(w_full)
     gen = lambda s: np.random.Generator(np.random.PCG64(s))  # noqa: E731
     dirty_L = _dirty_from_weights(sky, w_L, cfg.noise_rel, gen(s_nL))
     dirty_H = _dirty_from_weights(sky, w_H, cfg.noise_rel, gen(s_nH))
-    dirty_full = _dirty_from_weights(sky, w_full, cfg.noise_rel, gen(s_nF))
+    if with_full:
+        psf_full = _psf_from_weights(w_full)
+        dirty_full = _dirty_from_weights(sky, w_full, cfg.noise_rel, gen(s_nF))
+    else:
+        psf_full = dirty_full = None
     return Problem(
         cfg=cfg, n=n, P=P, sky=sky,
         w_L=w_L, w_H=w_H, w_full=w_full,

@@ -1,0 +1,71 @@
+"""The C ABI library loads without a GPU and exports every function that
+include/msr.h declares; pure host calls behave."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msr.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(msr_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2406_18356_amd import binding
+
+    if not os.path.exists(binding.library_path()):
+        pytest.fail("libmsr.so is not built (run __graft_entry__.build())")
+    return binding.lib()
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for must in ("msr_init", "msr_set_dirty_psf", "msr_step1_low_res", "msr_step2_full_res", "msr_objective"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    from paper_2406_18356_amd import binding
+
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in binding.SYMBOLS, name
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.library_path()], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (msr_[a-z0-9_]+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_abi_version(lib):
+    txt = open(HEADER).read()
+    v = int(re.search(r"#define MSR_ABI_VERSION (\d+)", txt).group(1))
+    assert lib.msr_abi_version() == v
+
+
+def test_workspace_bytes_host_only(lib):
+    from paper_2406_18356_amd import binding
+
+    b = binding.workspace_bytes(256)
+    assert b > 10 * 256 * 256 * 4
+    assert binding.workspace_bytes(2048) > 16 * binding.workspace_bytes(256) * 0.9
+    assert binding.workspace_bytes(12) == 0  # not a power of two
+    assert binding.workspace_bytes(16384) == 0  # above the maximum
+    assert binding.workspace_bytes(256, pad=3) == 0
+
+
+def test_init_rejects_bad_config_before_touching_a_device(lib):
+    from paper_2406_18356_amd import binding
+
+    cfg = binding.Config(12, 2, 0, 0, 0, 1e-6)
+    h = C.c_void_p(1)
+    assert lib.msr_init(C.byref(cfg), C.byref(h)) == binding.ERR_INVALID
+    assert not h.value
+    lib.msr_destroy(None)
+    assert lib.msr_last_error(None) == b"null context"

@@ -1,0 +1,353 @@
+"""GPU (HIP, gfx950) path against the FP64 oracle.
+
+Tolerance: the FP32 GPU path must agree with the FP64 oracle to
+max|x_gpu - x_oracle| / max|x_oracle| <= 1e-5 (images), and scalars to the
+relative tolerances stated per test.  Both sides run from the same seeded
+inputs; FISTA trajectories use the same x0, lambda, K and the same Lipschitz
+constant (passed to the library explicitly), so the comparison is of one
+deterministic trajectory.
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth.generator import tiny
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5          # images: max-abs error over the oracle's peak
+OP_TOL = 2e-6       # single operator applications (H x, gradients)
+SCALAR_TOL = 2e-6   # objectives and reductions (relative)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    print("gpu parity: device", torch.cuda.get_device_name(0), flush=True)
+    return torch, torch.device("cuda:0")
+
+
+def _t(torch_dev, a):
+    torch, dev = torch_dev
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+
+
+def _problem(n, pad=2, seed=5):
+    if n == 256 and pad == 2:
+        return synth.make_problem(synth.preset("small256"))
+    return synth.make_problem(tiny(n, seed=seed).replace(pad=pad))
+
+
+def _solver(torch_dev, pr, positivity=False, prune_tol=1e-6, seed=0):
+    from paper_2406_18356_amd import Solver
+
+    s = Solver(pr.n, pad=pr.cfg.pad, positivity=positivity, prune_tol=prune_tol, seed=seed)
+    s.set_dirty_psf(1, _t(torch_dev, pr.dirty_L), _t(torch_dev, pr.psf_L))
+    s.set_dirty_psf(2, _t(torch_dev, pr.dirty_H), _t(torch_dev, pr.psf_H))
+    return s
+
+
+# ----------------------------------------------------------------- operators
+@pytest.mark.parametrize("n,pad", [(8, 2), (16, 2), (64, 2), (256, 2), (32, 1), (128, 1)])
+def test_psf_spectrum(torch_dev, n, pad):
+    from oracle import conv
+
+    print(f"spectrum n={n} pad={pad}", flush=True)
+    pr = _problem(n, pad)
+    s = _solver(torch_dev, pr)
+    for step, psf in ((1, pr.psf_L), (2, pr.psf_H)):
+        h, kept = s.spectrum(step)
+        ho = conv.psf_spectrum(psf)
+        assert np.max(np.abs(ho.imag)) < 1e-9 * np.max(np.abs(ho.real))
+        ho = ho.real[:, : pr.P // 2 + 1]
+        peak = np.max(np.abs(ho))
+        assert rel(h[:, :kept], ho[:, :kept]) <= OP_TOL
+        # pruned columns only hold values below the pruning threshold (+ FP32 noise)
+        if kept < ho.shape[1]:
+            assert np.max(np.abs(ho[:, kept:])) <= 1e-6 * peak + 1e-7 * peak
+
+
+@pytest.mark.parametrize("n,pad", [(8, 2), (32, 2), (256, 2), (16, 1), (64, 1)])
+def test_apply_psf(torch_dev, n, pad):
+    from oracle import conv
+
+    pr = _problem(n, pad)
+    s = _solver(torch_dev, pr)
+    x = np.random.default_rng(n).normal(size=(n, n))
+    for step, psf in ((1, pr.psf_L), (2, pr.psf_H)):
+        y = s.apply_psf(step, _t(torch_dev, x)).cpu().numpy()
+        assert rel(y, conv.conv_fft(x, psf)) <= OP_TOL
+
+
+@pytest.mark.parametrize("n,pad", [(16, 2), (64, 2), (256, 2), (32, 1)])
+def test_gradients(torch_dev, n, pad):
+    from oracle import objectives
+
+    pr = _problem(n, pad)
+    s = _solver(torch_dev, pr)
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(n, n))
+    l = rng.normal(size=(n, n))
+    s.set_filters(pr.ell, pr.delta, 0.8, 0.3)
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    s2 = objectives.Step2(pr.dirty_H, pr.psf_H, l, pr.ell, pr.delta, 0.8, 0.3)
+    g1 = s.gradient(1, _t(torch_dev, x)).cpu().numpy()
+    g2 = s.gradient(2, _t(torch_dev, x), _t(torch_dev, l)).cpu().numpy()
+    assert rel(g1, s1.grad(x)) <= OP_TOL
+    assert rel(g2, s2.grad(x)) <= OP_TOL
+
+
+@pytest.mark.parametrize("n,pad", [(32, 2), (256, 2), (64, 1)])
+def test_objectives(torch_dev, n, pad):
+    from oracle import objectives
+
+    pr = _problem(n, pad)
+    s = _solver(torch_dev, pr)
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(n, n)) * 0.01
+    l = rng.normal(size=(n, n))
+    lam = 0.37
+    s.set_filters(pr.ell, pr.delta, 1.7, 2e-3)
+    F1 = s.objective(1, lam, _t(torch_dev, x))
+    F2 = s.objective(2, lam, _t(torch_dev, x), _t(torch_dev, l))
+    o1 = objectives.Step1(pr.dirty_L, pr.psf_L).objective(x.astype(np.float32).astype(np.float64), lam)
+    o2 = objectives.Step2(pr.dirty_H, pr.psf_H, l.astype(np.float32), pr.ell, pr.delta, 1.7, 2e-3).objective(
+        x.astype(np.float32).astype(np.float64), lam)
+    for a, b in zip(F1, o1):
+        assert a == pytest.approx(b, rel=SCALAR_TOL)
+    for a, b in zip(F2, o2):
+        assert a == pytest.approx(b, rel=SCALAR_TOL)
+
+
+@pytest.mark.parametrize("n,pad", [(16, 2), (64, 2), (32, 1)])
+def test_lipschitz(torch_dev, n, pad):
+    from oracle import objectives, lipschitz
+
+    pr = _problem(n, pad)
+    s = _solver(torch_dev, pr, seed=9)
+    s.set_filters(pr.ell, pr.delta, 0.8, 0.3)
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    s2 = objectives.Step2(pr.dirty_H, pr.psf_H, np.zeros((n, n)), pr.ell, pr.delta, 0.8, 0.3)
+    for step, prob in ((1, s1), (2, s2)):
+        th, it = s.lipschitz(step, max_iter=500, rtol=1e-9)
+        tho, ito, _ = lipschitz.power_iteration(prob.normal, n, seed=9, max_iter=500, rtol=1e-9)
+        assert th == pytest.approx(tho, rel=1e-5)
+        if pad == 1:  # circular: the paper's closed form (M = 1) is the exact value
+            cf = (lipschitz.closed_form_step1(prob.H.h) if step == 1
+                  else lipschitz.closed_form_step2(prob.H.h, prob.gL2, prob.gH2))
+            assert th == pytest.approx(cf, rel=1e-4)
+
+
+# ----------------------------------------------------------------- FISTA
+def _fista_case(torch_dev, n, pad, positivity, step, K, seed=5):
+    from oracle import objectives, fista, lipschitz
+
+    pr = _problem(n, pad, seed)
+    s = _solver(torch_dev, pr, positivity=positivity)
+    if step == 1:
+        prob = objectives.Step1(pr.dirty_L, pr.psf_L)
+        lam = 0.05 * np.linalg.norm(pr.dirty_L)
+    else:
+        l = np.asarray(pr.dirty_L, np.float32).astype(np.float64) * 0.5
+        sig2 = float(np.var(pr.dirty_H))
+        s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        prob = objectives.Step2(pr.dirty_H, pr.psf_H, l, pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        lam = 0.05 * np.linalg.norm(pr.dirty_H)
+    theta = 1.01 * lipschitz.power_iteration(prob.normal, n)[0]
+    s.set_lipschitz(step, theta)
+    if step == 1:
+        b, r = s.step1(lam, K)
+    else:
+        b, r = s.step2(lam, _t(torch_dev, l), K)
+    bo, _ = fista.fista(prob.grad, np.zeros((n, n)), 1.0 / theta, lam, K, positivity=positivity)
+    return b.cpu().numpy(), bo, r, prob, lam
+
+
+@pytest.mark.parametrize("n,pad,positivity", [(16, 2, False), (64, 2, True), (128, 2, False), (32, 1, True),
+                                              (64, 1, False)])
+@pytest.mark.parametrize("step", [1, 2])
+def test_fista_trajectory(torch_dev, n, pad, positivity, step):
+    print(f"fista n={n} pad={pad} pos={positivity} step={step}", flush=True)
+    b, bo, r, prob, lam = _fista_case(torch_dev, n, pad, positivity, step, 100)
+    assert rel(b, bo) <= TOL
+    Fo = prob.objective(bo, lam)[0]
+    assert r.objective == pytest.approx(Fo, rel=1e-5)
+    assert r.iters == 100
+    if positivity:
+        assert np.all(b >= 0)
+
+
+def test_two_step_small_workload(torch_dev):
+    """The 256^2 workload end to end: 200 iterations per step, positivity on."""
+    from oracle import objectives, fista, lipschitz, helpers
+
+    print("two-step 256", flush=True)
+    pr = _problem(256)
+    s = _solver(torch_dev, pr, positivity=True)
+    K = pr.cfg.iters
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    th1 = 1.01 * lipschitz.power_iteration(s1.normal, 256)[0]
+    lam1 = helpers.default_lambda(pr.dirty_L, 0.05)
+    assert s.default_lambda(1, 1, 0.05) == pytest.approx(lam1, rel=1e-6)
+    s.set_lipschitz(1, th1)
+    b1, iL, r1 = s.step1(lam1, K, image=True)
+    b1o, _ = fista.fista(s1.grad, np.zeros((256, 256)), 1 / th1, lam1, K, positivity=True)
+    iLo = helpers.low_res_image(b1o, pr.dirty_L, s1.H)
+    assert rel(b1.cpu().numpy(), b1o) <= TOL
+    assert rel(iL.cpu().numpy(), iLo) <= TOL
+    sig2 = helpers.sigma2_hat(pr.dirty_H)
+    assert s.estimate_sigma2(_t(torch_dev, pr.dirty_H)) == pytest.approx(sig2, rel=1e-6)
+    eta2 = helpers.eta2_hat(sig2)
+    l32 = iLo.astype(np.float32)
+    s2 = objectives.Step2(pr.dirty_H, pr.psf_H, l32.astype(np.float64), pr.ell, pr.delta, sig2, eta2)
+    th2 = 1.01 * lipschitz.power_iteration(s2.normal, 256)[0]
+    lam2 = helpers.default_lambda(pr.dirty_H, 0.05)
+    s.set_filters(pr.ell, pr.delta, sig2, eta2)
+    s.set_lipschitz(2, th2)
+    b2, r2 = s.step2(lam2, _t(torch_dev, l32), K)
+    b2o, _ = fista.fista(s2.grad, np.zeros((256, 256)), 1 / th2, lam2, K, positivity=True)
+    err2 = rel(b2.cpu().numpy(), b2o)
+    print("two-step errors", rel(b1.cpu().numpy(), b1o), err2, flush=True)
+    assert err2 <= TOL
+    assert r2.objective == pytest.approx(s2.objective(b2o, lam2)[0], rel=1e-5)
+
+
+def test_warm_start_and_degenerate_cases(torch_dev):
+    from oracle import objectives, fista, lipschitz
+
+    pr = _problem(32)
+    s = _solver(torch_dev, pr)
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    th = 1.01 * lipschitz.power_iteration(s1.normal, 32)[0]
+    s.set_lipschitz(1, th)
+    lam = 0.05 * np.linalg.norm(pr.dirty_L)
+    x0 = np.random.default_rng(1).normal(size=(32, 32)).astype(np.float32)
+    b, _ = s.step1(lam, 30, x0=_t(torch_dev, x0))
+    bo, _ = fista.fista(s1.grad, x0.astype(np.float64), 1 / th, lam, 30)
+    assert rel(b.cpu().numpy(), bo) <= TOL
+    # K = 0 returns x0 unchanged
+    b0, r0 = s.step1(lam, 0, x0=_t(torch_dev, x0))
+    np.testing.assert_array_equal(b0.cpu().numpy(), x0)
+    assert r0.iters == 0
+    # lambda above ||2 H^T y||_inf: the minimiser and every iterate from 0 is exactly 0
+    big = 1.01 * np.max(np.abs(s1.grad(np.zeros((32, 32)))))
+    bz, rz = s.step1(big, 20)
+    assert np.all(bz.cpu().numpy() == 0)
+    assert rz.l1_norm == 0.0
+    # zero data: zero solution
+    s.set_dirty_psf(1, _t(torch_dev, np.zeros((32, 32))), _t(torch_dev, pr.psf_L))
+    s.set_lipschitz(1, th)
+    bz2, _ = s.step1(1e-3, 10)
+    assert np.all(bz2.cpu().numpy() == 0)
+
+
+def test_determinism(torch_dev):
+    pr = _problem(64)
+    s = _solver(torch_dev, pr, positivity=True)
+    lam = 0.05 * np.linalg.norm(pr.dirty_L)
+    s.set_lipschitz(1, 1e6)
+    a, ra = s.step1(lam, 40)
+    b, rb = s.step1(lam, 40)
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    assert ra.objective == rb.objective
+    th1, _ = s.lipschitz(1)
+    th2, _ = s.lipschitz(1)
+    assert th1 == th2
+
+
+def test_stopping_rule(torch_dev):
+    """With f_ref = F* from a long run, the tol rule stops early and reports time to tolerance."""
+    pr = _problem(64)
+    s = _solver(torch_dev, pr, positivity=True)
+    lam = 0.05 * np.linalg.norm(pr.dirty_L)
+    _, rlong = s.step1(lam, 3000)
+    fstar = rlong.objective
+    _, r = s.step1(lam, 3000, check_every=5, tol=1e-3, f_ref=fstar)
+    assert r.converged == 1
+    assert r.iters < 3000 and r.iters % 5 == 0
+    assert r.time_to_tol_ms > 0
+    assert (r.objective - fstar) / abs(fstar) <= 1e-3
+
+
+def test_errors(torch_dev):
+    from paper_2406_18356_amd import MsrError, Solver, binding
+
+    pr = _problem(16)
+    s = Solver(16)
+    bad = pr.psf_L.copy()
+    bad[16, 16] = 0.5
+    with pytest.raises(MsrError) as e:
+        s.set_dirty_psf(1, _t(torch_dev, pr.dirty_L), _t(torch_dev, bad))
+    assert e.value.status == binding.ERR_INVALID
+    asym = pr.psf_L.copy()
+    asym[16, 17] += 0.3
+    with pytest.raises(MsrError) as e:
+        s.set_dirty_psf(1, _t(torch_dev, pr.dirty_L), _t(torch_dev, asym))
+    assert e.value.status == binding.ERR_INVALID
+    with pytest.raises(MsrError) as e:
+        s.step1(0.1, 10)
+    assert e.value.status == binding.ERR_STATE
+    s.set_dirty_psf(2, _t(torch_dev, pr.dirty_H), _t(torch_dev, pr.psf_H))
+    with pytest.raises(MsrError) as e:
+        s.step2(0.1, _t(torch_dev, pr.dirty_L), 10)
+    assert e.value.status == binding.ERR_STATE
+    with pytest.raises(MsrError):
+        s.set_filters(10.0, 0.0, 1.0, 1.0)
+    nan = pr.dirty_L.copy()
+    nan[3, 3] = np.nan
+    s.set_dirty_psf(1, _t(torch_dev, nan), _t(torch_dev, pr.psf_L))
+    s.set_lipschitz(1, 1e4)
+    with pytest.raises(MsrError) as e:
+        s.step1(0.1, 10, check_every=5)
+    assert e.value.status == binding.ERR_NUMERIC
+
+
+# ----------------------------------------------------------------- full size
+@pytest.fixture(scope="module")
+def big(torch_dev):
+    pr = synth.make_problem(synth.preset("sky2048"), with_full=False)
+    s = _solver(torch_dev, pr, positivity=True)
+    return pr, s
+
+
+def test_full_size_psf_sampled(torch_dev, big):
+    """2048^2 image, 4096^2 grid: H x at sampled pixels against the defining spatial sum."""
+    pr, s = big
+    n, P = pr.n, pr.P
+    x = np.zeros((n, n))
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, n, (64, 2))
+    x[idx[:, 0], idx[:, 1]] = rng.normal(size=64)
+    x[900:1100, 900:1100] = rng.normal(size=(200, 200))
+    y = s.apply_psf(1, _t(torch_dev, x)).cpu().numpy()
+    c = P // 2
+    xs = x.astype(np.float32).astype(np.float64)
+    qi, qj = np.nonzero(xs)
+    vals = xs[qi, qj]
+    peak = np.max(np.abs(y))
+    for p in rng.integers(0, n, (24, 2)):
+        ref = float(np.sum(pr.psf_L[c + p[0] - qi, c + p[1] - qj] * vals))
+        assert abs(y[p[0], p[1]] - ref) <= OP_TOL * peak
+
+
+def test_full_size_one_step_map(torch_dev, big):
+    """One FISTA step at 2048^2 from a nonzero x0, against the FP64 FFT oracle on the full grid."""
+    from oracle import objectives, fista
+
+    pr, s = big
+    n = pr.n
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    th = 2.5e9
+    s.set_lipschitz(1, th)
+    lam = 0.05 * np.linalg.norm(pr.dirty_L)
+    x0 = (np.abs(np.random.default_rng(2).normal(size=(n, n))) * 1e-3).astype(np.float32)
+    b, _ = s.step1(lam, 1, x0=_t(torch_dev, x0))
+    bo, _ = fista.fista(s1.grad, x0.astype(np.float64), 1 / th, lam, 1, positivity=True)
+    assert rel(b.cpu().numpy(), bo) <= TOL
