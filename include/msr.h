@@ -22,9 +22,14 @@
  * Conventions.
  *   - Every call returns msr_status; no C++ exception crosses the ABI.
  *     msr_last_error() returns a text for the last failed call on a context.
- *   - Images are float32, row-major, contiguous, device pointers, N x N
- *     (PSFs: P x P with the phase centre at (P/2, P/2)).  They stay owned by
- *     the caller; the library keeps no pointer to them after a call returns.
+ *   - Images are row-major, contiguous device arrays of N x N reals (PSFs:
+ *     P x P with the phase centre at (P/2, P/2)), float32 or float64 as the
+ *     context's msr_config.precision says (passed as void*).  They stay owned
+ *     by the caller; the library keeps no pointer to them after a call.
+ *   - precision 32 runs the transforms, the prox and the momentum in float32
+ *     with FP64 reductions (objectives, power iteration, sigma2_hat);
+ *     precision 64 runs everything in float64 (N <= 4096 zero padded,
+ *     N <= 8192 circular).
  *   - All device memory the library uses is one workspace the caller
  *     allocates (size from msr_workspace_bytes) and hands over with
  *     msr_set_workspace; the library itself never allocates device memory.
@@ -65,6 +70,8 @@ typedef struct msr_config {
     uint64_t seed;       /* power-iteration start vector seed (SplitMix64 counter) */
     double prune_tol;    /* spectral columns k_x whose |h_hat| stays below prune_tol * max|h_hat|
                             are treated as zero; 0 keeps every column */
+    int32_t precision;   /* 32: float32 images and arithmetic; 64: float64 */
+    int32_t reserved;    /* must be 0 */
 } msr_config;
 
 typedef struct msr_solve {
@@ -114,7 +121,7 @@ msr_status msr_set_workspace(msr_ctx* ctx, void* dev, size_t bytes);
  * Fails with MSR_ERR_INVALID if PSF[P/2][P/2] differs from 1 by more than
  * 1e-5, or if max|Im h_hat| > 1e-4 max|h_hat| (a PSF that is not point
  * symmetric).  dirty: N x N; psf: P x P.  Invalidates that step's theta. */
-msr_status msr_set_dirty_psf(msr_ctx* ctx, int step, const float* dirty, const float* psf, void* stream);
+msr_status msr_set_dirty_psf(msr_ctx* ctx, int step, const void* dirty, const void* psf, void* stream);
 
 /* The filters of Eqs. 6-10 for step 2: centre ell and half-width delta of the
  * overlap band (grid cells), and the noise variances sigma^2 (of i_H) and
@@ -139,26 +146,26 @@ msr_status msr_set_lipschitz(msr_ctx* ctx, int step, double theta);
  * i_L = beta_K + (i_L~ - H_L beta_K) (Sect. 3.2, one major cycle).  Computes
  * theta by power iteration first if none is cached.  Fills *res (may be
  * NULL).  Blocks until the results are written. */
-msr_status msr_step1_low_res(msr_ctx* ctx, const msr_solve* opt, const float* x0,
-                             float* model_out, float* image_out, msr_result* res, void* stream);
+msr_status msr_step1_low_res(msr_ctx* ctx, const msr_solve* opt, const void* x0,
+                             void* model_out, void* image_out, msr_result* res, void* stream);
 
 /* Step 2: FISTA on Eq. 5 with the constraint image l = low_res (N x N), from
  * x0 (NULL: zeros; any warm start may be passed here).  Requires
  * msr_set_dirty_psf(step 2) and msr_set_filters, else MSR_ERR_STATE. */
-msr_status msr_step2_full_res(msr_ctx* ctx, const msr_solve* opt, const float* low_res, const float* x0,
-                              float* model_out, msr_result* res, void* stream);
+msr_status msr_step2_full_res(msr_ctx* ctx, const msr_solve* opt, const void* low_res, const void* x0,
+                              void* model_out, msr_result* res, void* stream);
 
 /* Exact objective of step s at x: out[0] = F(x), out[1] = data term(s),
  * out[2] = ||x||_1 (FP64 accumulation).  low_res is required for step 2. */
-msr_status msr_objective(msr_ctx* ctx, int step, double lambda, const float* x, const float* low_res,
+msr_status msr_objective(msr_ctx* ctx, int step, double lambda, const void* x, const void* low_res,
                          double out[3], void* stream);
 
 /* Gradient of the smooth part of step s at x (Eq. 11 or Eq. 12), N x N. */
-msr_status msr_gradient(msr_ctx* ctx, int step, const float* x, const float* low_res, float* grad_out,
+msr_status msr_gradient(msr_ctx* ctx, int step, const void* x, const void* low_res, void* grad_out,
                         void* stream);
 
 /* H_s x (N x N in, N x N out): the PSF convolution of step s alone. */
-msr_status msr_apply_psf(msr_ctx* ctx, int step, const float* x, float* out, void* stream);
+msr_status msr_apply_psf(msr_ctx* ctx, int step, const void* x, void* out, void* stream);
 
 /* Copies the cached h_hat of step s to host memory as P x (P/2 + 1) doubles
  * (rfft half plane, row = k_y, column = k_x), pruned columns as zeros, and
@@ -167,7 +174,7 @@ msr_status msr_get_spectrum(msr_ctx* ctx, int step, double* host_out, int* kept,
 
 /* sigma2_hat of Sect. 4.3 on an N x N device image: the mean over all 5 x 5
  * windows inside the image of the window's population variance (FP64). */
-msr_status msr_estimate_sigma2(msr_ctx* ctx, const float* dirty, double* sigma2, void* stream);
+msr_status msr_estimate_sigma2(msr_ctx* ctx, const void* dirty, double* sigma2, void* stream);
 
 /* Default regularisation weight: c * ||i_s~||_2 * 2^(cycle - 1) (Sect. 5 and
  * App. A.2), from the dirty image set for step s. */

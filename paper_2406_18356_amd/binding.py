@@ -1,6 +1,7 @@
 """ctypes binding of libmsr (argument marshalling only).
 
-Names follow the C ABI in ``include/msr.h``.  Tensors must be float32,
+Names follow the C ABI in ``include/msr.h``.  Tensors must be float32 (or
+float64 for a precision-64 solver),
 contiguous and on the context's device; their ``data_ptr()`` and the current
 stream's handle are passed through unchanged.
 """
@@ -32,6 +33,8 @@ class Config(C.Structure):
         ("device", C.c_int32),
         ("seed", C.c_uint64),
         ("prune_tol", C.c_double),
+        ("precision", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -113,22 +116,21 @@ def abi_version() -> int:
     return lib().msr_abi_version()
 
 
-def _cfg(n, pad=2, positivity=False, device=0, seed=0, prune_tol=1e-6) -> Config:
-    return Config(int(n), int(pad), int(bool(positivity)), int(device), int(seed), float(prune_tol))
+def _cfg(n, pad=2, positivity=False, device=0, seed=0, prune_tol=1e-6, precision=32) -> Config:
+    return Config(int(n), int(pad), int(bool(positivity)), int(device), int(seed), float(prune_tol),
+                  int(precision), 0)
 
 
-def workspace_bytes(n, pad=2, positivity=False, seed=0, prune_tol=1e-6) -> int:
-    c = _cfg(n, pad, positivity, 0, seed, prune_tol)
+def workspace_bytes(n, pad=2, positivity=False, seed=0, prune_tol=1e-6, precision=32) -> int:
+    c = _cfg(n, pad, positivity, 0, seed, prune_tol, precision)
     return int(lib().msr_workspace_bytes(C.byref(c)))
 
 
-def _ptr(t) -> Optional[int]:
+def _ptr(t, dtype=None) -> Optional[int]:
     if t is None:
         return None
-    import torch
-
-    if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
-        raise ValueError("tensors must be contiguous float32 on the GPU")
+    if (dtype is not None and t.dtype != dtype) or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"tensors must be contiguous {dtype} on the GPU (got {t.dtype}, device {t.device})")
     return t.data_ptr()
 
 
@@ -150,14 +152,16 @@ class Solver:
     """
 
     def __init__(self, n: int, pad: int = 2, positivity: bool = False, device: int = 0, seed: int = 0,
-                 prune_tol: float = 1e-6):
+                 prune_tol: float = 1e-6, precision: int = 32):
         import torch
 
         self._lib = lib()
         self.n = n
         self.P = pad * n
+        self.precision = precision
+        self.dtype = torch.float32 if precision == 32 else torch.float64
         self.device = torch.device("cuda", device)
-        cfg = _cfg(n, pad, positivity, device, seed, prune_tol)
+        cfg = _cfg(n, pad, positivity, device, seed, prune_tol, precision)
         h = C.c_void_p()
         st = self._lib.msr_init(C.byref(cfg), C.byref(h))
         if st != OK:
@@ -185,11 +189,14 @@ class Solver:
     def _img(self):
         import torch
 
-        return torch.empty((self.n, self.n), dtype=torch.float32, device=self.device)
+        return torch.empty((self.n, self.n), dtype=self.dtype, device=self.device)
+
+    def _p(self, t):
+        return _ptr(t, self.dtype)
 
     # -- setup ------------------------------------------------------------------
     def set_dirty_psf(self, step: int, dirty, psf, stream=None):
-        self._check(self._lib.msr_set_dirty_psf(self._h, step, _ptr(dirty), _ptr(psf), _stream(stream)))
+        self._check(self._lib.msr_set_dirty_psf(self._h, step, self._p(dirty), self._p(psf), _stream(stream)))
 
     def set_filters(self, ell, delta, sigma2, eta2):
         self._check(self._lib.msr_set_filters(self._h, float(ell), float(delta), float(sigma2), float(eta2)))
@@ -209,7 +216,7 @@ class Solver:
         res = Result()
         beta = out if out is not None else self._img()
         img = self._img() if image else None
-        self._check(self._lib.msr_step1_low_res(self._h, C.byref(opt), _ptr(x0), _ptr(beta), _ptr(img),
+        self._check(self._lib.msr_step1_low_res(self._h, C.byref(opt), self._p(x0), self._p(beta), self._p(img),
                                                 C.byref(res), _stream(stream)))
         return (beta, img, res) if image else (beta, res)
 
@@ -217,24 +224,24 @@ class Solver:
         opt = SolveOptions(float(lam), int(iters), int(check_every), float(tol), float(f_ref))
         res = Result()
         beta = out if out is not None else self._img()
-        self._check(self._lib.msr_step2_full_res(self._h, C.byref(opt), _ptr(low_res), _ptr(x0), _ptr(beta),
+        self._check(self._lib.msr_step2_full_res(self._h, C.byref(opt), self._p(low_res), self._p(x0), self._p(beta),
                                                  C.byref(res), _stream(stream)))
         return beta, res
 
     # -- single operators ------------------------------------------------------
     def objective(self, step, lam, x, low_res=None, stream=None):
         out = (C.c_double * 3)()
-        self._check(self._lib.msr_objective(self._h, step, float(lam), _ptr(x), _ptr(low_res), out, _stream(stream)))
+        self._check(self._lib.msr_objective(self._h, step, float(lam), self._p(x), self._p(low_res), out, _stream(stream)))
         return tuple(out)
 
     def gradient(self, step, x, low_res=None, stream=None):
         g = self._img()
-        self._check(self._lib.msr_gradient(self._h, step, _ptr(x), _ptr(low_res), _ptr(g), _stream(stream)))
+        self._check(self._lib.msr_gradient(self._h, step, self._p(x), self._p(low_res), self._p(g), _stream(stream)))
         return g
 
     def apply_psf(self, step, x, stream=None):
         y = self._img()
-        self._check(self._lib.msr_apply_psf(self._h, step, _ptr(x), _ptr(y), _stream(stream)))
+        self._check(self._lib.msr_apply_psf(self._h, step, self._p(x), self._p(y), _stream(stream)))
         return y
 
     def spectrum(self, step, stream=None):
@@ -248,7 +255,7 @@ class Solver:
 
     def estimate_sigma2(self, dirty, stream=None):
         v = C.c_double()
-        self._check(self._lib.msr_estimate_sigma2(self._h, _ptr(dirty), C.byref(v), _stream(stream)))
+        self._check(self._lib.msr_estimate_sigma2(self._h, self._p(dirty), C.byref(v), _stream(stream)))
         return v.value
 
     def default_lambda(self, step, cycle=1, c=0.05, stream=None):

@@ -1,35 +1,68 @@
 // fft_engine.hpp -- register/LDS radix-16 Stockham FFT building blocks for gfx950.
 //
 // A length-L complex FFT is computed cooperatively by TPF = L/E threads, each
-// holding E = min(16, L) elements in registers.  Thread t holds element
-// t + m*TPF in register m on entry and the output bin t + m*TPF on exit, so a
-// forward transform followed by a pointwise multiply and an inverse transform
-// needs no reordering: the inverse's first stage reads exactly the registers
-// the forward's last stage wrote.  Stages are Stockham auto-sort passes of
-// radix R = min(E, remaining length); between stages the data goes through
-// LDS once (write, barrier, read, barrier).  Twiddles come from one table of
-// exp(-2 pi i k / Pt), k < Pt, computed in double precision on the host and
-// rounded to float (Pt = the logical transform length, L or 2L).
+// holding E elements in registers (E = 16 in single precision, 8 in double).
+// Thread t holds element t + m*TPF in register m on entry and the output bin
+// t + m*TPF on exit, so a forward transform followed by a pointwise multiply
+// and an inverse transform needs no reordering: the inverse's first stage
+// reads exactly the registers the forward's last stage wrote.  Stages are
+// Stockham auto-sort passes of radix R = min(E, remaining length); between
+// stages the data goes through LDS once (write, barrier, read, barrier).
+// Twiddles come from one table of exp(-2 pi i k / Pt), k < Pt, computed in
+// double precision on the host and rounded to the working precision
+// (Pt = the logical transform length, L or 2L).
 //
 // Several independent arrays ("halves") can be transformed together so they
 // share the barriers; each has its own LDS view.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace msr {
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+template <typename R>
+struct cplx_of;
+template <>
+struct cplx_of<float> {
+    using type = float2;
+};
+template <>
+struct cplx_of<double> {
+    using type = double2;
+};
+template <typename R>
+using cplx = typename cplx_of<R>::type;
+
+template <typename C>
+using real_of = std::conditional_t<std::is_same_v<C, float2>, float, double>;
+
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
+
+template <typename C>
+__device__ __forceinline__ C mk(real_of<C> x, real_of<C> y) {
+    C r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C>
+__device__ __forceinline__ C cscale(C a, real_of<C> s) { return mk<C>(a.x * s, a.y * s); }
 // a * w
-__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
-    return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C w) {
+    return mk<C>(fmaR(a.x, w.x, -(a.y * w.y)), fmaR(a.x, w.y, a.y * w.x));
 }
 // a * conj(w)
-__device__ __forceinline__ float2 cmulc(float2 a, float2 w) {
-    return make_float2(fmaf(a.x, w.x, a.y * w.y), fmaf(a.y, w.x, -(a.x * w.y)));
+template <typename C>
+__device__ __forceinline__ C cmulc(C a, C w) {
+    return mk<C>(fmaR(a.x, w.x, a.y * w.y), fmaR(a.y, w.x, -(a.x * w.y)));
 }
-__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
 template <int R>
 __host__ __device__ constexpr int bit_reverse(int i) {
@@ -42,14 +75,15 @@ __host__ __device__ constexpr int bit_reverse(int i) {
 }
 
 // Multiply by w16^e (forward: exp(-2 pi i e/16); inverse: the conjugate), e in [0, 8).
-template <bool INV>
-__device__ __forceinline__ float2 rot16(float2 b, int e) {
-    constexpr float C1 = 0.92387953251128674f;  // cos(pi/8)
-    constexpr float S1 = 0.38268343236508978f;  // sin(pi/8)
-    constexpr float H = 0.70710678118654752f;   // sqrt(1/2)
+template <bool INV, typename C>
+__device__ __forceinline__ C rot16(C b, int e) {
+    using R = real_of<C>;
+    constexpr R C1 = (R)0.92387953251128675613;  // cos(pi/8)
+    constexpr R S1 = (R)0.38268343236508977173;  // sin(pi/8)
+    constexpr R H = (R)0.70710678118654752440;   // sqrt(1/2)
     if (e == 0) return b;
-    if (e == 4) return INV ? make_float2(-b.y, b.x) : make_float2(b.y, -b.x);
-    float c, s;
+    if (e == 4) return INV ? mk<C>(-b.y, b.x) : mk<C>(b.y, -b.x);
+    R c, s;
     switch (e) {
         case 1: c = C1; s = S1; break;
         case 2: c = H; s = H; break;
@@ -59,86 +93,93 @@ __device__ __forceinline__ float2 rot16(float2 b, int e) {
         default: c = -C1; s = S1; break;  // 7
     }
     // forward multiplies by (c, -s), inverse by (c, s)
-    if (INV) return make_float2(fmaf(b.x, c, -(b.y * s)), fmaf(b.x, s, b.y * c));
-    return make_float2(fmaf(b.x, c, b.y * s), fmaf(b.y, c, -(b.x * s)));
+    if (INV) return mk<C>(fmaR(b.x, c, -(b.y * s)), fmaR(b.x, s, b.y * c));
+    return mk<C>(fmaR(b.x, c, b.y * s), fmaR(b.y, c, -(b.x * s)));
 }
 
-// In-register DFT of size R (2, 4, 8 or 16), natural order in and out.
-template <int R, bool INV>
-__device__ __forceinline__ void dft(float2 (&x)[R]) {
-    float2 y[R];
+// In-register DFT of size RD (2, 4, 8 or 16), natural order in and out.
+template <int RD, bool INV, typename C>
+__device__ __forceinline__ void dft(C (&x)[RD]) {
+    C y[RD];
 #pragma unroll
-    for (int i = 0; i < R; ++i) y[i] = x[bit_reverse<R>(i)];
+    for (int i = 0; i < RD; ++i) y[i] = x[bit_reverse<RD>(i)];
 #pragma unroll
-    for (int len = 2; len <= R; len <<= 1) {
+    for (int len = 2; len <= RD; len <<= 1) {
 #pragma unroll
-        for (int i = 0; i < R; i += len) {
+        for (int i = 0; i < RD; i += len) {
 #pragma unroll
             for (int k = 0; k < len / 2; ++k) {
-                const float2 a = y[i + k];
-                const float2 b = rot16<INV>(y[i + k + len / 2], k * (16 / len));
+                const C a = y[i + k];
+                const C b = rot16<INV>(y[i + k + len / 2], k * (16 / len));
                 y[i + k] = cadd(a, b);
                 y[i + k + len / 2] = csub(a, b);
             }
         }
     }
 #pragma unroll
-    for (int i = 0; i < R; ++i) x[i] = y[i];
+    for (int i = 0; i < RD; ++i) x[i] = y[i];
 }
 
 // LDS view of one transform's data: element p lives at base[(p + p/16) * S + c]
 // (one pad slot every 16 elements breaks the power-of-two strides of the
 // Stockham writes; S interleaves several columns).
-template <int S>
+template <int S, typename C>
 struct LdsView {
-    float2* base;
+    C* base;
     int c;
-    __device__ __forceinline__ float2& operator[](int p) const { return base[(p + (p >> 4)) * S + c]; }
+    __device__ __forceinline__ C& operator[](int p) const { return base[(p + (p >> 4)) * S + c]; }
 };
 
-template <int L>
-__host__ __device__ constexpr int padded_len() { return L + L / 16; }
+__host__ __device__ constexpr int padded_len(int L) { return L + L / 16; }
 
-template <int L>
-__host__ __device__ constexpr int elems_per_thread() { return L >= 16 ? 16 : L; }
+// Elements per thread: 16 complex in single precision, 8 in double.
+template <int L, typename C>
+__host__ __device__ constexpr int elems_per_thread() {
+    constexpr int EMAX = std::is_same_v<C, float2> ? 16 : 8;
+    return L >= EMAX ? EMAX : L;
+}
+
+// The register array of NH transforms held by one thread.
+template <int L, int NH, typename C>
+using RegArr = C[NH][elems_per_thread<L, C>()];
 
 // One Stockham stage on NH arrays at once.  Butterfly b of thread t owns the
-// register slots b + r*NB (r < R), so results go back into the same slots (last
-// stage) or straight to LDS (other stages): no second register copy.
-template <int L, int NS, bool INV, int TWS, int NH, int S>
-__device__ __forceinline__ void fft_stage(float2 (&v)[NH][elems_per_thread<L>()], const LdsView<S> (&lds)[NH], int t,
-                                          const float2* __restrict__ tw) {
-    constexpr int E = elems_per_thread<L>();
+// register slots b + r*NB (r < RD), so results go back into the same slots
+// (last stage) or straight to LDS (other stages): no second register copy.
+template <int L, int NS, bool INV, int TWS, int NH, int S, typename C>
+__device__ __forceinline__ void fft_stage(RegArr<L, NH, C>& v, const LdsView<S, C> (&lds)[NH], int t,
+                                          const C* __restrict__ tw) {
+    constexpr int E = elems_per_thread<L, C>();
     constexpr int TPF = L / E;
-    constexpr int R = (L / NS) >= E ? E : (L / NS);
-    constexpr int NB = E / R;
-    constexpr bool LAST = (NS * R == L);
+    constexpr int RD = (L / NS) >= E ? E : (L / NS);
+    constexpr int NB = E / RD;
+    constexpr bool LAST = (NS * RD == L);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + b * TPF;
         const int jm = j & (NS - 1);
-        float2 w[R];
+        C w[RD];
         if constexpr (NS > 1) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) w[r] = tw[(jm * r * (L / (NS * R))) * TWS];
+            for (int r = 1; r < RD; ++r) w[r] = tw[(jm * r * (L / (NS * RD))) * TWS];
         }
-        const int idxD = (j - jm) * R + jm;
+        const int idxD = (j - jm) * RD + jm;
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
-            float2 x[R];
+            C x[RD];
 #pragma unroll
-            for (int r = 0; r < R; ++r) x[r] = v[h][b + r * NB];
+            for (int r = 0; r < RD; ++r) x[r] = v[h][b + r * NB];
             if constexpr (NS > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) x[r] = INV ? cmulc(x[r], w[r]) : cmul(x[r], w[r]);
+                for (int r = 1; r < RD; ++r) x[r] = INV ? cmulc(x[r], w[r]) : cmul(x[r], w[r]);
             }
-            dft<R, INV>(x);
+            dft<RD, INV>(x);
             if constexpr (LAST) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[h][b + r * NB] = x[r];
+                for (int r = 0; r < RD; ++r) v[h][b + r * NB] = x[r];
             } else {
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[h][idxD + r * NS] = x[r];
+                for (int r = 0; r < RD; ++r) lds[h][idxD + r * NS] = x[r];
             }
         }
     }
@@ -152,22 +193,22 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[NH][elems_per_thread<L>()]
     }
 }
 
-template <int L, int NS, bool INV, int TWS, int NH, int S>
-__device__ __forceinline__ void fft_from(float2 (&v)[NH][elems_per_thread<L>()], const LdsView<S> (&lds)[NH], int t,
-                                         const float2* __restrict__ tw) {
-    constexpr int E = elems_per_thread<L>();
-    constexpr int R = (L / NS) >= E ? E : (L / NS);
-    fft_stage<L, NS, INV, TWS, NH, S>(v, lds, t, tw);
-    if constexpr (NS * R < L) fft_from<L, NS * R, INV, TWS, NH, S>(v, lds, t, tw);
+template <int L, int NS, bool INV, int TWS, int NH, int S, typename C>
+__device__ __forceinline__ void fft_from(RegArr<L, NH, C>& v, const LdsView<S, C> (&lds)[NH], int t,
+                                         const C* __restrict__ tw) {
+    constexpr int E = elems_per_thread<L, C>();
+    constexpr int RD = (L / NS) >= E ? E : (L / NS);
+    fft_stage<L, NS, INV, TWS, NH, S, C>(v, lds, t, tw);
+    if constexpr (NS * RD < L) fft_from<L, NS * RD, INV, TWS, NH, S, C>(v, lds, t, tw);
 }
 
 // Full transform of NH arrays (unnormalised; INV uses conjugate twiddles).
 // tw: the table of exp(-2 pi i k / (TWS * L)).  The caller must have a barrier
 // between any earlier use of the LDS views and this call.
-template <int L, bool INV, int TWS, int NH, int S>
-__device__ __forceinline__ void fft(float2 (&v)[NH][elems_per_thread<L>()], const LdsView<S> (&lds)[NH], int t,
-                                    const float2* __restrict__ tw) {
-    fft_from<L, 1, INV, TWS, NH, S>(v, lds, t, tw);
+template <int L, bool INV, int TWS, int NH, int S, typename C>
+__device__ __forceinline__ void fft(RegArr<L, NH, C>& v, const LdsView<S, C> (&lds)[NH], int t,
+                                    const C* __restrict__ tw) {
+    fft_from<L, 1, INV, TWS, NH, S, C>(v, lds, t, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,7 +221,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sums NQ doubles over a block of NT threads; thread 0 gets the totals in
-// out[].  `scratch` must hold NQ * max(NT / 64, NT < 64 ? NT : 1) doubles.
+// out[].  `scratch` must hold NQ * (NT >= 64 ? NT / 64 : NT) doubles.
 template <int NQ, int NT>
 __device__ __forceinline__ void block_sum(double (&v)[NQ], double* scratch, double (&out)[NQ]) {
     if constexpr (NT >= 64) {

@@ -34,7 +34,9 @@
 using namespace msr;
 
 namespace msr {
-#define MSR_DECL(Lv) const Ops* ops_len_##Lv(bool padded);
+#define MSR_DECL(Lv)                                       \
+    const Ops<float>* ops_len_f32_##Lv(bool padded);       \
+    const Ops<double>* ops_len_f64_##Lv(bool padded);
 MSR_DECL(8)
 MSR_DECL(16)
 MSR_DECL(32)
@@ -49,23 +51,25 @@ MSR_DECL(8192)
 MSR_DECL(16384)
 #undef MSR_DECL
 
-const Ops* ops_for(int L, bool padded) {
-    switch (L) {
-        case 8: return ops_len_8(padded);
-        case 16: return ops_len_16(padded);
-        case 32: return ops_len_32(padded);
-        case 64: return ops_len_64(padded);
-        case 128: return ops_len_128(padded);
-        case 256: return ops_len_256(padded);
-        case 512: return ops_len_512(padded);
-        case 1024: return ops_len_1024(padded);
-        case 2048: return ops_len_2048(padded);
-        case 4096: return ops_len_4096(padded);
-        case 8192: return ops_len_8192(padded);
-        case 16384: return ops_len_16384(padded);
-        default: return nullptr;
+#define MSR_CASES(pfx)                                   \
+    switch (L) {                                         \
+        case 8: return pfx##8(padded);                   \
+        case 16: return pfx##16(padded);                 \
+        case 32: return pfx##32(padded);                 \
+        case 64: return pfx##64(padded);                 \
+        case 128: return pfx##128(padded);               \
+        case 256: return pfx##256(padded);               \
+        case 512: return pfx##512(padded);               \
+        case 1024: return pfx##1024(padded);             \
+        case 2048: return pfx##2048(padded);             \
+        case 4096: return pfx##4096(padded);             \
+        case 8192: return pfx##8192(padded);             \
+        case 16384: return pfx##16384(padded);           \
+        default: return nullptr;                         \
     }
-}
+const Ops<float>* ops_for_f32(int L, bool padded) { MSR_CASES(ops_len_f32_) }
+const Ops<double>* ops_for_f64(int L, bool padded) { MSR_CASES(ops_len_f64_) }
+#undef MSR_CASES
 }  // namespace msr
 
 namespace {
@@ -80,15 +84,27 @@ struct Layout {
 };
 
 struct Shapes {
-    int N, P, logN, T, Cfull, Cpad, Tpsf, Cpad_psf;
+    int N, P, T, Cfull, Cpad, Tpsf, Cpad_psf;
     bool padded;
+    int prec;            // 32 or 64
+    size_t rs, cs;       // bytes of a real / complex element
     size_t spec_elems;   // N * Cpad complex
-    size_t hh_elems;     // P * Cpad floats
+    size_t hh_elems;     // P * Cpad reals
     size_t img_elems;    // N * N
     size_t partial_cnt;  // doubles
 };
 
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+template <typename R>
+bool tables(int N, int P, bool padded, int& T, int& Tpsf) {
+    const Ops<R>* o = ops_for<R>(N, padded);
+    const Ops<R>* op = ops_for<R>(P, false);
+    if (!o || !op || !o->row_update_fwd || !op->col_forward) return false;
+    T = o->T;
+    Tpsf = op->T;
+    return true;
+}
 
 bool make_shapes(const msr_config* c, Shapes& s, std::string* why) {
     if (!c) {
@@ -103,21 +119,24 @@ bool make_shapes(const msr_config* c, Shapes& s, std::string* why) {
         if (why) *why = "pad must be 1 (circular) or 2 (zero padded)";
         return false;
     }
+    if (c->precision != 32 && c->precision != 64) {
+        if (why) *why = "precision must be 32 or 64";
+        return false;
+    }
     s.N = c->n;
     s.padded = c->pad == 2;
     s.P = c->pad * c->n;
-    s.logN = 0;
-    while ((1 << s.logN) < s.N) ++s.logN;
-    const Ops* o = ops_for(s.N, s.padded);
-    const Ops* op = ops_for(s.P, false);
-    if (!o || !op || !o->row_update_fwd || !op->col_forward) {
-        if (why) *why = "no kernels built for this size";
+    s.prec = c->precision;
+    const bool ok = s.prec == 32 ? tables<float>(s.N, s.P, s.padded, s.T, s.Tpsf)
+                                 : tables<double>(s.N, s.P, s.padded, s.T, s.Tpsf);
+    if (!ok) {
+        if (why) *why = "no kernels built for this size and precision";
         return false;
     }
-    s.T = o->T;
+    s.rs = s.prec == 32 ? 4 : 8;
+    s.cs = 2 * s.rs;
     s.Cfull = s.P / 2 + 1;
     s.Cpad = (int)align_up(s.Cfull, s.T);
-    s.Tpsf = op->T;
     s.Cpad_psf = (int)align_up(s.Cfull, s.Tpsf);
     s.spec_elems = (size_t)s.N * s.Cpad;
     s.hh_elems = (size_t)s.P * s.Cpad;
@@ -134,24 +153,24 @@ Layout make_layout(const Shapes& s) {
         off = align_up(off + bytes, kAlign);
         return o;
     };
-    l.tw = take(sizeof(float2) * (size_t)s.P);
-    l.SA = take(sizeof(float2) * s.spec_elems);
+    l.tw = take(s.cs * (size_t)s.P);
+    l.SA = take(s.cs * s.spec_elems);
     // SB and SC are contiguous: together they hold the P-row PSF spectrum.
-    const size_t sbc = std::max(2 * sizeof(float2) * s.spec_elems, sizeof(float2) * (size_t)s.P * s.Cpad_psf);
+    const size_t sbc = std::max(align_up(s.cs * s.spec_elems, kAlign) * 2, s.cs * (size_t)s.P * s.Cpad_psf);
     l.SB = take(sbc);
-    l.SC = l.SB + align_up(sizeof(float2) * s.spec_elems, kAlign);
-    l.SL = take(sizeof(float2) * s.spec_elems);
-    l.hh1 = take(sizeof(float) * s.hh_elems);
-    l.hh2 = take(sizeof(float) * s.hh_elems);
-    l.d1 = take(sizeof(float) * s.img_elems);
-    l.d2 = take(sizeof(float) * s.img_elems);
-    l.b0 = take(sizeof(float) * s.img_elems);
-    l.b1 = take(sizeof(float) * s.img_elems);
-    l.t0 = take(sizeof(float) * s.img_elems);
-    l.t1 = take(sizeof(float) * s.img_elems);
+    l.SC = l.SB + align_up(s.cs * s.spec_elems, kAlign);
+    l.SL = take(s.cs * s.spec_elems);
+    l.hh1 = take(s.rs * s.hh_elems);
+    l.hh2 = take(s.rs * s.hh_elems);
+    l.d1 = take(s.rs * s.img_elems);
+    l.d2 = take(s.rs * s.img_elems);
+    l.b0 = take(s.rs * s.img_elems);
+    l.b1 = take(s.rs * s.img_elems);
+    l.t0 = take(s.rs * s.img_elems);
+    l.t1 = take(s.rs * s.img_elems);
     l.partials = take(sizeof(double) * s.partial_cnt);
     l.scal = take(sizeof(double) * 64);
-    l.colmax = take(sizeof(float) * (size_t)s.Cfull);
+    l.colmax = take(sizeof(double) * (size_t)s.Cfull);
     l.total = off;
     return l;
 }
@@ -162,19 +181,8 @@ struct msr_ctx {
     msr_config cfg{};
     Shapes sh{};
     Layout lay{};
-    const Ops* op = nullptr;   // N-length passes (padded or circular)
-    const Ops* opp = nullptr;  // P-length unpadded (PSF spectrum)
     char* ws = nullptr;
     size_t ws_bytes = 0;
-    // device views
-    float2 *tw = nullptr, *SA = nullptr, *SB = nullptr, *SC = nullptr, *SL = nullptr;
-    float* hh[2] = {nullptr, nullptr};
-    float* dirty[2] = {nullptr, nullptr};
-    float* beta[2] = {nullptr, nullptr};
-    float* tmp[2] = {nullptr, nullptr};
-    double* partials = nullptr;
-    double* scal = nullptr;
-    float* colmax = nullptr;
     // state
     int K[2] = {0, 0};  // kept columns per PSF
     bool have_psf[2] = {false, false};
@@ -182,7 +190,6 @@ struct msr_ctx {
     bool have_theta[2] = {false, false};
     double theta[2] = {0, 0};
     double ell = 0, delta = 0, sigma2 = 0, eta2 = 0;
-    FilterCoef fc{};
     int KL = 0;  // columns with g_L != 0
     std::string err;
 };
@@ -201,223 +208,534 @@ msr_status fail(msr_ctx* c, msr_status s, const char* fmt, ...) {
     return s;
 }
 
-#define HIPCHK(ctx, expr)                                                                          \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
+#define HIPCHK(ctx, expr)                                                                            \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
         if (e_ != hipSuccess) return fail(ctx, MSR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-#define LAUNCHCHK(ctx)                                                                              \
-    do {                                                                                            \
-        hipError_t e_ = hipGetLastError();                                                          \
+#define LAUNCHCHK(ctx)                                                                                   \
+    do {                                                                                                 \
+        hipError_t e_ = hipGetLastError();                                                               \
         if (e_ != hipSuccess) return fail(ctx, MSR_ERR_HIP, "kernel launch: %s", hipGetErrorString(e_)); \
     } while (0)
 
+#define TRY(expr)                               \
+    do {                                        \
+        msr_status st_ = (expr);                \
+        if (st_ != MSR_OK) return st_;          \
+    } while (0)
+
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline unsigned blocks_for(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
 
-inline RowArgs row_args(msr_ctx* c, const float2* in, int kin, const float2* in2, int kin2, float2* out, int kout) {
-    RowArgs a{};
-    a.spec_in = in;
-    a.spec_in2 = in2;
-    a.spec_out = out;
-    a.tw = c->tw;
-    a.partials = c->partials;
-    a.NR = c->sh.N;
-    a.K_in = kin;
-    a.K_in2 = in2 ? kin2 : 0;
-    a.K_out = kout;
-    return a;
-}
+// All typed work of one context, in precision R.
+template <typename R>
+struct Impl {
+    using C = cplx<R>;
+    msr_ctx* c;
+    const Ops<R>* op;   // N-length passes (padded or circular)
+    const Ops<R>* opp;  // P-length unpadded (PSF spectrum)
 
-inline ColArgs col_args(msr_ctx* c, const float2* in, const float2* in2, float2* out, int K) {
-    ColArgs a{};
-    a.spec_in = in;
-    a.spec_in2 = in2;
-    a.spec_out = out;
-    a.tw = c->tw;
-    a.partials = c->partials;
-    a.NR = c->sh.N;
-    a.K = K;
-    return a;
-}
+    explicit Impl(msr_ctx* ctx)
+        : c(ctx), op(ops_for<R>(ctx->sh.N, ctx->sh.padded)), opp(ops_for<R>(ctx->sh.P, false)) {}
 
-inline int row_grid(msr_ctx* c) { return c->sh.N / c->op->row_rows; }
-inline int col_grid(msr_ctx* c, int K) { return (K + c->sh.T - 1) / c->sh.T; }
+    template <typename X>
+    X* at(size_t off) const { return reinterpret_cast<X*>(c->ws + off); }
+    C* tw() const { return at<C>(c->lay.tw); }
+    C* SA() const { return at<C>(c->lay.SA); }
+    C* SB() const { return at<C>(c->lay.SB); }
+    C* SC() const { return at<C>(c->lay.SC); }
+    C* SL() const { return at<C>(c->lay.SL); }
+    R* hh(int step) const { return at<R>(step == 1 ? c->lay.hh1 : c->lay.hh2); }
+    R* dirty(int step) const { return at<R>(step == 1 ? c->lay.d1 : c->lay.d2); }
+    R* beta(int k) const { return at<R>((k & 1) ? c->lay.b1 : c->lay.b0); }
+    R* tmp(int i) const { return at<R>(i ? c->lay.t1 : c->lay.t0); }
+    double* partials() const { return at<double>(c->lay.partials); }
+    double* scal() const { return at<double>(c->lay.scal); }
+    double* colmax() const { return at<double>(c->lay.colmax); }
+    int N() const { return c->sh.N; }
+    int P() const { return c->sh.P; }
 
-// Sum `nq` quantities over `nblocks` partial rows into scal[off..]; returns them to host if `host`.
-msr_status reduce(msr_ctx* c, int nblocks, int nq, int off, double* host, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_sums, dim3(1), dim3(256), 0, s, c->partials, nblocks, nq, c->scal + off);
-    LAUNCHCHK(c);
-    if (host) {
-        HIPCHK(c, hipMemcpyAsync(host, c->scal + off, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
+    FilterCoef<R> filters() const {
+        FilterCoef<R> f{};
+        f.ell = (R)c->ell;
+        f.delta = (R)c->delta;
+        f.inv_sigma2 = (R)(1.0 / c->sigma2);
+        f.inv_eta2 = (R)(1.0 / c->eta2);
+        f.sigma2 = (R)c->sigma2;
+        f.eta2 = (R)c->eta2;
+        f.half_pi_over_delta = (R)(M_PI / (2.0 * c->delta));
+        f.P = c->sh.P;
+        return f;
     }
-    return MSR_OK;
-}
+    R inv_p2() const { return (R)(1.0 / ((double)P() * (double)P())); }
 
-msr_status image_reduce(msr_ctx* c, const float* x, const float* y, int mode, double* host, hipStream_t s) {
-    const size_t n = c->sh.img_elems;
-    int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
-    hipLaunchKernelGGL(image_sums, dim3(blocks), dim3(256), 0, s, x, y, n, mode, c->partials);
-    LAUNCHCHK(c);
-    return reduce(c, blocks, 1, 8, host, s);
-}
-
-bool ready(msr_ctx* c) { return c && c->ws; }
-
-int KA(msr_ctx* c, int step) { return step == 1 ? c->K[0] : std::max(c->K[1], c->KL); }
-
-// image -> SA-like spectrum
-msr_status fwd_image(msr_ctx* c, const float* img, float scale, float2* out, int kout, hipStream_t s) {
-    EpiLoad e{img, c->sh.N, scale};
-    c->op->row_load_fwd(row_args(c, nullptr, 0, nullptr, 0, out, kout), e, s);
-    LAUNCHCHK(c);
-    return MSR_OK;
-}
-
-msr_status col_psf(msr_ctx* c, int step, const float2* in, float2* out, hipStream_t s) {
-    ModePsf m{c->hh[step - 1], c->sh.P, c->sh.T};
-    c->op->col_psf(col_args(c, in, nullptr, out, c->K[step - 1]), m, s);
-    LAUNCHCHK(c);
-    return MSR_OK;
-}
-
-msr_status col_filth(msr_ctx* c, const float2* in, float2* out, hipStream_t s) {
-    ModeFilterH m{c->fc, (float)(1.0 / ((double)c->sh.P * c->sh.P))};
-    c->op->col_filth(col_args(c, in, nullptr, out, c->sh.Cfull), m, s);
-    LAUNCHCHK(c);
-    return MSR_OK;
-}
-
-msr_status col_filtl(msr_ctx* c, const float2* in, const float2* in2, float2* out, hipStream_t s) {
-    ModeFilterL m{c->fc, (float)(1.0 / ((double)c->sh.P * c->sh.P))};
-    c->op->col_filtl(col_args(c, in, in2, out, c->KL), m, s);
-    LAUNCHCHK(c);
-    return MSR_OK;
-}
-
-// The gradient chain of step s applied to the spectrum in SA (alpha); leaves the
-// half-gradient spectrum in SB (+ SC for k_x < K_L in step 2).  `y` is the data
-// term's image (null for the normal operator alone); `l` spectrum SL is used in
-// step 2 when `use_l`.
-msr_status grad_chain(msr_ctx* c, int step, const float* y, bool use_l, hipStream_t s) {
-    msr_status st;
-    const int Ks = c->K[step - 1];
-    if ((st = col_psf(c, step, c->SA, c->SB, s)) != MSR_OK) return st;
-    EpiResid er{y, nullptr, c->sh.N};
-    const int kr = step == 1 ? Ks : c->sh.Cfull;
-    c->op->row_resid_fwd(row_args(c, c->SB, Ks, nullptr, 0, c->SC, kr), er, s);
-    LAUNCHCHK(c);
-    if (step == 1) return col_psf(c, 1, c->SC, c->SB, s);
-    if ((st = col_filth(c, c->SC, c->SB, s)) != MSR_OK) return st;
-    EpiResid rp{nullptr, nullptr, c->sh.N};
-    c->op->row_resid_fwd(row_args(c, c->SB, c->sh.Cfull, nullptr, 0, c->SC, Ks), rp, s);
-    LAUNCHCHK(c);
-    if ((st = col_psf(c, 2, c->SC, c->SB, s)) != MSR_OK) return st;
-    return col_filtl(c, c->SA, use_l ? c->SL : nullptr, c->SC, s);
-}
-
-double momentum(int k) { return k >= 1 ? (k - 1.0) / (k + 2.0) : 0.0; }
-
-// One FISTA iteration k (1-based) of step s.
-msr_status iterate(msr_ctx* c, int step, int k, double mu, double lambda, hipStream_t s) {
-    msr_status st = grad_chain(c, step, c->dirty[step - 1], true, s);
-    if (st != MSR_OK) return st;
-    EpiUpdate u{};
-    u.b1 = c->beta[(k - 1) & 1];
-    u.b2 = c->beta[k & 1];
-    u.ld = c->sh.N;
-    u.two_mu = (float)(2.0 * mu);
-    u.thr = (float)(mu * lambda);
-    u.t_prev = (float)momentum(k - 1);
-    u.t_cur = (float)momentum(k);
-    u.positivity = c->cfg.positivity;
-    const int Ks = c->K[step - 1];
-    RowArgs a = step == 1 ? row_args(c, c->SB, Ks, nullptr, 0, c->SA, KA(c, 1))
-                          : row_args(c, c->SB, Ks, c->SC, c->KL, c->SA, KA(c, 2));
-    c->op->row_update_fwd(a, u, s);
-    LAUNCHCHK(c);
-    return MSR_OK;
-}
-
-// Exact objective of step s at image x (device), FP64 sums.  out: F, data, l1.
-// Uses SB, SC (and SL for step 2) as scratch; SA is preserved.
-msr_status objective_at(msr_ctx* c, int step, double lambda, const float* x, double out[3], hipStream_t s) {
-    msr_status st;
-    double data = 0.0;
-    if (step == 1) {
-        if ((st = fwd_image(c, x, 1.f, c->SB, c->K[0], s)) != MSR_OK) return st;
-        if ((st = col_psf(c, 1, c->SB, c->SC, s)) != MSR_OK) return st;
-        EpiResid er{c->dirty[0], nullptr, c->sh.N};
-        c->op->row_resid(row_args(c, c->SC, c->K[0], nullptr, 0, nullptr, 0), er, s);
-        LAUNCHCHK(c);
-        if ((st = reduce(c, row_grid(c), 1, 0, &data, s)) != MSR_OK) return st;
-    } else {
-        const double ip2 = 1.0 / ((double)c->sh.P * c->sh.P);
-        double dh = 0.0, dl = 0.0;
-        if ((st = fwd_image(c, x, 1.f, c->SB, KA(c, 2), s)) != MSR_OK) return st;
-        if ((st = col_psf(c, 2, c->SB, c->SC, s)) != MSR_OK) return st;
-        EpiResid er{c->dirty[1], nullptr, c->sh.N};
-        c->op->row_resid_fwd(row_args(c, c->SC, c->K[1], nullptr, 0, c->SC, c->sh.Cfull), er, s);
-        LAUNCHCHK(c);
-        if ((st = col_filth(c, c->SC, c->SC, s)) != MSR_OK) return st;
-        if ((st = reduce(c, col_grid(c, c->sh.Cfull), 1, 0, &dh, s)) != MSR_OK) return st;
-        if ((st = col_filtl(c, c->SB, c->SL, c->SC, s)) != MSR_OK) return st;
-        if ((st = reduce(c, col_grid(c, c->KL), 1, 0, &dl, s)) != MSR_OK) return st;
-        data = (dh + dl) * ip2;
+    RowArgs<R> row_args(const C* in, int kin, const C* in2, int kin2, C* out, int kout, bool reduce = false) const {
+        RowArgs<R> a{};
+        a.spec_in = in;
+        a.spec_in2 = in2;
+        a.spec_out = out;
+        a.tw = tw();
+        a.partials = partials();
+        a.NR = N();
+        a.K_in = kin;
+        a.K_in2 = in2 ? kin2 : 0;
+        a.K_out = kout;
+        a.reduce = reduce ? 1 : 0;
+        return a;
     }
-    double l1 = 0.0;
-    if ((st = image_reduce(c, x, nullptr, 0, &l1, s)) != MSR_OK) return st;
-    out[0] = data + lambda * l1;
-    out[1] = data;
-    out[2] = l1;
-    return MSR_OK;
-}
+    ColArgs<R> col_args(const C* in, const C* in2, C* out, int K, bool reduce = false) const {
+        ColArgs<R> a{};
+        a.spec_in = in;
+        a.spec_in2 = in2;
+        a.spec_out = out;
+        a.tw = tw();
+        a.partials = partials();
+        a.NR = N();
+        a.K = K;
+        a.reduce = reduce ? 1 : 0;
+        return a;
+    }
+    int row_grid() const { return N() / op->row_rows; }
+    int col_grid(int K) const { return (K + c->sh.T - 1) / c->sh.T; }
+    int KA(int step) const { return step == 1 ? c->K[0] : std::max(c->K[1], c->KL); }
 
-msr_status set_low_res(msr_ctx* c, const float* low_res, hipStream_t s) {
-    return fwd_image(c, low_res, 1.f, c->SL, c->KL, s);
-}
-
-msr_status power_iteration(msr_ctx* c, int step, int max_iter, double rtol, double* theta_out, int* iters_out,
-                           hipStream_t s) {
-    msr_status st;
-    const size_t n = c->sh.img_elems;
-    float* v = c->tmp[0];
-    float* w = c->tmp[1];
-    hipLaunchKernelGGL(start_vector, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, (unsigned long long)c->cfg.seed, n);
-    LAUNCHCHK(c);
-    double nv2 = 0.0;
-    if ((st = image_reduce(c, v, nullptr, 1, &nv2, s)) != MSR_OK) return st;
-    if (!(nv2 > 0)) return fail(c, MSR_ERR_NUMERIC, "zero start vector");
-    double scale = 1.0 / std::sqrt(nv2);
-    double theta = 0.0, prev = -1.0;
-    int j = 0;
-    for (j = 1; j <= max_iter; ++j) {
-        if ((st = fwd_image(c, v, (float)scale, c->SA, KA(c, step), s)) != MSR_OK) return st;
-        if ((st = grad_chain(c, step, nullptr, false, s)) != MSR_OK) return st;
-        EpiPower ep{v, w, c->sh.N, (float)scale};
-        RowArgs a = step == 1 ? row_args(c, c->SB, c->K[0], nullptr, 0, nullptr, 0)
-                              : row_args(c, c->SB, c->K[1], c->SC, c->KL, nullptr, 0);
-        c->op->row_power(a, ep, s);
+    // Sum `nq` quantities over `nblocks` partial rows into scal[off..]; copies them to host.
+    msr_status reduce(int nblocks, int nq, int off, double* host, hipStream_t s) {
+        hipLaunchKernelGGL(finalize_sums, dim3(1), dim3(256), 0, s, partials(), nblocks, nq, scal() + off);
         LAUNCHCHK(c);
-        double sums[2];
-        if ((st = reduce(c, row_grid(c), 2, 0, sums, s)) != MSR_OK) return st;
-        // v has unit norm: theta = 2 <v, A v>
-        theta = 2.0 * sums[1];
-        if (!std::isfinite(theta) || !(sums[0] > 0)) {
+        if (host) {
+            HIPCHK(c, hipMemcpyAsync(host, scal() + off, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+        }
+        return MSR_OK;
+    }
+
+    msr_status image_reduce(const R* x, const R* y, int mode, double* host, hipStream_t s) {
+        const size_t n = c->sh.img_elems;
+        const int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
+        hipLaunchKernelGGL(image_sums<R>, dim3(blocks), dim3(256), 0, s, x, y, n, mode, partials());
+        LAUNCHCHK(c);
+        return reduce(blocks, 1, 8, host, s);
+    }
+
+    // image -> row spectrum
+    msr_status fwd_image(const R* img, R scale, C* out, int kout, hipStream_t s) {
+        op->row_load_fwd(row_args(nullptr, 0, nullptr, 0, out, kout), EpiLoad<R>{img, N(), scale}, s);
+        LAUNCHCHK(c);
+        return MSR_OK;
+    }
+
+    msr_status col_psf(int step, const C* in, C* out, hipStream_t s) {
+        op->col_psf(col_args(in, nullptr, out, c->K[step - 1]), ModePsf<R>{hh(step), P(), c->sh.T}, s);
+        LAUNCHCHK(c);
+        return MSR_OK;
+    }
+    msr_status col_filth(const C* in, C* out, bool red, hipStream_t s) {
+        op->col_filth(col_args(in, nullptr, out, c->sh.Cfull, red), ModeFilterH<R>{filters(), inv_p2()}, s);
+        LAUNCHCHK(c);
+        return MSR_OK;
+    }
+    msr_status col_filtl(const C* in, const C* in2, C* out, bool red, hipStream_t s) {
+        op->col_filtl(col_args(in, in2, out, c->KL, red), ModeFilterL<R>{filters(), inv_p2()}, s);
+        LAUNCHCHK(c);
+        return MSR_OK;
+    }
+
+    // The gradient chain of step s applied to the spectrum in SA (alpha); leaves
+    // the half-gradient spectrum in SB (+ SC for k_x < K_L in step 2).  `y` is
+    // the data image (null for the normal operator alone); step 2 subtracts the
+    // spectrum of l (SL) when `use_l`.
+    msr_status grad_chain(int step, const R* y, bool use_l, hipStream_t s) {
+        const int Ks = c->K[step - 1];
+        TRY(col_psf(step, SA(), SB(), s));
+        const int kr = step == 1 ? Ks : c->sh.Cfull;
+        op->row_resid_fwd(row_args(SB(), Ks, nullptr, 0, SC(), kr), EpiResid<R>{y, nullptr, N()}, s);
+        LAUNCHCHK(c);
+        if (step == 1) return col_psf(1, SC(), SB(), s);
+        TRY(col_filth(SC(), SB(), false, s));
+        op->row_resid_fwd(row_args(SB(), c->sh.Cfull, nullptr, 0, SC(), Ks), EpiResid<R>{nullptr, nullptr, N()}, s);
+        LAUNCHCHK(c);
+        TRY(col_psf(2, SC(), SB(), s));
+        return col_filtl(SA(), use_l ? SL() : nullptr, SC(), false, s);
+    }
+
+    static double momentum(int k) { return k >= 1 ? (k - 1.0) / (k + 2.0) : 0.0; }
+
+    // One FISTA iteration k (1-based) of step s.
+    msr_status iterate(int step, int k, double mu, double lambda, hipStream_t s) {
+        TRY(grad_chain(step, dirty(step), true, s));
+        EpiUpdate<R> u{};
+        u.b1 = beta(k - 1);
+        u.b2 = beta(k);
+        u.ld = N();
+        u.two_mu = (R)(2.0 * mu);
+        u.thr = (R)(mu * lambda);
+        u.t_prev = (R)momentum(k - 1);
+        u.t_cur = (R)momentum(k);
+        u.positivity = c->cfg.positivity;
+        const int Ks = c->K[step - 1];
+        RowArgs<R> a = step == 1 ? row_args(SB(), Ks, nullptr, 0, SA(), KA(1))
+                                 : row_args(SB(), Ks, SC(), c->KL, SA(), KA(2));
+        op->row_update_fwd(a, u, s);
+        LAUNCHCHK(c);
+        return MSR_OK;
+    }
+
+    // Exact objective of step s at image x (device), FP64 sums.  out: F, data, l1.
+    // Uses SB, SC as scratch (and SL for step 2); SA is preserved.
+    msr_status objective_at(int step, double lambda, const R* x, double out[3], hipStream_t s) {
+        double data = 0.0;
+        if (step == 1) {
+            TRY(fwd_image(x, (R)1, SB(), c->K[0], s));
+            TRY(col_psf(1, SB(), SC(), s));
+            op->row_resid(row_args(SC(), c->K[0], nullptr, 0, nullptr, 0, true), EpiResid<R>{dirty(1), nullptr, N()}, s);
+            LAUNCHCHK(c);
+            TRY(reduce(row_grid(), 1, 0, &data, s));
+        } else {
+            double dh = 0.0, dl = 0.0;
+            TRY(fwd_image(x, (R)1, SB(), KA(2), s));
+            TRY(col_psf(2, SB(), SC(), s));
+            op->row_resid_fwd(row_args(SC(), c->K[1], nullptr, 0, SC(), c->sh.Cfull),
+                              EpiResid<R>{dirty(2), nullptr, N()}, s);
+            LAUNCHCHK(c);
+            TRY(col_filth(SC(), SC(), true, s));
+            TRY(reduce(col_grid(c->sh.Cfull), 1, 0, &dh, s));
+            TRY(col_filtl(SB(), SL(), SC(), true, s));
+            TRY(reduce(col_grid(c->KL), 1, 0, &dl, s));
+            data = (dh + dl) / ((double)P() * (double)P());
+        }
+        double l1 = 0.0;
+        TRY(image_reduce(x, nullptr, 0, &l1, s));
+        out[0] = data + lambda * l1;
+        out[1] = data;
+        out[2] = l1;
+        return MSR_OK;
+    }
+
+    msr_status set_low_res(const R* low_res, hipStream_t s) { return fwd_image(low_res, (R)1, SL(), c->KL, s); }
+
+    msr_status power_iteration(int step, int max_iter, double rtol, double* theta_out, int* iters_out, hipStream_t s) {
+        const size_t n = c->sh.img_elems;
+        R* v = tmp(0);
+        R* w = tmp(1);
+        hipLaunchKernelGGL(start_vector<R>, dim3(blocks_for(n)), dim3(256), 0, s, v, (unsigned long long)c->cfg.seed, n);
+        LAUNCHCHK(c);
+        double nv2 = 0.0;
+        TRY(image_reduce(v, nullptr, 1, &nv2, s));
+        if (!(nv2 > 0)) return fail(c, MSR_ERR_NUMERIC, "zero start vector");
+        double scale = 1.0 / std::sqrt(nv2);
+        double theta = 0.0, prev = -1.0;
+        int j = 0;
+        for (j = 1; j <= max_iter; ++j) {
+            TRY(fwd_image(v, (R)scale, SA(), KA(step), s));
+            TRY(grad_chain(step, nullptr, false, s));
+            EpiPower<R> ep{v, w, N(), (R)scale};
+            RowArgs<R> a = step == 1 ? row_args(SB(), c->K[0], nullptr, 0, nullptr, 0, true)
+                                     : row_args(SB(), c->K[1], SC(), c->KL, nullptr, 0, true);
+            op->row_power(a, ep, s);
+            LAUNCHCHK(c);
+            double sums[2];
+            TRY(reduce(row_grid(), 2, 0, sums, s));
+            // v has unit norm: theta = 2 <v, A v>
+            theta = 2.0 * sums[1];
             if (sums[0] == 0.0) {
                 theta = 0.0;
                 break;
             }
-            return fail(c, MSR_ERR_NUMERIC, "power iteration diverged at %d", j);
+            if (!std::isfinite(theta) || !std::isfinite(sums[0]))
+                return fail(c, MSR_ERR_NUMERIC, "power iteration diverged at %d", j);
+            scale = 1.0 / std::sqrt(sums[0]);
+            std::swap(v, w);
+            if (prev >= 0 && std::fabs(theta - prev) <= rtol * theta) break;
+            prev = theta;
         }
-        scale = 1.0 / std::sqrt(sums[0]);
-        std::swap(v, w);
-        if (prev >= 0 && std::fabs(theta - prev) <= rtol * theta) break;
-        prev = theta;
+        if (theta_out) *theta_out = theta;
+        if (iters_out) *iters_out = std::min(j, max_iter);
+        return MSR_OK;
     }
-    if (theta_out) *theta_out = theta;
-    if (iters_out) *iters_out = std::min(j, max_iter);
+
+    msr_status set_workspace() {
+        const int Pn = P();
+        std::vector<C> t(Pn);
+        for (int k = 0; k < Pn; ++k) {
+            const double a = -2.0 * M_PI * (double)k / (double)Pn;
+            t[k] = mk_host(std::cos(a), std::sin(a));
+        }
+        HIPCHK(c, hipMemcpy(tw(), t.data(), sizeof(C) * Pn, hipMemcpyHostToDevice));
+        return MSR_OK;
+    }
+    static C mk_host(double x, double y) {
+        C r;
+        r.x = (R)x;
+        r.y = (R)y;
+        return r;
+    }
+
+    msr_status set_dirty_psf(int step, const R* dirty_in, const R* psf, hipStream_t s) {
+        const int Pn = P();
+        HIPCHK(c, hipMemcpyAsync(dirty(step), dirty_in, c->sh.rs * c->sh.img_elems, hipMemcpyDeviceToDevice, s));
+        R centre = 0;
+        HIPCHK(c, hipMemcpyAsync(&centre, psf + (size_t)(Pn / 2) * Pn + Pn / 2, sizeof(R), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (!(std::fabs((double)centre - 1.0) <= 1e-5))
+            return fail(c, MSR_ERR_INVALID, "PSF value at (P/2, P/2) is %g, expected 1", (double)centre);
+        // h_hat = F(ifftshift PSF): row pass (P rows, unpadded), then column pass in place.
+        C* tmpspec = SB();  // SB and SC are contiguous and hold P x Cpad_psf
+        RowArgs<R> ra{};
+        ra.spec_out = tmpspec;
+        ra.tw = tw();
+        ra.partials = partials();
+        ra.NR = Pn;
+        ra.K_out = c->sh.Cfull;
+        opp->row_loadshift_fwd(ra, EpiLoadShift<R>{psf, Pn}, s);
+        LAUNCHCHK(c);
+        ColArgs<R> ca{};
+        ca.spec_in = tmpspec;
+        ca.spec_out = tmpspec;
+        ca.tw = tw();
+        ca.partials = partials();
+        ca.NR = Pn;
+        ca.K = c->sh.Cfull;
+        opp->col_forward(ca, ModeForward<R>{}, s);
+        LAUNCHCHK(c);
+        R* h = hh(step);
+        hipLaunchKernelGGL(psf_extract<R>, dim3(c->sh.Cfull), dim3(256), 0, s, tmpspec, c->sh.Tpsf, Pn, c->sh.T, h,
+                           colmax(), partials());
+        LAUNCHCHK(c);
+        if (c->sh.Cpad > c->sh.Cfull) {
+            hipLaunchKernelGGL(zero_hh_cols<R>, dim3(blocks_for(Pn)), dim3(256), 0, s, h, Pn, c->sh.T, c->sh.Cfull,
+                               c->sh.Cpad);
+            LAUNCHCHK(c);
+        }
+        std::vector<double> cm(c->sh.Cfull);
+        std::vector<double> part(2 * (size_t)c->sh.Cfull);
+        HIPCHK(c, hipMemcpyAsync(cm.data(), colmax(), sizeof(double) * c->sh.Cfull, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(part.data(), partials(), sizeof(double) * 2 * c->sh.Cfull, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        double mre = 0.0, mim = 0.0;
+        for (int k = 0; k < c->sh.Cfull; ++k) {
+            mre = std::max(mre, part[2 * k]);
+            mim = std::max(mim, part[2 * k + 1]);
+        }
+        if (!(mre > 0) || !std::isfinite(mre)) return fail(c, MSR_ERR_INVALID, "PSF spectrum is zero or not finite");
+        if (mim > 1e-4 * mre)
+            return fail(c, MSR_ERR_INVALID, "PSF is not point symmetric: max|Im h| / max|h| = %g", mim / mre);
+        int keep = c->sh.Cfull;
+        if (c->cfg.prune_tol > 0) {
+            const double thr = c->cfg.prune_tol * mre;
+            keep = 1;
+            for (int k = 0; k < c->sh.Cfull; ++k)
+                if (cm[k] > thr) keep = k + 1;
+        }
+        c->K[step - 1] = keep;
+        c->have_psf[step - 1] = true;
+        c->have_theta[step - 1] = false;
+        return MSR_OK;
+    }
+
+    msr_status solve(int step, const msr_solve* opt, const R* low_res, const R* x0, R* model_out, R* image_out,
+                     msr_result* res, hipStream_t s) {
+        if (!c->have_theta[step - 1]) {
+            double th = 0.0;
+            TRY(power_iteration(step, 200, 1e-6, &th, nullptr, s));
+            if (!(th > 0)) return fail(c, MSR_ERR_NUMERIC, "zero Lipschitz constant");
+            c->theta[step - 1] = kThetaMargin * th;
+            c->have_theta[step - 1] = true;
+        }
+        const double theta = c->theta[step - 1];
+        const double mu = 1.0 / theta;
+        const size_t nb = c->sh.rs * c->sh.img_elems;
+        if (x0) {
+            HIPCHK(c, hipMemcpyAsync(beta(0), x0, nb, hipMemcpyDeviceToDevice, s));
+        } else {
+            HIPCHK(c, hipMemsetAsync(beta(0), 0, nb, s));
+        }
+        HIPCHK(c, hipMemcpyAsync(beta(1), beta(0), nb, hipMemcpyDeviceToDevice, s));
+        if (step == 2) TRY(set_low_res(low_res, s));
+        TRY(fwd_image(beta(0), (R)1, SA(), KA(step), s));
+
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, hipEventRecord(e0, s));
+        const bool rule = opt->check_every > 0 && opt->f_ref != 0.0 && opt->tol > 0;
+        double F[3] = {0, 0, 0};
+        int k = 0;
+        bool conv = false;
+        double ttt = -1.0;
+        msr_status st = MSR_OK;
+        for (k = 1; k <= opt->max_iters; ++k) {
+            if ((st = iterate(step, k, mu, opt->lambda, s)) != MSR_OK) break;
+            if (opt->check_every > 0 && (k % opt->check_every == 0)) {
+                if ((st = objective_at(step, opt->lambda, beta(k), F, s)) != MSR_OK) break;
+                if (!std::isfinite(F[0])) {
+                    st = fail(c, MSR_ERR_NUMERIC, "objective is not finite at iteration %d", k);
+                    break;
+                }
+                if (rule && (F[0] - opt->f_ref) / std::fabs(opt->f_ref) <= opt->tol) {
+                    conv = true;
+                    float ms = 0.f;
+                    if (hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+                        ttt = ms;
+                    break;
+                }
+            }
+        }
+        const int done = std::min(k, opt->max_iters);
+        float ms = 0.f;
+        if (st == MSR_OK) {
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                st = fail(c, MSR_ERR_HIP, "event timing failed");
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (res) res->iters = done;
+        if (st != MSR_OK) return st;
+        const R* bK = beta(done);
+        TRY(objective_at(step, opt->lambda, bK, F, s));
+        if (!std::isfinite(F[0])) return fail(c, MSR_ERR_NUMERIC, "objective is not finite after %d iterations", done);
+        HIPCHK(c, hipMemcpyAsync(model_out, bK, nb, hipMemcpyDeviceToDevice, s));
+        if (image_out) {
+            // i_L = beta + (i~ - H beta) = beta - r
+            TRY(fwd_image(bK, (R)1, SB(), c->K[step - 1], s));
+            TRY(col_psf(step, SB(), SC(), s));
+            op->row_resid(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0), EpiResid<R>{dirty(step), tmp(0), N()},
+                          s);
+            LAUNCHCHK(c);
+            const size_t n = c->sh.img_elems;
+            hipLaunchKernelGGL(image_axpby<R>, dim3(blocks_for(n)), dim3(256), 0, s, image_out, bK, (const R*)tmp(0),
+                               (R)1, (R)-1, n);
+            LAUNCHCHK(c);
+        }
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (res) {
+            res->iters = done;
+            res->converged = conv ? 1 : 0;
+            res->objective = F[0];
+            res->data_term = F[1];
+            res->l1_norm = F[2];
+            res->theta = theta;
+            res->elapsed_ms = ms;
+            res->time_to_tol_ms = ttt;
+        }
+        return MSR_OK;
+    }
+
+    msr_status gradient(int step, const R* x, const R* low_res, R* g, hipStream_t s) {
+        if (step == 2) TRY(set_low_res(low_res, s));
+        TRY(fwd_image(x, (R)1, SA(), KA(step), s));
+        TRY(grad_chain(step, dirty(step), true, s));
+        RowArgs<R> a = step == 1 ? row_args(SB(), c->K[0], nullptr, 0, nullptr, 0)
+                                 : row_args(SB(), c->K[1], SC(), c->KL, nullptr, 0);
+        op->row_store(a, EpiStore<R>{g, N(), (R)2}, s);
+        LAUNCHCHK(c);
+        HIPCHK(c, hipStreamSynchronize(s));
+        return MSR_OK;
+    }
+
+    msr_status apply_psf(int step, const R* x, R* out, hipStream_t s) {
+        TRY(fwd_image(x, (R)1, SB(), c->K[step - 1], s));
+        TRY(col_psf(step, SB(), SC(), s));
+        op->row_store(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0), EpiStore<R>{out, N(), (R)1}, s);
+        LAUNCHCHK(c);
+        HIPCHK(c, hipStreamSynchronize(s));
+        return MSR_OK;
+    }
+
+    msr_status get_spectrum(int step, double* host_out, hipStream_t s) {
+        const int Pn = P(), T = c->sh.T, Cf = c->sh.Cfull;
+        std::vector<R> h(c->sh.hh_elems);
+        HIPCHK(c, hipMemcpyAsync(h.data(), hh(step), sizeof(R) * h.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        const double p2 = (double)Pn * Pn;
+        const int K = c->K[step - 1];
+        for (int ky = 0; ky < Pn; ++ky)
+            for (int kx = 0; kx < Cf; ++kx)
+                host_out[(size_t)ky * Cf + kx] = kx < K ? (double)h[((size_t)(kx / T) * Pn + ky) * T + kx % T] * p2 : 0.0;
+        return MSR_OK;
+    }
+
+    msr_status sigma2(const R* img, double* out, hipStream_t s) {
+        const int n = N();
+        const size_t nw = (size_t)(n - 4) * (n - 4);
+        const int blocks = (int)std::min<size_t>(1024, (nw + 255) / 256);
+        hipLaunchKernelGGL(window_variance<R>, dim3(blocks), dim3(256), 0, s, img, n, partials());
+        LAUNCHCHK(c);
+        double tot = 0.0;
+        TRY(reduce(blocks, 1, 8, &tot, s));
+        *out = tot / (double)nw;
+        return MSR_OK;
+    }
+
+    msr_status time_pass(int which, int reps, double* ms_out, double* bytes_out, hipStream_t s) {
+        const int Nn = N(), Pn = P(), K = c->K[0];
+        const double es = (double)c->sh.cs, rs = (double)c->sh.rs;
+        const double spec = (double)Nn * K * es, img = (double)Nn * Nn * rs;
+        auto launch = [&]() -> msr_status {
+            if (which == 0) return col_psf(1, SA(), SB(), s);
+            if (which == 1) {
+                op->row_resid_fwd(row_args(SB(), K, nullptr, 0, SC(), K), EpiResid<R>{dirty(1), nullptr, Nn}, s);
+                LAUNCHCHK(c);
+                return MSR_OK;
+            }
+            EpiUpdate<R> u{};
+            u.b1 = beta(0);
+            u.b2 = beta(1);
+            u.ld = Nn;
+            u.positivity = c->cfg.positivity;
+            op->row_update_fwd(row_args(SB(), K, nullptr, 0, SC(), K), u, s);
+            LAUNCHCHK(c);
+            return MSR_OK;
+        };
+        double bytes;
+        if (which == 0) bytes = 2 * spec + (double)Pn * K * rs;
+        else if (which == 1) bytes = 2 * spec + img;
+        else bytes = 2 * spec + 3 * img;
+        TRY(launch());  // warm
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, hipEventRecord(e0, s));
+        msr_status st = MSR_OK;
+        for (int r = 0; r < reps && st == MSR_OK; ++r) st = launch();
+        float ms = 0.f;
+        if (st == MSR_OK) {
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                st = fail(c, MSR_ERR_HIP, "event timing failed");
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (st != MSR_OK) return st;
+        if (ms_out) *ms_out = ms / reps;
+        if (bytes_out) *bytes_out = bytes;
+        return MSR_OK;
+    }
+};
+
+// Runs f(Impl<R>&) in the context's precision.
+template <typename F>
+msr_status with_impl(msr_ctx* c, F&& f) {
+    if (c->sh.prec == 64) {
+        Impl<double> im(c);
+        return f(im);
+    }
+    Impl<float> im(c);
+    return f(im);
+}
+
+bool ready(msr_ctx* c) { return c && c->ws; }
+
+msr_status check_step(msr_ctx* c, int step, bool need_filters_for_2) {
+    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
+    if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
+    if (need_filters_for_2 && step == 2 && !c->have_filters) return fail(c, MSR_ERR_STATE, "set_filters first");
+    HIPCHK(c, hipSetDevice(c->cfg.device));
     return MSR_OK;
 }
 
@@ -450,8 +768,6 @@ msr_status msr_init(const msr_config* cfg, msr_ctx** out) {
     c->cfg = *cfg;
     c->sh = s;
     c->lay = make_layout(s);
-    c->op = ops_for(s.N, s.padded);
-    c->opp = ops_for(s.P, false);
     *out = c;
     return MSR_OK;
 }
@@ -467,143 +783,48 @@ msr_status msr_set_workspace(msr_ctx* c, void* dev, size_t bytes) {
     HIPCHK(c, hipSetDevice(c->cfg.device));
     c->ws = static_cast<char*>(dev);
     c->ws_bytes = bytes;
-    const Layout& l = c->lay;
-    c->tw = reinterpret_cast<float2*>(c->ws + l.tw);
-    c->SA = reinterpret_cast<float2*>(c->ws + l.SA);
-    c->SB = reinterpret_cast<float2*>(c->ws + l.SB);
-    c->SC = reinterpret_cast<float2*>(c->ws + l.SC);
-    c->SL = reinterpret_cast<float2*>(c->ws + l.SL);
-    c->hh[0] = reinterpret_cast<float*>(c->ws + l.hh1);
-    c->hh[1] = reinterpret_cast<float*>(c->ws + l.hh2);
-    c->dirty[0] = reinterpret_cast<float*>(c->ws + l.d1);
-    c->dirty[1] = reinterpret_cast<float*>(c->ws + l.d2);
-    c->beta[0] = reinterpret_cast<float*>(c->ws + l.b0);
-    c->beta[1] = reinterpret_cast<float*>(c->ws + l.b1);
-    c->tmp[0] = reinterpret_cast<float*>(c->ws + l.t0);
-    c->tmp[1] = reinterpret_cast<float*>(c->ws + l.t1);
-    c->partials = reinterpret_cast<double*>(c->ws + l.partials);
-    c->scal = reinterpret_cast<double*>(c->ws + l.scal);
-    c->colmax = reinterpret_cast<float*>(c->ws + l.colmax);
-    // twiddles exp(-2 pi i k / P), computed in double and rounded
-    const int P = c->sh.P;
-    std::vector<float2> tw(P);
-    for (int k = 0; k < P; ++k) {
-        const double a = -2.0 * M_PI * (double)k / (double)P;
-        tw[k] = make_float2((float)std::cos(a), (float)std::sin(a));
-    }
-    HIPCHK(c, hipMemcpy(c->tw, tw.data(), sizeof(float2) * P, hipMemcpyHostToDevice));
     c->have_psf[0] = c->have_psf[1] = false;
     c->have_theta[0] = c->have_theta[1] = false;
     c->have_filters = false;
-    return MSR_OK;
+    return with_impl(c, [](auto& im) { return im.set_workspace(); });
 }
 
-msr_status msr_set_dirty_psf(msr_ctx* c, int step, const float* dirty, const float* psf, void* stream) {
+msr_status msr_set_dirty_psf(msr_ctx* c, int step, const void* dirty, const void* psf, void* stream) {
     if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
     if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
     if (!dirty || !psf) return fail(c, MSR_ERR_INVALID, "null image");
-    hipStream_t s = S(stream);
     HIPCHK(c, hipSetDevice(c->cfg.device));
-    const int N = c->sh.N, P = c->sh.P;
-    HIPCHK(c, hipMemcpyAsync(c->dirty[step - 1], dirty, sizeof(float) * c->sh.img_elems, hipMemcpyDeviceToDevice, s));
-    float centre = 0.f;
-    HIPCHK(c, hipMemcpyAsync(&centre, psf + (size_t)(P / 2) * P + P / 2, sizeof(float), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (!(std::fabs(centre - 1.f) <= 1e-5f))
-        return fail(c, MSR_ERR_INVALID, "PSF value at (P/2, P/2) is %g, expected 1", (double)centre);
-    // h_hat = F(ifftshift PSF): row pass (P rows, unpadded), then column pass in place.
-    float2* tmp = c->SB;  // SB and SC are contiguous and hold P x Cpad_psf
-    RowArgs ra{};
-    ra.spec_out = tmp;
-    ra.tw = c->tw;
-    ra.partials = c->partials;
-    ra.NR = P;
-    ra.K_out = c->sh.Cfull;
-    EpiLoadShift el{psf, P};
-    c->opp->row_loadshift_fwd(ra, el, s);
-    LAUNCHCHK(c);
-    ColArgs ca{};
-    ca.spec_in = tmp;
-    ca.spec_out = tmp;
-    ca.tw = c->tw;
-    ca.partials = c->partials;
-    ca.NR = P;
-    ca.K = c->sh.Cfull;
-    c->opp->col_forward(ca, ModeForward{}, s);
-    LAUNCHCHK(c);
-    float* hh = c->hh[step - 1];
-    hipLaunchKernelGGL(psf_extract, dim3(c->sh.Cfull), dim3(256), 0, s, tmp, c->sh.Tpsf, P, c->sh.T, c->sh.Cfull, hh,
-                       c->colmax, c->partials);
-    LAUNCHCHK(c);
-    if (c->sh.Cpad > c->sh.Cfull) {
-        hipLaunchKernelGGL(zero_hh_cols, dim3((P + 255) / 256), dim3(256), 0, s, hh, P, c->sh.T, c->sh.Cfull, c->sh.Cpad);
-        LAUNCHCHK(c);
-    }
-    std::vector<float> colmax(c->sh.Cfull);
-    std::vector<double> part(2 * (size_t)c->sh.Cfull);
-    HIPCHK(c, hipMemcpyAsync(colmax.data(), c->colmax, sizeof(float) * c->sh.Cfull, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(part.data(), c->partials, sizeof(double) * 2 * c->sh.Cfull, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    double mre = 0.0, mim = 0.0;
-    for (int k = 0; k < c->sh.Cfull; ++k) {
-        mre = std::max(mre, part[2 * k]);
-        mim = std::max(mim, part[2 * k + 1]);
-    }
-    if (!(mre > 0) || !std::isfinite(mre)) return fail(c, MSR_ERR_INVALID, "PSF spectrum is zero or not finite");
-    if (mim > 1e-4 * mre) return fail(c, MSR_ERR_INVALID, "PSF is not point symmetric: max|Im h| / max|h| = %g", mim / mre);
-    int keep = c->sh.Cfull;
-    if (c->cfg.prune_tol > 0) {
-        const double thr = c->cfg.prune_tol * mre;
-        keep = 1;
-        for (int k = 0; k < c->sh.Cfull; ++k)
-            if ((double)colmax[k] > thr) keep = k + 1;
-    }
-    c->K[step - 1] = keep;
-    c->have_psf[step - 1] = true;
-    c->have_theta[step - 1] = false;
-    (void)N;
-    return MSR_OK;
+    c->have_psf[step - 1] = false;
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        return im.set_dirty_psf(step, static_cast<const R*>(dirty), static_cast<const R*>(psf), S(stream));
+    });
 }
 
 msr_status msr_set_filters(msr_ctx* c, double ell, double delta, double sigma2, double eta2) {
     if (!c) return MSR_ERR_INVALID;
-    if (!(delta > 0) || !(sigma2 > 0) || !(eta2 > 0) || !std::isfinite(ell))
-        return fail(c, MSR_ERR_INVALID, "need delta > 0, sigma2 > 0, eta2 > 0");
+    if (!(delta > 0) || !(sigma2 > 0) || !(eta2 > 0) || !std::isfinite(ell) || !std::isfinite(delta) ||
+        !std::isfinite(sigma2) || !std::isfinite(eta2))
+        return fail(c, MSR_ERR_INVALID, "need finite ell, delta > 0, sigma2 > 0, eta2 > 0");
     c->ell = ell;
     c->delta = delta;
     c->sigma2 = sigma2;
     c->eta2 = eta2;
-    FilterCoef f{};
-    f.ell = (float)ell;
-    f.delta = (float)delta;
-    f.inv_sigma2 = (float)(1.0 / sigma2);
-    f.inv_eta2 = (float)(1.0 / eta2);
-    f.sigma2 = (float)sigma2;
-    f.eta2 = (float)eta2;
-    f.half_pi_over_delta = (float)(M_PI / (2.0 * delta));
-    f.P = c->sh.P;
-    c->fc = f;
-    // g_L vanishes for r >= ell + delta: columns k_x <= ell + delta can be non-zero.
+    // g_L vanishes for r >= ell + delta: only columns k_x <= ell + delta can be non-zero.
     const double lim = ell + delta;
     int kl = lim < 0 ? 0 : (int)std::floor(lim) + 1;
-    c->KL = std::min(std::max(kl, 0), c->sh.Cfull);
-    if (c->KL == 0) c->KL = 1;
+    c->KL = std::max(1, std::min(kl, c->sh.Cfull));
     c->have_filters = true;
     c->have_theta[1] = false;
     return MSR_OK;
 }
 
 msr_status msr_lipschitz(msr_ctx* c, int step, int max_iter, double rtol, double* theta, int* iters, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
-    if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
-    if (!c->have_psf[step - 1] || (step == 2 && !c->have_filters))
-        return fail(c, MSR_ERR_STATE, "set the PSF (and filters for step 2) first");
+    TRY(check_step(c, step, true));
     if (max_iter <= 0) max_iter = 200;
     if (!(rtol > 0)) rtol = 1e-6;
-    HIPCHK(c, hipSetDevice(c->cfg.device));
     double th = 0.0;
-    msr_status st = power_iteration(c, step, max_iter, rtol, &th, iters, S(stream));
-    if (st != MSR_OK) return st;
+    TRY(with_impl(c, [&](auto& im) { return im.power_iteration(step, max_iter, rtol, &th, iters, S(stream)); }));
     if (theta) *theta = th;
     c->theta[step - 1] = kThetaMargin * th;
     c->have_theta[step - 1] = th > 0;
@@ -619,262 +840,93 @@ msr_status msr_set_lipschitz(msr_ctx* c, int step, double theta) {
     return MSR_OK;
 }
 
-static msr_status solve(msr_ctx* c, int step, const msr_solve* opt, const float* low_res, const float* x0,
-                        float* model_out, float* image_out, msr_result* res, hipStream_t s) {
+static msr_status solve_entry(msr_ctx* c, int step, const msr_solve* opt, const void* low_res, const void* x0,
+                              void* model_out, void* image_out, msr_result* res, void* stream) {
     if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
     if (!opt || !model_out) return fail(c, MSR_ERR_INVALID, "null argument");
     if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
     if (step == 2 && (!c->have_filters || !low_res)) return fail(c, MSR_ERR_STATE, "step 2 needs filters and low_res");
-    if (opt->max_iters < 0 || !(opt->lambda >= 0)) return fail(c, MSR_ERR_INVALID, "bad solve options");
+    if (opt->max_iters < 0 || !(opt->lambda >= 0) || !std::isfinite(opt->lambda))
+        return fail(c, MSR_ERR_INVALID, "bad solve options");
     HIPCHK(c, hipSetDevice(c->cfg.device));
-    msr_status st;
-    if (!c->have_theta[step - 1]) {
-        if ((st = msr_lipschitz(c, step, 200, 1e-6, nullptr, nullptr, s)) != MSR_OK) return st;
-        if (!c->have_theta[step - 1]) return fail(c, MSR_ERR_NUMERIC, "zero Lipschitz constant");
-    }
-    const double theta = c->theta[step - 1];
-    const double mu = 1.0 / theta;
-    const size_t nb = sizeof(float) * c->sh.img_elems;
-    if (x0) {
-        HIPCHK(c, hipMemcpyAsync(c->beta[0], x0, nb, hipMemcpyDeviceToDevice, s));
-    } else {
-        HIPCHK(c, hipMemsetAsync(c->beta[0], 0, nb, s));
-    }
-    HIPCHK(c, hipMemcpyAsync(c->beta[1], c->beta[0], nb, hipMemcpyDeviceToDevice, s));
-    if (step == 2 && (st = set_low_res(c, low_res, s)) != MSR_OK) return st;
-    if ((st = fwd_image(c, c->beta[0], 1.f, c->SA, KA(c, step), s)) != MSR_OK) return st;
-
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
-    HIPCHK(c, hipEventRecord(e0, s));
-    const bool rule = opt->check_every > 0 && opt->f_ref != 0.0 && opt->tol > 0;
-    double F[3] = {0, 0, 0};
-    int k = 0;
-    bool conv = false;
-    double ttt = -1.0;
-    for (k = 1; k <= opt->max_iters; ++k) {
-        if ((st = iterate(c, step, k, mu, opt->lambda, s)) != MSR_OK) break;
-        if (opt->check_every > 0 && (k % opt->check_every == 0)) {
-            if ((st = objective_at(c, step, opt->lambda, c->beta[k & 1], F, s)) != MSR_OK) break;
-            if (!std::isfinite(F[0])) {
-                st = fail(c, MSR_ERR_NUMERIC, "objective is not finite at iteration %d", k);
-                break;
-            }
-            if (rule && (F[0] - opt->f_ref) / std::fabs(opt->f_ref) <= opt->tol) {
-                conv = true;
-                HIPCHK(c, hipEventRecord(e1, s));
-                HIPCHK(c, hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-                ttt = ms;
-                break;
-            }
-        }
-    }
-    const int done = std::min(k, opt->max_iters);
-    if (st != MSR_OK) {
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
-        if (res) res->iters = done;
-        return st;
-    }
-    HIPCHK(c, hipEventRecord(e1, s));
-    HIPCHK(c, hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    const float* bK = c->beta[done & 1];
-    if ((st = objective_at(c, step, opt->lambda, bK, F, s)) != MSR_OK) return st;
-    if (!std::isfinite(F[0])) {
-        if (res) res->iters = done;
-        return fail(c, MSR_ERR_NUMERIC, "objective is not finite at the end (%d iterations)", done);
-    }
-    HIPCHK(c, hipMemcpyAsync(model_out, bK, nb, hipMemcpyDeviceToDevice, s));
-    if (image_out) {
-        // i_L = beta + (i~ - H beta) = beta - r
-        if ((st = fwd_image(c, bK, 1.f, c->SB, c->K[step - 1], s)) != MSR_OK) return st;
-        if ((st = col_psf(c, step, c->SB, c->SC, s)) != MSR_OK) return st;
-        EpiResid er{c->dirty[step - 1], c->tmp[0], c->sh.N};
-        c->op->row_resid(row_args(c, c->SC, c->K[step - 1], nullptr, 0, nullptr, 0), er, s);
-        LAUNCHCHK(c);
-        const size_t n = c->sh.img_elems;
-        hipLaunchKernelGGL(image_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, image_out, bK,
-                           (const float*)c->tmp[0], 1.f, -1.f, n);
-        LAUNCHCHK(c);
-    }
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (res) {
-        res->iters = done;
-        res->converged = conv ? 1 : 0;
-        res->objective = F[0];
-        res->data_term = F[1];
-        res->l1_norm = F[2];
-        res->theta = theta;
-        res->elapsed_ms = ms;
-        res->time_to_tol_ms = ttt;
-    }
-    return MSR_OK;
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        return im.solve(step, opt, static_cast<const R*>(low_res), static_cast<const R*>(x0), static_cast<R*>(model_out),
+                        static_cast<R*>(image_out), res, S(stream));
+    });
 }
 
-msr_status msr_step1_low_res(msr_ctx* c, const msr_solve* opt, const float* x0, float* model_out, float* image_out,
+msr_status msr_step1_low_res(msr_ctx* c, const msr_solve* opt, const void* x0, void* model_out, void* image_out,
                              msr_result* res, void* stream) {
-    return solve(c, 1, opt, nullptr, x0, model_out, image_out, res, S(stream));
+    return solve_entry(c, 1, opt, nullptr, x0, model_out, image_out, res, stream);
 }
 
-msr_status msr_step2_full_res(msr_ctx* c, const msr_solve* opt, const float* low_res, const float* x0,
-                              float* model_out, msr_result* res, void* stream) {
-    return solve(c, 2, opt, low_res, x0, model_out, nullptr, res, S(stream));
+msr_status msr_step2_full_res(msr_ctx* c, const msr_solve* opt, const void* low_res, const void* x0, void* model_out,
+                              msr_result* res, void* stream) {
+    return solve_entry(c, 2, opt, low_res, x0, model_out, nullptr, res, stream);
 }
 
-msr_status msr_objective(msr_ctx* c, int step, double lambda, const float* x, const float* low_res, double out[3],
+msr_status msr_objective(msr_ctx* c, int step, double lambda, const void* x, const void* low_res, double out[3],
                          void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
-    if ((step != 1 && step != 2) || !x || !out) return fail(c, MSR_ERR_INVALID, "bad arguments");
-    if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
-    if (step == 2 && (!c->have_filters || !low_res)) return fail(c, MSR_ERR_STATE, "step 2 needs filters and low_res");
-    HIPCHK(c, hipSetDevice(c->cfg.device));
-    hipStream_t s = S(stream);
-    msr_status st;
-    if (step == 2 && (st = set_low_res(c, low_res, s)) != MSR_OK) return st;
-    return objective_at(c, step, lambda, x, out, s);
+    TRY(check_step(c, step, true));
+    if (!x || !out || (step == 2 && !low_res)) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        if (step == 2) TRY(im.set_low_res(static_cast<const R*>(low_res), S(stream)));
+        return im.objective_at(step, lambda, static_cast<const R*>(x), out, S(stream));
+    });
 }
 
-msr_status msr_gradient(msr_ctx* c, int step, const float* x, const float* low_res, float* grad_out, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
-    if ((step != 1 && step != 2) || !x || !grad_out) return fail(c, MSR_ERR_INVALID, "bad arguments");
-    if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
-    if (step == 2 && (!c->have_filters || !low_res)) return fail(c, MSR_ERR_STATE, "step 2 needs filters and low_res");
-    HIPCHK(c, hipSetDevice(c->cfg.device));
-    hipStream_t s = S(stream);
-    msr_status st;
-    if (step == 2 && (st = set_low_res(c, low_res, s)) != MSR_OK) return st;
-    if ((st = fwd_image(c, x, 1.f, c->SA, KA(c, step), s)) != MSR_OK) return st;
-    if ((st = grad_chain(c, step, c->dirty[step - 1], true, s)) != MSR_OK) return st;
-    EpiStore es{grad_out, c->sh.N, 2.f};
-    RowArgs a = step == 1 ? row_args(c, c->SB, c->K[0], nullptr, 0, nullptr, 0)
-                          : row_args(c, c->SB, c->K[1], c->SC, c->KL, nullptr, 0);
-    c->op->row_store(a, es, s);
-    LAUNCHCHK(c);
-    HIPCHK(c, hipStreamSynchronize(s));
-    return MSR_OK;
+msr_status msr_gradient(msr_ctx* c, int step, const void* x, const void* low_res, void* grad_out, void* stream) {
+    TRY(check_step(c, step, true));
+    if (!x || !grad_out || (step == 2 && !low_res)) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        return im.gradient(step, static_cast<const R*>(x), static_cast<const R*>(low_res), static_cast<R*>(grad_out),
+                           S(stream));
+    });
 }
 
-msr_status msr_apply_psf(msr_ctx* c, int step, const float* x, float* out, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
-    if ((step != 1 && step != 2) || !x || !out) return fail(c, MSR_ERR_INVALID, "bad arguments");
-    if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
-    HIPCHK(c, hipSetDevice(c->cfg.device));
-    hipStream_t s = S(stream);
-    msr_status st;
-    if ((st = fwd_image(c, x, 1.f, c->SB, c->K[step - 1], s)) != MSR_OK) return st;
-    if ((st = col_psf(c, step, c->SB, c->SC, s)) != MSR_OK) return st;
-    EpiStore es{out, c->sh.N, 1.f};
-    c->op->row_store(row_args(c, c->SC, c->K[step - 1], nullptr, 0, nullptr, 0), es, s);
-    LAUNCHCHK(c);
-    HIPCHK(c, hipStreamSynchronize(s));
-    return MSR_OK;
+msr_status msr_apply_psf(msr_ctx* c, int step, const void* x, void* out, void* stream) {
+    TRY(check_step(c, step, false));
+    if (!x || !out) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        return im.apply_psf(step, static_cast<const R*>(x), static_cast<R*>(out), S(stream));
+    });
 }
 
 msr_status msr_get_spectrum(msr_ctx* c, int step, double* host_out, int* kept, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
-    if ((step != 1 && step != 2) || !host_out) return fail(c, MSR_ERR_INVALID, "bad arguments");
-    if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
-    HIPCHK(c, hipSetDevice(c->cfg.device));
-    hipStream_t s = S(stream);
-    const int P = c->sh.P, T = c->sh.T, C = c->sh.Cfull;
-    std::vector<float> hh(c->sh.hh_elems);
-    HIPCHK(c, hipMemcpyAsync(hh.data(), c->hh[step - 1], sizeof(float) * hh.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    const double p2 = (double)P * P;
-    const int K = c->K[step - 1];
-    for (int ky = 0; ky < P; ++ky)
-        for (int kx = 0; kx < C; ++kx)
-            host_out[(size_t)ky * C + kx] = kx < K ? (double)hh[((size_t)(kx / T) * P + ky) * T + kx % T] * p2 : 0.0;
-    if (kept) *kept = K;
+    TRY(check_step(c, step, false));
+    if (!host_out) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    TRY(with_impl(c, [&](auto& im) { return im.get_spectrum(step, host_out, S(stream)); }));
+    if (kept) *kept = c->K[step - 1];
     return MSR_OK;
 }
 
-msr_status msr_estimate_sigma2(msr_ctx* c, const float* dirty, double* sigma2, void* stream) {
+msr_status msr_estimate_sigma2(msr_ctx* c, const void* dirty, double* sigma2, void* stream) {
     if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
     if (!dirty || !sigma2) return fail(c, MSR_ERR_INVALID, "bad arguments");
     HIPCHK(c, hipSetDevice(c->cfg.device));
-    hipStream_t s = S(stream);
-    const int n = c->sh.N;
-    const size_t nw = (size_t)(n - 4) * (n - 4);
-    const int blocks = (int)std::min<size_t>(1024, (nw + 255) / 256);
-    hipLaunchKernelGGL(window_variance, dim3(blocks), dim3(256), 0, s, dirty, n, c->partials);
-    LAUNCHCHK(c);
-    double tot = 0.0;
-    msr_status st = reduce(c, blocks, 1, 8, &tot, s);
-    if (st != MSR_OK) return st;
-    *sigma2 = tot / (double)nw;
-    return MSR_OK;
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        return im.sigma2(static_cast<const R*>(dirty), sigma2, S(stream));
+    });
 }
 
 msr_status msr_default_lambda(msr_ctx* c, int step, int cycle, double cc, double* lambda, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
-    if ((step != 1 && step != 2) || !lambda || cycle < 1) return fail(c, MSR_ERR_INVALID, "bad arguments");
-    if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
-    HIPCHK(c, hipSetDevice(c->cfg.device));
+    TRY(check_step(c, step, false));
+    if (!lambda || cycle < 1) return fail(c, MSR_ERR_INVALID, "bad arguments");
     double s2 = 0.0;
-    msr_status st = image_reduce(c, c->dirty[step - 1], nullptr, 1, &s2, S(stream));
-    if (st != MSR_OK) return st;
+    TRY(with_impl(c, [&](auto& im) { return im.image_reduce(im.dirty(step), nullptr, 1, &s2, S(stream)); }));
     *lambda = cc * std::sqrt(s2) * std::ldexp(1.0, cycle - 1);
     return MSR_OK;
 }
 
 msr_status msr_time_pass(msr_ctx* c, int which, int reps, double* ms_out, double* bytes_out, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
-    if (!c->have_psf[0]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(1) first");
+    TRY(check_step(c, 1, false));
     if (reps <= 0 || which < 0 || which > 2) return fail(c, MSR_ERR_INVALID, "bad arguments");
-    HIPCHK(c, hipSetDevice(c->cfg.device));
-    hipStream_t s = S(stream);
-    const int N = c->sh.N, P = c->sh.P, K = c->K[0];
-    const double spec = (double)N * K * 8.0, img = (double)N * N * 4.0;
-    double bytes = 0.0;
-    auto launch = [&]() -> msr_status {
-        if (which == 0) return col_psf(c, 1, c->SA, c->SB, s);
-        if (which == 1) {
-            EpiResid er{c->dirty[0], nullptr, N};
-            c->op->row_resid_fwd(row_args(c, c->SB, K, nullptr, 0, c->SC, K), er, s);
-            LAUNCHCHK(c);
-            return MSR_OK;
-        }
-        EpiUpdate u{};
-        u.b1 = c->beta[0];
-        u.b2 = c->beta[1];
-        u.ld = N;
-        u.two_mu = 0.f;
-        u.thr = 0.f;
-        u.t_prev = 0.f;
-        u.t_cur = 0.f;
-        u.positivity = c->cfg.positivity;
-        c->op->row_update_fwd(row_args(c, c->SB, K, nullptr, 0, c->SC, K), u, s);
-        LAUNCHCHK(c);
-        return MSR_OK;
-    };
-    if (which == 0) bytes = 2 * spec + (double)P * K * 4.0;
-    else if (which == 1) bytes = 2 * spec + img;
-    else bytes = 2 * spec + 3 * img;
-    msr_status st = launch();  // warm
-    if (st != MSR_OK) return st;
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
-    HIPCHK(c, hipEventRecord(e0, s));
-    for (int r = 0; r < reps && st == MSR_OK; ++r) st = launch();
-    HIPCHK(c, hipEventRecord(e1, s));
-    HIPCHK(c, hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (st != MSR_OK) return st;
-    if (ms_out) *ms_out = ms / reps;
-    if (bytes_out) *bytes_out = bytes;
-    return MSR_OK;
+    return with_impl(c, [&](auto& im) { return im.time_pass(which, reps, ms_out, bytes_out, S(stream)); });
 }
 
 }  // extern "C"

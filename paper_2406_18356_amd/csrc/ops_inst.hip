@@ -9,28 +9,29 @@
 namespace msr {
 namespace {
 
-template <int L, bool PADDED>
+template <typename R, int L, bool PADDED>
 struct Inst {
-    using C = LineCfg<L, PADDED>;
-    static constexpr int T = tile_width(L);
-    static constexpr int PAIRS = row_pairs(L, PADDED);
-    static constexpr int RT = PAIRS * C::TPF;
-    static constexpr int CT = T * C::TPF;
+    using Cf = LineCfg<L, PADDED, R>;
+    static constexpr int ES = (int)sizeof(cplx<R>);
+    static constexpr int T = tile_width(L, ES);
+    static constexpr int PAIRS = row_pairs(L, PADDED, ES);
+    static constexpr int RT = PAIRS * Cf::TPF;
+    static constexpr int CT = T * Cf::TPF;
 
     template <bool INV_IN, bool FWD_OUT, class Epi>
-    static void row(const RowArgs& a, const Epi& e, hipStream_t s) {
+    static void row(const RowArgs<R>& a, const Epi& e, hipStream_t s) {
         const int grid = a.NR / (2 * PAIRS);
-        hipLaunchKernelGGL((row_kernel<L, PADDED, PAIRS, T, INV_IN, FWD_OUT, Epi>), dim3(grid), dim3(RT), 0, s, a, e);
+        hipLaunchKernelGGL((row_kernel<R, L, PADDED, PAIRS, T, INV_IN, FWD_OUT, Epi>), dim3(grid), dim3(RT), 0, s, a, e);
     }
     template <class Mode>
-    static void col(const ColArgs& a, const Mode& m, hipStream_t s) {
+    static void col(const ColArgs<R>& a, const Mode& m, hipStream_t s) {
         const int grid = (a.K + T - 1) / T;
         if (grid <= 0) return;
-        hipLaunchKernelGGL((col_kernel<L, PADDED, T, Mode>), dim3(grid), dim3(CT), 0, s, a, m);
+        hipLaunchKernelGGL((col_kernel<R, L, PADDED, T, Mode>), dim3(grid), dim3(CT), 0, s, a, m);
     }
 
-    static Ops make(bool full) {
-        Ops o;
+    static Ops<R> make(bool full) {
+        Ops<R> o;
         o.L = L;
         o.padded = PADDED;
         o.T = T;
@@ -39,43 +40,53 @@ struct Inst {
         o.row_threads = RT;
         o.col_threads = CT;
         if constexpr (!PADDED) {
-            o.row_loadshift_fwd = &row<false, true, EpiLoadShift>;
-            o.col_forward = &col<ModeForward>;
+            o.row_loadshift_fwd = &row<false, true, EpiLoadShift<R>>;
+            o.col_forward = &col<ModeForward<R>>;
         }
         if (full) {
-            o.row_load_fwd = &row<false, true, EpiLoad>;
-            o.row_store = &row<true, false, EpiStore>;
-            o.row_resid_fwd = &row<true, true, EpiResid>;
-            o.row_resid = &row<true, false, EpiResid>;
-            o.row_update_fwd = &row<true, true, EpiUpdate>;
-            o.row_power = &row<true, false, EpiPower>;
-            o.col_psf = &col<ModePsf>;
-            o.col_filth = &col<ModeFilterH>;
-            o.col_filtl = &col<ModeFilterL>;
+            o.row_load_fwd = &row<false, true, EpiLoad<R>>;
+            o.row_store = &row<true, false, EpiStore<R>>;
+            o.row_resid_fwd = &row<true, true, EpiResid<R>>;
+            o.row_resid = &row<true, false, EpiResid<R>>;
+            o.row_update_fwd = &row<true, true, EpiUpdate<R>>;
+            o.row_power = &row<true, false, EpiPower<R>>;
+            o.col_psf = &col<ModePsf<R>>;
+            o.col_filth = &col<ModeFilterH<R>>;
+            o.col_filtl = &col<ModeFilterL<R>>;
         }
         return o;
     }
 };
+
+// Solver passes exist for images up to 8192 wide; the unpadded forward
+// transform (PSF spectra) up to L = 16384.  Combinations whose LDS footprint
+// exceeds a CU's LDS are not built.
+template <typename R, bool PADDED>
+const Ops<R>* table() {
+    constexpr int ES = (int)sizeof(cplx<R>);
+    if constexpr (!fits_lds(MSR_L, PADDED, ES)) {
+        return nullptr;
+    } else {
+        constexpr bool full = MSR_L <= 8192;
+        if constexpr (PADDED && !full) {
+            return nullptr;
+        } else {
+            static const Ops<R> o = Inst<R, MSR_L, PADDED>::make(full);
+            return &o;
+        }
+    }
+}
 
 }  // namespace
 
 #define MSR_CAT2(a, b) a##b
 #define MSR_CAT(a, b) MSR_CAT2(a, b)
 
-// Images are at most 8192 wide: the solver passes exist up to L = 8192, the
-// unpadded forward transform (PSF spectra) up to L = 16384.
-const Ops* MSR_CAT(ops_len_, MSR_L)(bool padded) {
-    constexpr bool full = MSR_L <= 8192;
-    if (padded) {
-        if constexpr (full) {
-            static const Ops o = Inst<MSR_L, true>::make(true);
-            return &o;
-        } else {
-            return nullptr;
-        }
-    }
-    static const Ops o = Inst<MSR_L, false>::make(full);
-    return &o;
+const Ops<float>* MSR_CAT(ops_len_f32_, MSR_L)(bool padded) {
+    return padded ? table<float, true>() : table<float, false>();
+}
+const Ops<double>* MSR_CAT(ops_len_f64_, MSR_L)(bool padded) {
+    return padded ? table<double, true>() : table<double, false>();
 }
 
 }  // namespace msr

@@ -5,7 +5,6 @@
 
 namespace msr {
 
-
 // Deterministic final reduction of per-block partials: out[q] = sum_b partials[b*NQ + q].
 __global__ void __launch_bounds__(256) finalize_sums(const double* __restrict__ partials, int nblocks, int nq,
                                                      double* __restrict__ out) {
@@ -22,28 +21,29 @@ __global__ void __launch_bounds__(256) finalize_sums(const double* __restrict__ 
 }
 
 // PSF spectrum extraction: reads the complex forward spectrum (tiled with width
-// TS, P rows), writes Re/P^2 tiled with width T (P rows), and per-block
-// partials (max |Re|, max |Im|) plus the per-column max |Re|.
-__global__ void __launch_bounds__(256) psf_extract(const float2* __restrict__ spec, int TS, int P, int T, int ncols,
-                                                   float* __restrict__ hh, float* __restrict__ colmax,
+// TS, P rows), writes Re/P^2 tiled with width T (P rows), the per-column max
+// |Re| and per-block partials (max |Re|, max |Im|).  One block per column.
+template <typename R>
+__global__ void __launch_bounds__(256) psf_extract(const cplx<R>* __restrict__ spec, int TS, int P, int T,
+                                                   R* __restrict__ hh, double* __restrict__ colmax,
                                                    double* __restrict__ partials) {
-    // one block per column kx
     const int kx = blockIdx.x;
-    __shared__ float mr[256], mi[256];
-    float ar = 0.f, ai = 0.f;
+    __shared__ double mr[256], mi[256];
+    double ar = 0.0, ai = 0.0;
+    const R inv = (R)(1.0 / ((double)P * (double)P));
     for (int ky = threadIdx.x; ky < P; ky += 256) {
-        const float2 v = spec[((size_t)(kx / TS) * P + ky) * TS + kx % TS];
-        ar = fmaxf(ar, fabsf(v.x));
-        ai = fmaxf(ai, fabsf(v.y));
-        hh[((size_t)(kx / T) * P + ky) * T + kx % T] = v.x / ((float)P * (float)P);
+        const cplx<R> v = spec[((size_t)(kx / TS) * P + ky) * TS + kx % TS];
+        ar = fmax(ar, fabs((double)v.x));
+        ai = fmax(ai, fabs((double)v.y));
+        hh[((size_t)(kx / T) * P + ky) * T + kx % T] = v.x * inv;
     }
     mr[threadIdx.x] = ar;
     mi[threadIdx.x] = ai;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
-            mr[threadIdx.x] = fmaxf(mr[threadIdx.x], mr[threadIdx.x + s]);
-            mi[threadIdx.x] = fmaxf(mi[threadIdx.x], mi[threadIdx.x + s]);
+            mr[threadIdx.x] = fmax(mr[threadIdx.x], mr[threadIdx.x + s]);
+            mi[threadIdx.x] = fmax(mi[threadIdx.x], mi[threadIdx.x + s]);
         }
         __syncthreads();
     }
@@ -52,19 +52,20 @@ __global__ void __launch_bounds__(256) psf_extract(const float2* __restrict__ sp
         partials[2 * kx] = mr[0];
         partials[2 * kx + 1] = mi[0];
     }
-    (void)ncols;
 }
 
-// Zero the columns [c0, c1) of a tiled P-row float layout (tile tail of hh).
-__global__ void zero_hh_cols(float* __restrict__ hh, int P, int T, int c0, int c1) {
+// Zero the columns [c0, c1) of a tiled P-row layout (tile tail of hh).
+template <typename R>
+__global__ void zero_hh_cols(R* __restrict__ hh, int P, int T, int c0, int c1) {
     const int ky = blockIdx.x * blockDim.x + threadIdx.x;
     if (ky >= P) return;
-    for (int kx = c0; kx < c1; ++kx) hh[((size_t)(kx / T) * P + ky) * T + kx % T] = 0.f;
+    for (int kx = c0; kx < c1; ++kx) hh[((size_t)(kx / T) * P + ky) * T + kx % T] = (R)0;
 }
 
 // Image reductions (FP64 partials, one per block):
 //   mode 0: sum |x|          mode 1: sum x^2         mode 2: sum (x - y)^2
-__global__ void __launch_bounds__(256) image_sums(const float* __restrict__ x, const float* __restrict__ y, size_t n,
+template <typename R>
+__global__ void __launch_bounds__(256) image_sums(const R* __restrict__ x, const R* __restrict__ y, size_t n,
                                                   int mode, double* __restrict__ partials) {
     __shared__ double red[4];
     double s = 0.0;
@@ -84,33 +85,36 @@ __global__ void __launch_bounds__(256) image_sums(const float* __restrict__ x, c
 }
 
 // out = a*x + b*y  (y may be null)
-__global__ void image_axpby(float* __restrict__ out, const float* __restrict__ x, const float* __restrict__ y,
-                            float a, float b, size_t n) {
+template <typename R>
+__global__ void image_axpby(R* __restrict__ out, const R* __restrict__ x, const R* __restrict__ y, R a, R b,
+                            size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float v = a * x[i];
-    if (y) v = fmaf(b, y[i], v);
+    R v = a * x[i];
+    if (y) v = fmaR(b, y[i], v);
     out[i] = v;
 }
 
 // Power-iteration start vector: v[n] = splitmix64_mix(seed + n) * 2^-64 - 1/2,
-// taking the top 53 bits for an exact double, then rounding to float.
+// taking the top 53 bits for an exact double, then rounding to R.
 __device__ __forceinline__ unsigned long long splitmix64_mix(unsigned long long c) {
     unsigned long long z = c + 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
-__global__ void start_vector(float* __restrict__ v, unsigned long long seed, size_t n) {
+template <typename R>
+__global__ void start_vector(R* __restrict__ v, unsigned long long seed, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const unsigned long long z = splitmix64_mix(seed + (unsigned long long)i);
-    v[i] = (float)((double)(z >> 11) * 0x1.0p-53 - 0.5);
+    v[i] = (R)((double)(z >> 11) * 0x1.0p-53 - 0.5);
 }
 
 // sigma2_hat: mean over all 5x5 windows inside the image of the population
 // variance.  One thread per window top-left corner; FP64 accumulation.
-__global__ void __launch_bounds__(256) window_variance(const float* __restrict__ img, int n,
+template <typename R>
+__global__ void __launch_bounds__(256) window_variance(const R* __restrict__ img, int n,
                                                        double* __restrict__ partials) {
     __shared__ double red[4];
     const int m = n - 4;  // windows per axis

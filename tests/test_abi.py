@@ -58,12 +58,18 @@ def test_workspace_bytes_host_only(lib):
     assert binding.workspace_bytes(12) == 0  # not a power of two
     assert binding.workspace_bytes(16384) == 0  # above the maximum
     assert binding.workspace_bytes(256, pad=3) == 0
+    # double precision: twice the bytes; zero padded up to 4096, circular up to 8192
+    assert binding.workspace_bytes(256, precision=64) > 1.9 * b
+    assert binding.workspace_bytes(4096, precision=64) > 0
+    assert binding.workspace_bytes(8192, precision=64) == 0
+    assert binding.workspace_bytes(8192, pad=1, precision=64) > 0
+    assert binding.workspace_bytes(256, precision=16) == 0
 
 
 def test_init_rejects_bad_config_before_touching_a_device(lib):
     from paper_2406_18356_amd import binding
 
-    cfg = binding.Config(12, 2, 0, 0, 0, 1e-6)
+    cfg = binding.Config(12, 2, 0, 0, 0, 1e-6, 32, 0)
     h = C.c_void_p(1)
     assert lib.msr_init(C.byref(cfg), C.byref(h)) == binding.ERR_INVALID
     assert not h.value
