@@ -91,6 +91,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--ttt-ref-iters", type=int, default=4000)
+    ap.add_argument("--kernels-only", type=int, default=0, metavar="K",
+                    help="profiling aid: set up the workload, autotune, run K iterations of each step and exit")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 (the multi-GPU layout is "
@@ -111,7 +113,22 @@ def main(argv=None):
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
     tensors = (T(pr.dirty_L), T(pr.psf_L), T(pr.dirty_H), T(pr.psf_H))
     s = Solver(pr.n, pad=2, positivity=True, prune_tol=1e-6)
+    s.set_dirty_psf(1, tensors[0], tensors[1])
+    s.set_dirty_psf(2, tensors[2], tensors[3])
+    tuned = s.autotune(reps=20)
+    log("autotune (row variant, column variant, {variant: (col ms, row ms)}):", tuned)
     torch.cuda.synchronize()
+    if args.kernels_only:
+        s.lipschitz(1)
+        b1, iL, r1 = s.step1(s.default_lambda(1, 1, 0.05), args.kernels_only, image=True)
+        sig2 = s.estimate_sigma2(tensors[2])
+        s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        s.lipschitz(2)
+        b2, r2 = s.step2(s.default_lambda(2, 1, 0.05), iL, args.kernels_only)
+        torch.cuda.synchronize()
+        log(f"kernels-only: step1 {r1.elapsed_ms / max(r1.iters, 1) * 1e3:.1f} us/it, "
+            f"step2 {r2.elapsed_ms / max(r2.iters, 1) * 1e3:.1f} us/it")
+        return 0
 
     for w in range(args.warmup):
         two_step(s, dev, tensors, pr, iters, torch)

@@ -180,6 +180,20 @@ msr_status msr_estimate_sigma2(msr_ctx* ctx, const void* dirty, double* sigma2, 
  * App. A.2), from the dirty image set for step s. */
 msr_status msr_default_lambda(msr_ctx* ctx, int step, int cycle, double c, double* lambda, void* stream);
 
+#define MSR_MAX_VARIANTS 4
+
+/* Picks, by timing, the kernel variant (elements per thread, hence radix
+ * schedule and LDS footprint) of the column pass and of the fused row pass for
+ * this context's size, using the step-1 PSF set with msr_set_dirty_psf: each
+ * built variant is run `reps` times and the fastest kept.  Results of later
+ * solves differ from the default variant's only by rounding.  Writes the
+ * chosen variants (0 = default) to *row_variant / *col_variant and, if
+ * times_ms is not NULL, the mean times in ms to times_ms[2*v] (column pass)
+ * and times_ms[2*v + 1] (row pass) for v < MSR_MAX_VARIANTS (-1: not built).
+ * Any output pointer may be NULL. */
+msr_status msr_autotune(msr_ctx* ctx, int reps, int* row_variant, int* col_variant, double* times_ms,
+                        void* stream);
+
 /* Runs one kernel of the iteration `reps` times back to back on `stream` and
  * returns its mean device time in milliseconds, plus the algorithmic bytes one
  * launch moves.  which: 0 = column convolution pass, 1 = residual row pass,

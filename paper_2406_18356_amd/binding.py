@@ -87,6 +87,7 @@ SYMBOLS = {
     "msr_estimate_sigma2": (_ST, [_P, _P, C.POINTER(C.c_double), _P]),
     "msr_default_lambda": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), _P]),
     "msr_time_pass": (_ST, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]),
+    "msr_autotune": (_ST, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double), _P]),
 }
 
 _lib = None
@@ -262,6 +263,15 @@ class Solver:
         v = C.c_double()
         self._check(self._lib.msr_default_lambda(self._h, step, cycle, float(c), C.byref(v), _stream(stream)))
         return v.value
+
+    def autotune(self, reps=10, stream=None):
+        """Returns (row variant, column variant, {variant: (column ms, row ms)})."""
+        vr = C.c_int()
+        vc = C.c_int()
+        t = (C.c_double * 8)()
+        self._check(self._lib.msr_autotune(self._h, reps, C.byref(vr), C.byref(vc), t, _stream(stream)))
+        times = {v: (t[2 * v], t[2 * v + 1]) for v in range(4) if t[2 * v] >= 0}
+        return vr.value, vc.value, times
 
     def time_pass(self, which, reps=20, stream=None):
         ms = C.c_double()

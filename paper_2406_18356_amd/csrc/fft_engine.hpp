@@ -1,7 +1,7 @@
 // fft_engine.hpp -- register/LDS radix-16 Stockham FFT building blocks for gfx950.
 //
 // A length-L complex FFT is computed cooperatively by TPF = L/E threads, each
-// holding E elements in registers (E = 16 in single precision, 8 in double).
+// holding E elements in registers (E = 16 or 8, chosen per kernel variant).
 // Thread t holds element t + m*TPF in register m on entry and the output bin
 // t + m*TPF on exit, so a forward transform followed by a pointwise multiply
 // and an inverse transform needs no reordering: the inverse's first stage
@@ -132,24 +132,19 @@ struct LdsView {
 
 __host__ __device__ constexpr int padded_len(int L) { return L + L / 16; }
 
-// Elements per thread: 16 complex in single precision, 8 in double.
-template <int L, typename C>
-__host__ __device__ constexpr int elems_per_thread() {
-    constexpr int EMAX = std::is_same_v<C, float2> ? 16 : 8;
-    return L >= EMAX ? EMAX : L;
-}
+// Elements per thread for a transform of length L when at most EMAX are wanted.
+__host__ __device__ constexpr int elems_per_thread(int L, int EMAX) { return L >= EMAX ? EMAX : L; }
 
-// The register array of NH transforms held by one thread.
-template <int L, int NH, typename C>
-using RegArr = C[NH][elems_per_thread<L, C>()];
+// The register array of NH transforms held by one thread (E elements each).
+template <int NH, int E, typename C>
+using RegArr = C[NH][E];
 
 // One Stockham stage on NH arrays at once.  Butterfly b of thread t owns the
 // register slots b + r*NB (r < RD), so results go back into the same slots
 // (last stage) or straight to LDS (other stages): no second register copy.
-template <int L, int NS, bool INV, int TWS, int NH, int S, typename C>
-__device__ __forceinline__ void fft_stage(RegArr<L, NH, C>& v, const LdsView<S, C> (&lds)[NH], int t,
+template <int L, int E, int NS, bool INV, int TWS, int NH, int S, typename C>
+__device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
                                           const C* __restrict__ tw) {
-    constexpr int E = elems_per_thread<L, C>();
     constexpr int TPF = L / E;
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
     constexpr int NB = E / RD;
@@ -193,22 +188,21 @@ __device__ __forceinline__ void fft_stage(RegArr<L, NH, C>& v, const LdsView<S, 
     }
 }
 
-template <int L, int NS, bool INV, int TWS, int NH, int S, typename C>
-__device__ __forceinline__ void fft_from(RegArr<L, NH, C>& v, const LdsView<S, C> (&lds)[NH], int t,
+template <int L, int E, int NS, bool INV, int TWS, int NH, int S, typename C>
+__device__ __forceinline__ void fft_from(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
                                          const C* __restrict__ tw) {
-    constexpr int E = elems_per_thread<L, C>();
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
-    fft_stage<L, NS, INV, TWS, NH, S, C>(v, lds, t, tw);
-    if constexpr (NS * RD < L) fft_from<L, NS * RD, INV, TWS, NH, S, C>(v, lds, t, tw);
+    fft_stage<L, E, NS, INV, TWS, NH, S, C>(v, lds, t, tw);
+    if constexpr (NS * RD < L) fft_from<L, E, NS * RD, INV, TWS, NH, S, C>(v, lds, t, tw);
 }
 
 // Full transform of NH arrays (unnormalised; INV uses conjugate twiddles).
 // tw: the table of exp(-2 pi i k / (TWS * L)).  The caller must have a barrier
 // between any earlier use of the LDS views and this call.
-template <int L, bool INV, int TWS, int NH, int S, typename C>
-__device__ __forceinline__ void fft(RegArr<L, NH, C>& v, const LdsView<S, C> (&lds)[NH], int t,
+template <int L, int E, bool INV, int TWS, int NH, int S, typename C>
+__device__ __forceinline__ void fft(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
                                     const C* __restrict__ tw) {
-    fft_from<L, 1, INV, TWS, NH, S, C>(v, lds, t, tw);
+    fft_from<L, E, 1, INV, TWS, NH, S, C>(v, lds, t, tw);
 }
 
 // ---------------------------------------------------------------------------

@@ -27,10 +27,10 @@
 
 namespace msr {
 
-template <int L, bool PADDED, typename R>
+template <int L, bool PADDED, typename R, int EMAX>
 struct LineCfg {
     using C = cplx<R>;
-    static constexpr int E = elems_per_thread<L, C>();
+    static constexpr int E = elems_per_thread(L, EMAX);
     static constexpr int TPF = L / E;               // threads per line (pair of rows) / per column
     static constexpr int NH = PADDED ? 2 : 1;       // half transforms per line
     static constexpr int PT = PADDED ? 2 * L : L;   // logical transform length P
@@ -60,10 +60,23 @@ struct RowArgs {
     int reduce;                      // accumulate the epilogue's FP64 sums
 };
 
-template <typename R, int L, bool PADDED, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
-__global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R>::TPF))
+// Waves per SIMD the register allocation is made for: what the LDS footprint
+// of the variant allows (2 with 16 complex per thread, 4 with 8 or fewer).
+template <int EMAX, typename R>
+constexpr int waves_per_eu() {
+    return (EMAX * (int)sizeof(cplx<R>)) >= 128 ? 2 : 4;
+}
+#ifdef MSR_WAVES_PER_EU
+#define MSR_WAVES_ATTR(EMAX, R) __attribute__((amdgpu_waves_per_eu(waves_per_eu<EMAX, R>())))
+#else
+#define MSR_WAVES_ATTR(EMAX, R)
+#endif
+
+template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
+__global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R, EMAX>::TPF))
+MSR_WAVES_ATTR(EMAX, R)
 row_kernel(RowArgs<R> a, Epi epi) {
-    using Cf = LineCfg<L, PADDED, R>;
+    using Cf = LineCfg<L, PADDED, R, EMAX>;
     using C = cplx<R>;
     constexpr int E = Cf::E, TPF = Cf::TPF, NH = Cf::NH, PT = Cf::PT, HALF = Cf::HALF;
     constexpr int ZLEN = padded_len(PT);
@@ -143,7 +156,7 @@ row_kernel(RowArgs<R> a, Epi epi) {
 #pragma unroll
             for (int h = 0; h < NH; ++h) v[h][m] = zv[NH * (t + m * TPF) + h];
         __syncthreads();
-        fft<L, true, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
+        fft<L, E, true, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             C s = v[0][m];
@@ -168,31 +181,40 @@ row_kernel(RowArgs<R> a, Epi epi) {
             if constexpr (PADDED) v[1][m] = cmul(z[m], a.tw[t + m * TPF]);
         }
         __syncthreads();
-        fft<L, false, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
+        fft<L, E, false, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < E; ++m)
 #pragma unroll
             for (int h = 0; h < NH; ++h) zv[NH * (t + m * TPF) + h] = v[h][m];
         __syncthreads();
+        // Split the packed spectra and store columns [0, K_out) of both rows
+        // (tile tail zero-filled); unrolled over a compile-time item bound.
         const int ntile = (a.K_out + T - 1) / T;
+        const int nitems = ntile * T * PAIRS;
+        constexpr int OMAX = ((HALF + T) / T) * T * PAIRS;
+        constexpr int OPT = (OMAX + NT - 1) / NT;
         const R half = (R)0.5;
-        for (int q = tid; q < ntile * T * PAIRS; q += NT) {
-            const int c = q % T;
-            const int rest = q / T;
-            const int p = rest % PAIRS;
-            const int kx = (rest / PAIRS) * T + c;
-            const int rr = row0 + 2 * p;
-            C xa = mk<C>(zero, zero), xb = xa;
-            if (kx < a.K_out) {
-                const LdsView<1, C> zp{lds + p * ZLEN, 0};
-                const C zk = zp[kx];
-                const C zm = zp[kx == 0 ? 0 : PT - kx];
-                xa = mk<C>(half * (zk.x + zm.x), half * (zk.y - zm.y));
-                xb = mk<C>(half * (zk.y + zm.y), -half * (zk.x - zm.x));
+#pragma unroll
+        for (int u = 0; u < OPT; ++u) {
+            const int q = tid + u * NT;
+            if (q < nitems) {
+                const int c = q % T;
+                const int rest = q / T;
+                const int p = rest % PAIRS;
+                const int kx = (rest / PAIRS) * T + c;
+                const int rr = row0 + 2 * p;
+                C xa = mk<C>(zero, zero), xb = xa;
+                if (kx < a.K_out) {
+                    const LdsView<1, C> zp{lds + p * ZLEN, 0};
+                    const C zk = zp[kx];
+                    const C zm = zp[kx == 0 ? 0 : PT - kx];
+                    xa = mk<C>(half * (zk.x + zm.x), half * (zk.y - zm.y));
+                    xb = mk<C>(half * (zk.y + zm.y), -half * (zk.x - zm.x));
+                }
+                a.spec_out[spec_idx(kx, rr, a.NR, T)] = xa;
+                a.spec_out[spec_idx(kx, rr + 1, a.NR, T)] = xb;
             }
-            a.spec_out[spec_idx(kx, rr, a.NR, T)] = xa;
-            a.spec_out[spec_idx(kx, rr + 1, a.NR, T)] = xb;
         }
     }
 
@@ -345,29 +367,34 @@ struct ColArgs {
     int reduce;  // accumulate the mode's FP64 sums
 };
 
-template <typename R, int L, bool PADDED, int T, class Mode>
-__global__ void __launch_bounds__((T * LineCfg<L, PADDED, R>::TPF))
+// A block transforms CB adjacent columns (CB divides the tile width T): block
+// b covers columns b*CB .. b*CB + CB - 1 of tile (b*CB)/T.
+template <typename R, int L, bool PADDED, int EMAX, int T, int CB, class Mode>
+__global__ void __launch_bounds__((CB * LineCfg<L, PADDED, R, EMAX>::TPF))
+MSR_WAVES_ATTR(EMAX, R)
 col_kernel(ColArgs<R> a, Mode md) {
-    using Cf = LineCfg<L, PADDED, R>;
+    using Cf = LineCfg<L, PADDED, R, EMAX>;
     using C = cplx<R>;
     constexpr int E = Cf::E, TPF = Cf::TPF, NH = Cf::NH;
-    constexpr int NT = T * TPF;
+    constexpr int NT = CB * TPF;
     constexpr int NQ = Mode::NQ;
     constexpr int HL = padded_len(L);
-    __shared__ C lds[NH * T * HL];
+    static_assert(T % CB == 0, "CB must divide T");
+    __shared__ C lds[NH * CB * HL];
     __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
 
     const int tid = threadIdx.x;
-    const int c = tid % T;
-    const int t = tid / T;
-    const int tile = blockIdx.x;
-    const int kx = tile * T + c;
+    const int cl = tid % CB;
+    const int t = tid / CB;
+    const int kx = blockIdx.x * CB + cl;
+    const int tile = kx / T;
+    const int c = kx % T;
     const bool live = kx < a.K;
     const bool red_on = a.reduce != 0;
     const R zero = 0;
-    LdsView<T, C> hv[NH];
+    LdsView<CB, C> hv[NH];
 #pragma unroll
-    for (int h = 0; h < NH; ++h) hv[h] = LdsView<T, C>{lds + h * T * HL, c};
+    for (int h = 0; h < NH; ++h) hv[h] = LdsView<CB, C>{lds + h * CB * HL, cl};
 
     C v[NH][E];
     const size_t base = (size_t)tile * a.NR * T + c;
@@ -382,7 +409,7 @@ col_kernel(ColArgs<R> a, Mode md) {
         v[0][m] = y;
         if constexpr (PADDED) v[1][m] = cmul(y, a.tw[i]);
     }
-    fft<L, false, Cf::TWS, NH, T, C>(v, hv, t, a.tw);
+    fft<L, E, false, Cf::TWS, NH, CB, C>(v, hv, t, a.tw);
 
     double acc[NQ > 0 ? NQ : 1];
 #pragma unroll
@@ -398,7 +425,7 @@ col_kernel(ColArgs<R> a, Mode md) {
 
     if constexpr (Mode::INVERSE) {
         __syncthreads();
-        fft<L, true, Cf::TWS, NH, T, C>(v, hv, t, a.tw);
+        fft<L, E, true, Cf::TWS, NH, CB, C>(v, hv, t, a.tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int i = t + m * TPF;
@@ -438,28 +465,42 @@ struct ModePsf {
     }
 };
 
-__device__ __forceinline__ float sinR(float x) { return sinf(x); }
-__device__ __forceinline__ double sinR(double x) { return sin(x); }
 __device__ __forceinline__ float sqrtR(float x) { return sqrtf(x); }
 __device__ __forceinline__ double sqrtR(double x) { return sqrt(x); }
 
-// Filter responses of Eqs. 6-10 (squared), evaluated per DFT cell.
+// sin(x) for |x| <= pi/2.  Single precision: the Taylor series through x^11
+// (truncation below 6e-8 on that interval, about one ulp); double precision:
+// the library sine.
+__device__ __forceinline__ float sin_half_pi(float x) {
+    const float x2 = x * x;
+    float p = -2.5052108385441720e-08f;          // -1/11!
+    p = fmaf(p, x2, 2.7557319223985893e-06f);    //  1/9!
+    p = fmaf(p, x2, -1.9841269841269841e-04f);   // -1/7!
+    p = fmaf(p, x2, 8.3333333333333333e-03f);    //  1/5!
+    p = fmaf(p, x2, -1.6666666666666667e-01f);   // -1/3!
+    return fmaf(p * x2, x, x);
+}
+__device__ __forceinline__ double sin_half_pi(double x) { return sin(x); }
+
+// Filter responses of Eqs. 6-10 (squared), evaluated per DFT cell.  The flat
+// regions are decided on the integer squared radius r2 = kx^2 + ky^2:
+// r > ell + delta  <=>  r2 > hi_r2 = floor((ell + delta)^2), and
+// r < ell - delta  <=>  r2 < lo_r2 = ceil((ell - delta)^2) (0 when ell < delta).
 template <typename R>
 struct FilterCoef {
     R ell, delta, inv_sigma2, inv_eta2, sigma2, eta2, half_pi_over_delta;
+    int hi_r2, lo_r2;  // clamped to [0, 2^31 - 1]; r2 <= P^2 / 2 < 2^31 for P <= 16384
     int P;
-    __device__ __forceinline__ R radius(int kx, int ky) const {
-        const int sy = ky < P / 2 ? ky : ky - P;
-        const int sx = kx < P / 2 ? kx : kx - P;  // kx <= P/2 in the half plane
-        return sqrtR((R)(sx * sx + sy * sy));
-    }
     // returns (gL^2, gH^2)
     __device__ __forceinline__ cplx<R> sq(int kx, int ky) const {
-        const R r = radius(kx, ky);
+        const int sy = ky < P / 2 ? ky : ky - P;
+        const int sx = kx < P / 2 ? kx : kx - P;  // kx <= P/2 in the half plane
+        const int r2 = sx * sx + sy * sy;
         const R zero = 0, one = 1;
-        if (r > ell + delta) return mk<cplx<R>>(zero, inv_sigma2);
-        if (r < ell - delta) return mk<cplx<R>>(inv_eta2, zero);
-        const R s = sinR(half_pi_over_delta * (r - ell));
+        if (r2 > hi_r2) return mk<cplx<R>>(zero, inv_sigma2);
+        if (r2 < lo_r2) return mk<cplx<R>>(inv_eta2, zero);
+        const R r = sqrtR((R)r2);
+        const R s = sin_half_pi(half_pi_over_delta * (r - ell));
         const R lo = (one - s) * (one - s), hi = (one + s) * (one + s);
         const R a2 = one / (sigma2 * hi + eta2 * lo);
         return mk<cplx<R>>(a2 * lo, a2 * hi);

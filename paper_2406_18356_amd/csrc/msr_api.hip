@@ -32,11 +32,12 @@
 #include "small_kernels.hpp"
 
 using namespace msr;
+static_assert(kVariants <= MSR_MAX_VARIANTS, "variant table larger than the ABI's timing array");
 
 namespace msr {
-#define MSR_DECL(Lv)                                       \
-    const Ops<float>* ops_len_f32_##Lv(bool padded);       \
-    const Ops<double>* ops_len_f64_##Lv(bool padded);
+#define MSR_DECL(Lv)                                                \
+    const Ops<float>* ops_len_f32_##Lv(bool padded, int variant);   \
+    const Ops<double>* ops_len_f64_##Lv(bool padded, int variant);
 MSR_DECL(8)
 MSR_DECL(16)
 MSR_DECL(32)
@@ -53,22 +54,22 @@ MSR_DECL(16384)
 
 #define MSR_CASES(pfx)                                   \
     switch (L) {                                         \
-        case 8: return pfx##8(padded);                   \
-        case 16: return pfx##16(padded);                 \
-        case 32: return pfx##32(padded);                 \
-        case 64: return pfx##64(padded);                 \
-        case 128: return pfx##128(padded);               \
-        case 256: return pfx##256(padded);               \
-        case 512: return pfx##512(padded);               \
-        case 1024: return pfx##1024(padded);             \
-        case 2048: return pfx##2048(padded);             \
-        case 4096: return pfx##4096(padded);             \
-        case 8192: return pfx##8192(padded);             \
-        case 16384: return pfx##16384(padded);           \
+        case 8: return pfx##8(padded, variant);                   \
+        case 16: return pfx##16(padded, variant);                 \
+        case 32: return pfx##32(padded, variant);                 \
+        case 64: return pfx##64(padded, variant);                 \
+        case 128: return pfx##128(padded, variant);               \
+        case 256: return pfx##256(padded, variant);               \
+        case 512: return pfx##512(padded, variant);               \
+        case 1024: return pfx##1024(padded, variant);             \
+        case 2048: return pfx##2048(padded, variant);             \
+        case 4096: return pfx##4096(padded, variant);             \
+        case 8192: return pfx##8192(padded, variant);             \
+        case 16384: return pfx##16384(padded, variant);           \
         default: return nullptr;                         \
     }
-const Ops<float>* ops_for_f32(int L, bool padded) { MSR_CASES(ops_len_f32_) }
-const Ops<double>* ops_for_f64(int L, bool padded) { MSR_CASES(ops_len_f64_) }
+const Ops<float>* ops_for_f32(int L, bool padded, int variant) { MSR_CASES(ops_len_f32_) }
+const Ops<double>* ops_for_f64(int L, bool padded, int variant) { MSR_CASES(ops_len_f64_) }
 #undef MSR_CASES
 }  // namespace msr
 
@@ -98,8 +99,8 @@ bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 template <typename R>
 bool tables(int N, int P, bool padded, int& T, int& Tpsf) {
-    const Ops<R>* o = ops_for<R>(N, padded);
-    const Ops<R>* op = ops_for<R>(P, false);
+    const Ops<R>* o = ops_for<R>(N, padded, 0);
+    const Ops<R>* op = ops_for<R>(P, false, 0);
     if (!o || !op || !o->row_update_fwd || !op->col_forward) return false;
     T = o->T;
     Tpsf = op->T;
@@ -191,6 +192,7 @@ struct msr_ctx {
     double theta[2] = {0, 0};
     double ell = 0, delta = 0, sigma2 = 0, eta2 = 0;
     int KL = 0;  // columns with g_L != 0
+    int var_row[2] = {0, 0}, var_col[2] = {0, 0};  // kernel variants per step (autotuned)
     std::string err;
 };
 
@@ -234,11 +236,22 @@ template <typename R>
 struct Impl {
     using C = cplx<R>;
     msr_ctx* c;
-    const Ops<R>* op;   // N-length passes (padded or circular)
-    const Ops<R>* opp;  // P-length unpadded (PSF spectrum)
+    const Ops<R>* opr_[2];  // N-length row passes per step (padded or circular)
+    const Ops<R>* opc_[2];  // N-length column passes per step
+    const Ops<R>* opp;      // P-length unpadded (PSF spectrum)
 
-    explicit Impl(msr_ctx* ctx)
-        : c(ctx), op(ops_for<R>(ctx->sh.N, ctx->sh.padded)), opp(ops_for<R>(ctx->sh.P, false)) {}
+    static const Ops<R>* variant_or_default(int L, bool padded, int v) {
+        const Ops<R>* o = ops_for<R>(L, padded, v);
+        return (o && o->row_update_fwd) ? o : ops_for<R>(L, padded, 0);
+    }
+    explicit Impl(msr_ctx* ctx) : c(ctx), opp(ops_for<R>(ctx->sh.P, false, 0)) {
+        for (int s = 0; s < 2; ++s) {
+            opr_[s] = variant_or_default(ctx->sh.N, ctx->sh.padded, ctx->var_row[s]);
+            opc_[s] = variant_or_default(ctx->sh.N, ctx->sh.padded, ctx->var_col[s]);
+        }
+    }
+    const Ops<R>* opr(int step) const { return opr_[step - 1]; }
+    const Ops<R>* opc(int step) const { return opc_[step - 1]; }
 
     template <typename X>
     X* at(size_t off) const { return reinterpret_cast<X*>(c->ws + off); }
@@ -266,6 +279,9 @@ struct Impl {
         f.sigma2 = (R)c->sigma2;
         f.eta2 = (R)c->eta2;
         f.half_pi_over_delta = (R)(M_PI / (2.0 * c->delta));
+        const double hi = c->ell + c->delta, lo = c->ell - c->delta;
+        f.hi_r2 = (long long)std::floor(hi * hi);
+        f.lo_r2 = lo > 0 ? (long long)std::ceil(lo * lo) : 0;
         f.P = c->sh.P;
         return f;
     }
@@ -297,8 +313,8 @@ struct Impl {
         a.reduce = reduce ? 1 : 0;
         return a;
     }
-    int row_grid() const { return N() / op->row_rows; }
-    int col_grid(int K) const { return (K + c->sh.T - 1) / c->sh.T; }
+    int row_grid(int step) const { return N() / opr(step)->row_rows; }
+    int col_grid(int step, int K) const { return (K + opc(step)->col_cb - 1) / opc(step)->col_cb; }
     int KA(int step) const { return step == 1 ? c->K[0] : std::max(c->K[1], c->KL); }
 
     // Sum `nq` quantities over `nblocks` partial rows into scal[off..]; copies them to host.
@@ -321,24 +337,24 @@ struct Impl {
     }
 
     // image -> row spectrum
-    msr_status fwd_image(const R* img, R scale, C* out, int kout, hipStream_t s) {
-        op->row_load_fwd(row_args(nullptr, 0, nullptr, 0, out, kout), EpiLoad<R>{img, N(), scale}, s);
+    msr_status fwd_image(int step, const R* img, R scale, C* out, int kout, hipStream_t s) {
+        opr(step)->row_load_fwd(row_args(nullptr, 0, nullptr, 0, out, kout), EpiLoad<R>{img, N(), scale}, s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
 
     msr_status col_psf(int step, const C* in, C* out, hipStream_t s) {
-        op->col_psf(col_args(in, nullptr, out, c->K[step - 1]), ModePsf<R>{hh(step), P(), c->sh.T}, s);
+        opc(step)->col_psf(col_args(in, nullptr, out, c->K[step - 1]), ModePsf<R>{hh(step), P(), c->sh.T}, s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
     msr_status col_filth(const C* in, C* out, bool red, hipStream_t s) {
-        op->col_filth(col_args(in, nullptr, out, c->sh.Cfull, red), ModeFilterH<R>{filters(), inv_p2()}, s);
+        opc(2)->col_filth(col_args(in, nullptr, out, c->sh.Cfull, red), ModeFilterH<R>{filters(), inv_p2()}, s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
     msr_status col_filtl(const C* in, const C* in2, C* out, bool red, hipStream_t s) {
-        op->col_filtl(col_args(in, in2, out, c->KL, red), ModeFilterL<R>{filters(), inv_p2()}, s);
+        opc(2)->col_filtl(col_args(in, in2, out, c->KL, red), ModeFilterL<R>{filters(), inv_p2()}, s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
@@ -351,11 +367,11 @@ struct Impl {
         const int Ks = c->K[step - 1];
         TRY(col_psf(step, SA(), SB(), s));
         const int kr = step == 1 ? Ks : c->sh.Cfull;
-        op->row_resid_fwd(row_args(SB(), Ks, nullptr, 0, SC(), kr), EpiResid<R>{y, nullptr, N()}, s);
+        opr(step)->row_resid_fwd(row_args(SB(), Ks, nullptr, 0, SC(), kr), EpiResid<R>{y, nullptr, N()}, s);
         LAUNCHCHK(c);
         if (step == 1) return col_psf(1, SC(), SB(), s);
         TRY(col_filth(SC(), SB(), false, s));
-        op->row_resid_fwd(row_args(SB(), c->sh.Cfull, nullptr, 0, SC(), Ks), EpiResid<R>{nullptr, nullptr, N()}, s);
+        opr(step)->row_resid_fwd(row_args(SB(), c->sh.Cfull, nullptr, 0, SC(), Ks), EpiResid<R>{nullptr, nullptr, N()}, s);
         LAUNCHCHK(c);
         TRY(col_psf(2, SC(), SB(), s));
         return col_filtl(SA(), use_l ? SL() : nullptr, SC(), false, s);
@@ -378,7 +394,7 @@ struct Impl {
         const int Ks = c->K[step - 1];
         RowArgs<R> a = step == 1 ? row_args(SB(), Ks, nullptr, 0, SA(), KA(1))
                                  : row_args(SB(), Ks, SC(), c->KL, SA(), KA(2));
-        op->row_update_fwd(a, u, s);
+        opr(step)->row_update_fwd(a, u, s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
@@ -388,22 +404,22 @@ struct Impl {
     msr_status objective_at(int step, double lambda, const R* x, double out[3], hipStream_t s) {
         double data = 0.0;
         if (step == 1) {
-            TRY(fwd_image(x, (R)1, SB(), c->K[0], s));
+            TRY(fwd_image(1, x, (R)1, SB(), c->K[0], s));
             TRY(col_psf(1, SB(), SC(), s));
-            op->row_resid(row_args(SC(), c->K[0], nullptr, 0, nullptr, 0, true), EpiResid<R>{dirty(1), nullptr, N()}, s);
+            opr(1)->row_resid(row_args(SC(), c->K[0], nullptr, 0, nullptr, 0, true), EpiResid<R>{dirty(1), nullptr, N()}, s);
             LAUNCHCHK(c);
-            TRY(reduce(row_grid(), 1, 0, &data, s));
+            TRY(reduce(row_grid(1), 1, 0, &data, s));
         } else {
             double dh = 0.0, dl = 0.0;
-            TRY(fwd_image(x, (R)1, SB(), KA(2), s));
+            TRY(fwd_image(2, x, (R)1, SB(), KA(2), s));
             TRY(col_psf(2, SB(), SC(), s));
-            op->row_resid_fwd(row_args(SC(), c->K[1], nullptr, 0, SC(), c->sh.Cfull),
+            opr(2)->row_resid_fwd(row_args(SC(), c->K[1], nullptr, 0, SC(), c->sh.Cfull),
                               EpiResid<R>{dirty(2), nullptr, N()}, s);
             LAUNCHCHK(c);
             TRY(col_filth(SC(), SC(), true, s));
-            TRY(reduce(col_grid(c->sh.Cfull), 1, 0, &dh, s));
+            TRY(reduce(col_grid(2, c->sh.Cfull), 1, 0, &dh, s));
             TRY(col_filtl(SB(), SL(), SC(), true, s));
-            TRY(reduce(col_grid(c->KL), 1, 0, &dl, s));
+            TRY(reduce(col_grid(2, c->KL), 1, 0, &dl, s));
             data = (dh + dl) / ((double)P() * (double)P());
         }
         double l1 = 0.0;
@@ -414,7 +430,7 @@ struct Impl {
         return MSR_OK;
     }
 
-    msr_status set_low_res(const R* low_res, hipStream_t s) { return fwd_image(low_res, (R)1, SL(), c->KL, s); }
+    msr_status set_low_res(const R* low_res, hipStream_t s) { return fwd_image(2, low_res, (R)1, SL(), c->KL, s); }
 
     msr_status power_iteration(int step, int max_iter, double rtol, double* theta_out, int* iters_out, hipStream_t s) {
         const size_t n = c->sh.img_elems;
@@ -429,15 +445,15 @@ struct Impl {
         double theta = 0.0, prev = -1.0;
         int j = 0;
         for (j = 1; j <= max_iter; ++j) {
-            TRY(fwd_image(v, (R)scale, SA(), KA(step), s));
+            TRY(fwd_image(step, v, (R)scale, SA(), KA(step), s));
             TRY(grad_chain(step, nullptr, false, s));
             EpiPower<R> ep{v, w, N(), (R)scale};
             RowArgs<R> a = step == 1 ? row_args(SB(), c->K[0], nullptr, 0, nullptr, 0, true)
                                      : row_args(SB(), c->K[1], SC(), c->KL, nullptr, 0, true);
-            op->row_power(a, ep, s);
+            opr(step)->row_power(a, ep, s);
             LAUNCHCHK(c);
             double sums[2];
-            TRY(reduce(row_grid(), 2, 0, sums, s));
+            TRY(reduce(row_grid(step), 2, 0, sums, s));
             // v has unit norm: theta = 2 <v, A v>
             theta = 2.0 * sums[1];
             if (sums[0] == 0.0) {
@@ -554,7 +570,7 @@ struct Impl {
         }
         HIPCHK(c, hipMemcpyAsync(beta(1), beta(0), nb, hipMemcpyDeviceToDevice, s));
         if (step == 2) TRY(set_low_res(low_res, s));
-        TRY(fwd_image(beta(0), (R)1, SA(), KA(step), s));
+        TRY(fwd_image(step, beta(0), (R)1, SA(), KA(step), s));
 
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
@@ -601,9 +617,9 @@ struct Impl {
         HIPCHK(c, hipMemcpyAsync(model_out, bK, nb, hipMemcpyDeviceToDevice, s));
         if (image_out) {
             // i_L = beta + (i~ - H beta) = beta - r
-            TRY(fwd_image(bK, (R)1, SB(), c->K[step - 1], s));
+            TRY(fwd_image(step, bK, (R)1, SB(), c->K[step - 1], s));
             TRY(col_psf(step, SB(), SC(), s));
-            op->row_resid(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0), EpiResid<R>{dirty(step), tmp(0), N()},
+            opr(step)->row_resid(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0), EpiResid<R>{dirty(step), tmp(0), N()},
                           s);
             LAUNCHCHK(c);
             const size_t n = c->sh.img_elems;
@@ -627,20 +643,20 @@ struct Impl {
 
     msr_status gradient(int step, const R* x, const R* low_res, R* g, hipStream_t s) {
         if (step == 2) TRY(set_low_res(low_res, s));
-        TRY(fwd_image(x, (R)1, SA(), KA(step), s));
+        TRY(fwd_image(step, x, (R)1, SA(), KA(step), s));
         TRY(grad_chain(step, dirty(step), true, s));
         RowArgs<R> a = step == 1 ? row_args(SB(), c->K[0], nullptr, 0, nullptr, 0)
                                  : row_args(SB(), c->K[1], SC(), c->KL, nullptr, 0);
-        op->row_store(a, EpiStore<R>{g, N(), (R)2}, s);
+        opr(step)->row_store(a, EpiStore<R>{g, N(), (R)2}, s);
         LAUNCHCHK(c);
         HIPCHK(c, hipStreamSynchronize(s));
         return MSR_OK;
     }
 
     msr_status apply_psf(int step, const R* x, R* out, hipStream_t s) {
-        TRY(fwd_image(x, (R)1, SB(), c->K[step - 1], s));
+        TRY(fwd_image(step, x, (R)1, SB(), c->K[step - 1], s));
         TRY(col_psf(step, SB(), SC(), s));
-        op->row_store(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0), EpiStore<R>{out, N(), (R)1}, s);
+        opr(step)->row_store(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0), EpiStore<R>{out, N(), (R)1}, s);
         LAUNCHCHK(c);
         HIPCHK(c, hipStreamSynchronize(s));
         return MSR_OK;
@@ -671,14 +687,42 @@ struct Impl {
         return MSR_OK;
     }
 
-    msr_status time_pass(int which, int reps, double* ms_out, double* bytes_out, hipStream_t s) {
-        const int Nn = N(), Pn = P(), K = c->K[0];
+    // For each step whose PSF is set, times every built variant of the column
+    // PSF pass and of the fused update row pass on that step's shapes and keeps
+    // the fastest of each.  times[2v], times[2v+1]: step-1 column / row ms.
+    msr_status autotune(int reps, double* times, hipStream_t s) {
+        for (int step = 1; step <= 2; ++step) {
+            if (!c->have_psf[step - 1]) continue;
+            double best_c = 1e30, best_r = 1e30;
+            int vc = 0, vr = 0;
+            for (int v = 0; v < kVariants; ++v) {
+                const Ops<R>* o = ops_for<R>(N(), c->sh.padded, v);
+                if (!o || !o->row_update_fwd) continue;
+                c->var_row[step - 1] = v;
+                c->var_col[step - 1] = v;
+                Impl<R> im(c);
+                double ms = 0.0;
+                TRY(im.time_pass(0, step, reps, &ms, nullptr, s));
+                if (times && step == 1) times[2 * v] = ms;
+                if (ms < best_c) best_c = ms, vc = v;
+                TRY(im.time_pass(2, step, reps, &ms, nullptr, s));
+                if (times && step == 1) times[2 * v + 1] = ms;
+                if (ms < best_r) best_r = ms, vr = v;
+            }
+            c->var_row[step - 1] = vr;
+            c->var_col[step - 1] = vc;
+        }
+        return MSR_OK;
+    }
+
+    msr_status time_pass(int which, int step, int reps, double* ms_out, double* bytes_out, hipStream_t s) {
+        const int Nn = N(), Pn = P(), K = c->K[step - 1];
         const double es = (double)c->sh.cs, rs = (double)c->sh.rs;
         const double spec = (double)Nn * K * es, img = (double)Nn * Nn * rs;
         auto launch = [&]() -> msr_status {
-            if (which == 0) return col_psf(1, SA(), SB(), s);
+            if (which == 0) return col_psf(step, SA(), SB(), s);
             if (which == 1) {
-                op->row_resid_fwd(row_args(SB(), K, nullptr, 0, SC(), K), EpiResid<R>{dirty(1), nullptr, Nn}, s);
+                opr(step)->row_resid_fwd(row_args(SB(), K, nullptr, 0, SC(), K), EpiResid<R>{dirty(step), nullptr, Nn}, s);
                 LAUNCHCHK(c);
                 return MSR_OK;
             }
@@ -687,7 +731,7 @@ struct Impl {
             u.b2 = beta(1);
             u.ld = Nn;
             u.positivity = c->cfg.positivity;
-            op->row_update_fwd(row_args(SB(), K, nullptr, 0, SC(), K), u, s);
+            opr(step)->row_update_fwd(row_args(SB(), K, nullptr, 0, SC(), K), u, s);
             LAUNCHCHK(c);
             return MSR_OK;
         };
@@ -923,10 +967,21 @@ msr_status msr_default_lambda(msr_ctx* c, int step, int cycle, double cc, double
     return MSR_OK;
 }
 
+msr_status msr_autotune(msr_ctx* c, int reps, int* row_variant, int* col_variant, double* times_ms, void* stream) {
+    TRY(check_step(c, 1, false));
+    if (reps <= 0) reps = 10;
+    if (times_ms)
+        for (int i = 0; i < 2 * MSR_MAX_VARIANTS; ++i) times_ms[i] = -1.0;
+    TRY(with_impl(c, [&](auto& im) { return im.autotune(reps, times_ms, S(stream)); }));
+    if (row_variant) *row_variant = c->var_row[0];
+    if (col_variant) *col_variant = c->var_col[0];
+    return MSR_OK;
+}
+
 msr_status msr_time_pass(msr_ctx* c, int which, int reps, double* ms_out, double* bytes_out, void* stream) {
     TRY(check_step(c, 1, false));
     if (reps <= 0 || which < 0 || which > 2) return fail(c, MSR_ERR_INVALID, "bad arguments");
-    return with_impl(c, [&](auto& im) { return im.time_pass(which, reps, ms_out, bytes_out, S(stream)); });
+    return with_impl(c, [&](auto& im) { return im.time_pass(which, 1, reps, ms_out, bytes_out, S(stream)); });
 }
 
 }  // extern "C"

@@ -20,10 +20,14 @@ __host__ __device__ constexpr int tile_width(int L, int esize) {
     return L <= 1024 ? 4 : (L <= 2048 ? 2 : 1);
 }
 
+// Largest number of complex elements a thread holds in a transform (the
+// register / LDS trade-off): 16 in single precision, 8 in double.
+__host__ __device__ constexpr int default_emax(int esize) { return esize == 8 ? 16 : 8; }
+
 // Pairs of rows handled by one row-pass block: about 256 threads, at most
 // ~72 KB of LDS (one pair may use more).
-__host__ __device__ constexpr int row_pairs(int L, bool padded, int esize) {
-    const int E = esize == 8 ? (L >= 16 ? 16 : L) : (L >= 8 ? 8 : L);
+__host__ __device__ constexpr int row_pairs(int L, bool padded, int esize, int emax) {
+    const int E = L >= emax ? emax : L;
     const int TPF = L / E;
     const int PT = padded ? 2 * L : L;
     const int lds_pair = (PT + PT / 16) * esize;
@@ -33,20 +37,37 @@ __host__ __device__ constexpr int row_pairs(int L, bool padded, int esize) {
     return p;
 }
 
-// Whether the passes of a (length, padding, element size) combination fit the
-// 160 KB of LDS of a gfx950 CU.
-__host__ __device__ constexpr bool fits_lds(int L, bool padded, int esize) {
+// Whether the passes of a (length, padding, element size, elements per
+// thread) combination fit the 160 KB of LDS and the 1024-thread block limit.
+__host__ __device__ constexpr bool fits_lds(int L, bool padded, int esize, int emax) {
     const int NH = padded ? 2 : 1;
-    const int col = NH * tile_width(L, esize) * (L + L / 16) * esize;
+    const int E = L >= emax ? emax : L;
+    const int T = tile_width(L, esize);
+    const int col = NH * T * (L + L / 16) * esize;  // the whole-tile column block is the larger one
     const int PT = padded ? 2 * L : L;
-    const int row = row_pairs(L, padded, esize) * (PT + PT / 16) * esize;
-    return col <= 160 * 1024 - 4096 && row <= 160 * 1024 - 4096;
+    const int pairs = row_pairs(L, padded, esize, emax);
+    const int row = pairs * (PT + PT / 16) * esize;
+    return col <= 160 * 1024 - 4096 && row <= 160 * 1024 - 4096 && T * (L / E) <= 1024 && pairs * (L / E) <= 1024;
 }
+
+// Kernel variants per precision: elements per thread (hence radix schedule
+// and LDS per thread) and, for the column pass, whether a block takes a whole
+// tile of T columns or a single column (more, shorter blocks for narrow
+// spectra).  v0: large E, whole tile; v1: small E, whole tile; v2: small E,
+// one column; v3: large E, one column.
+constexpr int kVariants = 4;
+__host__ __device__ constexpr int variant_emax(int esize, int v) {
+    const bool big = (v == 0 || v == 3);
+    return esize == 8 ? (big ? 16 : 8) : (big ? 8 : 4);
+}
+__host__ __device__ constexpr bool variant_single_column(int v) { return v >= 2; }
 
 template <typename R>
 struct Ops {
     int L = 0;
     bool padded = false;
+    int emax = 0;         // elements per thread of this variant
+    int col_cb = 0;       // columns per column-pass block
     int T = 0;            // tile width of the spectra this table reads and writes
     int pairs = 0;        // row pairs per row-pass block
     int row_rows = 0;     // image rows per row-pass block (2 * pairs)
@@ -65,14 +86,14 @@ struct Ops {
     void (*col_forward)(const ColArgs<R>&, const ModeForward<R>&, hipStream_t) = nullptr;  // unpadded forward only
 };
 
-// Tables per line length (L = 8 .. 16384); nullptr where not built.
-const Ops<float>* ops_for_f32(int L, bool padded);
-const Ops<double>* ops_for_f64(int L, bool padded);
+// Tables per line length (L = 8 .. 16384) and variant; nullptr where not built.
+const Ops<float>* ops_for_f32(int L, bool padded, int variant);
+const Ops<double>* ops_for_f64(int L, bool padded, int variant);
 
 template <typename R>
-const Ops<R>* ops_for(int L, bool padded) {
-    if constexpr (std::is_same_v<R, float>) return ops_for_f32(L, padded);
-    else return ops_for_f64(L, padded);
+const Ops<R>* ops_for(int L, bool padded, int variant = 0) {
+    if constexpr (std::is_same_v<R, float>) return ops_for_f32(L, padded, variant);
+    else return ops_for_f64(L, padded, variant);
 }
 
 }  // namespace msr

@@ -9,31 +9,34 @@
 namespace msr {
 namespace {
 
-template <typename R, int L, bool PADDED>
+template <typename R, int L, bool PADDED, int EMAX, bool ONECOL>
 struct Inst {
-    using Cf = LineCfg<L, PADDED, R>;
     static constexpr int ES = (int)sizeof(cplx<R>);
+    using Cf = LineCfg<L, PADDED, R, EMAX>;
     static constexpr int T = tile_width(L, ES);
-    static constexpr int PAIRS = row_pairs(L, PADDED, ES);
+    static constexpr int CB = ONECOL ? 1 : T;
+    static constexpr int PAIRS = row_pairs(L, PADDED, ES, EMAX);
     static constexpr int RT = PAIRS * Cf::TPF;
-    static constexpr int CT = T * Cf::TPF;
+    static constexpr int CT = CB * Cf::TPF;
 
     template <bool INV_IN, bool FWD_OUT, class Epi>
     static void row(const RowArgs<R>& a, const Epi& e, hipStream_t s) {
         const int grid = a.NR / (2 * PAIRS);
-        hipLaunchKernelGGL((row_kernel<R, L, PADDED, PAIRS, T, INV_IN, FWD_OUT, Epi>), dim3(grid), dim3(RT), 0, s, a, e);
+        hipLaunchKernelGGL((row_kernel<R, L, PADDED, EMAX, PAIRS, T, INV_IN, FWD_OUT, Epi>), dim3(grid), dim3(RT), 0, s, a, e);
     }
     template <class Mode>
     static void col(const ColArgs<R>& a, const Mode& m, hipStream_t s) {
-        const int grid = (a.K + T - 1) / T;
+        const int grid = (a.K + CB - 1) / CB;
         if (grid <= 0) return;
-        hipLaunchKernelGGL((col_kernel<R, L, PADDED, T, Mode>), dim3(grid), dim3(CT), 0, s, a, m);
+        hipLaunchKernelGGL((col_kernel<R, L, PADDED, EMAX, T, CB, Mode>), dim3(grid), dim3(CT), 0, s, a, m);
     }
 
     static Ops<R> make(bool full) {
         Ops<R> o;
         o.L = L;
         o.padded = PADDED;
+        o.emax = EMAX;
+        o.col_cb = CB;
         o.T = T;
         o.pairs = PAIRS;
         o.row_rows = 2 * PAIRS;
@@ -61,19 +64,31 @@ struct Inst {
 // Solver passes exist for images up to 8192 wide; the unpadded forward
 // transform (PSF spectra) up to L = 16384.  Combinations whose LDS footprint
 // exceeds a CU's LDS are not built.
-template <typename R, bool PADDED>
+template <typename R, bool PADDED, int V>
 const Ops<R>* table() {
     constexpr int ES = (int)sizeof(cplx<R>);
-    if constexpr (!fits_lds(MSR_L, PADDED, ES)) {
+    constexpr int EMAX = variant_emax(ES, V);
+    if constexpr (!fits_lds(MSR_L, PADDED, ES, EMAX)) {
         return nullptr;
     } else {
         constexpr bool full = MSR_L <= 8192;
         if constexpr (PADDED && !full) {
             return nullptr;
         } else {
-            static const Ops<R> o = Inst<R, MSR_L, PADDED>::make(full);
+            static const Ops<R> o = Inst<R, MSR_L, PADDED, EMAX, variant_single_column(V)>::make(full);
             return &o;
         }
+    }
+}
+
+template <typename R>
+const Ops<R>* pick(bool padded, int variant) {
+    switch (variant) {
+        case 0: return padded ? table<R, true, 0>() : table<R, false, 0>();
+        case 1: return padded ? table<R, true, 1>() : table<R, false, 1>();
+        case 2: return padded ? table<R, true, 2>() : table<R, false, 2>();
+        case 3: return padded ? table<R, true, 3>() : table<R, false, 3>();
+        default: return nullptr;
     }
 }
 
@@ -82,11 +97,7 @@ const Ops<R>* table() {
 #define MSR_CAT2(a, b) a##b
 #define MSR_CAT(a, b) MSR_CAT2(a, b)
 
-const Ops<float>* MSR_CAT(ops_len_f32_, MSR_L)(bool padded) {
-    return padded ? table<float, true>() : table<float, false>();
-}
-const Ops<double>* MSR_CAT(ops_len_f64_, MSR_L)(bool padded) {
-    return padded ? table<double, true>() : table<double, false>();
-}
+const Ops<float>* MSR_CAT(ops_len_f32_, MSR_L)(bool padded, int variant) { return pick<float>(padded, variant); }
+const Ops<double>* MSR_CAT(ops_len_f64_, MSR_L)(bool padded, int variant) { return pick<double>(padded, variant); }
 
 }  // namespace msr
