@@ -28,7 +28,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FISTA iters/s & time-to-1e-6 rel objective at 4096²; warm-start vs cold"
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector peak
+
+
+def traffic_file(kernel, workload):
+    """HBM traffic of one pass measured with rocprofv3 counters (see prof_summary)."""
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
 
 WORKLOADS = {
     2048: ("sky2048", "two-step solve, 2048x2048 image on a 4096x4096 zero-padded grid: 2000 points + 50 "
@@ -54,7 +60,7 @@ def two_step(s, dev, tensors, pr, iters, torch):
     s.lipschitz(2)
     lam2 = s.default_lambda(2, 1, 0.05)
     b2, r2 = s.step2(lam2, iL, iters)
-    return r1, r2, iL, lam2
+    return r1, r2, iL, lam2, b1
 
 
 def cpu_baseline(pr, budget_s=15.0):
@@ -90,13 +96,16 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=None, help="FISTA iterations per step (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
-    ap.add_argument("--ttt-ref-iters", type=int, default=4000)
+    ap.add_argument("--ttt-ref-iters", type=int, default=20000)
+    ap.add_argument("--profile-pass", type=int, nargs=3, default=None, metavar=("STEP", "WHICH", "REPS"),
+                    help="profiling aid: after setup, run only msr_time_pass(STEP, WHICH, REPS) and one "
+                         "64 MiB device copy (counter calibration), then exit")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="K",
                     help="profiling aid: set up the workload, autotune, run K iterations of each step and exit")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 (the multi-GPU layout is "
-              "described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus must be 1 (a multi-GPU split of the "
+              "channels or of the image is not implemented)", file=sys.stderr)
         return 2
 
     import torch
@@ -118,6 +127,22 @@ def main(argv=None):
     tuned = s.autotune(reps=20)
     log("autotune (row variant, column variant, {variant: (col ms, row ms)}):", tuned)
     torch.cuda.synchronize()
+    if args.profile_pass:
+        step, which, reps = args.profile_pass
+        s.lipschitz(1)
+        b1, iL, _ = s.step1(s.default_lambda(1, 1, 0.05), 10, image=True)
+        sig2 = s.estimate_sigma2(tensors[2])
+        s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        s.lipschitz(2)
+        s.step2(s.default_lambda(2, 1, 0.05), iL, 10)
+        src = torch.empty(16 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        ms, by, fl = s.time_pass(which, reps=reps, step=step)
+        torch.cuda.synchronize()
+        log(f"profile-pass step {step} which {which}: {ms * 1e3:.2f} us, {by:.0f} bytes, {fl:.0f} flops")
+        return 0
     if args.kernels_only:
         s.lipschitz(1)
         b1, iL, r1 = s.step1(s.default_lambda(1, 1, 0.05), args.kernels_only, image=True)
@@ -141,36 +166,55 @@ def main(argv=None):
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    r1, r2, iL, lam2 = res
+    r1, r2, iL, lam2, b1 = res
     total_iters = args.steps * 2 * iters
     value = total_iters / el
 
-    # dominant kernel: each pass of a step-1 iteration timed alone (HIP events on the library's stream)
+    # Each pass of an iteration of both steps timed alone (HIP events on the
+    # library's stream); the dominant one is the largest share of an iteration.
+    per_iter = {(1, 0): 2, (1, 1): 1, (1, 2): 1, (2, 0): 2, (2, 1): 2, (2, 2): 1, (2, 3): 1}
+    names = {0: "col_psf", 1: "row_resid", 2: "row_update", 3: "col_filter"}
     passes = {}
-    for which, name, per_iter in ((0, "col_conv", 2), (1, "row_resid", 1), (2, "row_update", 1)):
-        ms, by = s.time_pass(which, reps=50)
-        passes[name] = {"ms": ms, "bytes": by, "per_iter": per_iter, "gbs": by / (ms * 1e-3) / 1e9}
+    for (step, which), cnt in per_iter.items():
+        ms, by, fl = s.time_pass(which, reps=50, step=step)
+        passes[f"{names[which]}_step{step}"] = {
+            "ms": ms, "bytes": by, "flops": fl, "per_iter": cnt,
+            "gbs": by / (ms * 1e-3) / 1e9, "tflops": fl / (ms * 1e-3) / 1e12,
+        }
     dom = max(passes, key=lambda k: passes[k]["ms"] * passes[k]["per_iter"])
     d = passes[dom]
-    roofline = {
-        "bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
-        "bytes_per_launch": d["bytes"], "launch_ms": d["ms"],
-    }
+    hbm_frac = d["gbs"] / HBM_PEAK_GBS
+    alu_frac = d["tflops"] / FP32_VECTOR_TFLOPS
+    traffic = None
+    try:
+        from paper_2406_18356_amd.prof_summary import kernel_source_hash
+
+        rec = json.load(open(traffic_file(dom, preset)))
+        if rec["source_sha256"] == kernel_source_hash():
+            traffic = rec["traffic_bytes"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
+    if alu_frac >= hbm_frac:
+        roofline = {"bound": "alu", "kernel": dom, "achieved": d["tflops"], "peak": FP32_VECTOR_TFLOPS,
+                    "unit": "TFLOP/s", "frac": alu_frac}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": hbm_frac}
+    roofline.update({"traffic": traffic, "algorithmic_bytes": d["bytes"], "algorithmic_flops": d["flops"],
+                     "launch_ms": d["ms"], "hbm_gbs": d["gbs"], "hbm_frac": hbm_frac})
     log("passes:", json.dumps(passes))
 
     ttt = None
     if not args.no_ttt:
-        # F* from a long cold run of step 2 (same problem, same lambda), then cold vs warm to 1e-6
+        # F* from a long cold run of step 2 (same problem and lambda); then the
+        # time to reach (F - F*)/|F*| <= 1e-6 from a cold start and from two
+        # non-learned warm starts: the low-resolution image and the step-1 model.
         _, rref = s.step2(lam2, iL, args.ttt_ref_iters)
         fstar = rref.objective
-        _, rc = s.step2(lam2, iL, args.ttt_ref_iters, check_every=10, tol=1e-6, f_ref=fstar)
-        _, rw = s.step2(lam2, iL, args.ttt_ref_iters, x0=iL, check_every=10, tol=1e-6, f_ref=fstar)
-        ttt = {
-            "tol": 1e-6, "f_star": fstar, "f_star_iters": args.ttt_ref_iters, "check_every": 10,
-            "cold": {"ms": rc.time_to_tol_ms, "iters": rc.iters, "converged": bool(rc.converged)},
-            "low_res_warm": {"ms": rw.time_to_tol_ms, "iters": rw.iters, "converged": bool(rw.converged)},
-        }
+        ttt = {"tol": 1e-6, "f_star": fstar, "f_star_iters": args.ttt_ref_iters, "check_every": 10}
+        for name, x0 in (("cold", None), ("low_res_warm", iL), ("step1_model_warm", b1)):
+            _, rc = s.step2(lam2, iL, args.ttt_ref_iters, x0=x0, check_every=10, tol=1e-6, f_ref=fstar)
+            ttt[name] = {"ms": rc.time_to_tol_ms, "iters": rc.iters, "converged": bool(rc.converged)}
         log("time to tolerance:", json.dumps(ttt))
 
     cpu = None
@@ -195,7 +239,7 @@ def main(argv=None):
                    "parallelism": "none (1 GPU)"},
         "step1_loop_iters_per_s": r1.iters / (r1.elapsed_ms * 1e-3),
         "step2_loop_iters_per_s": r2.iters / (r2.elapsed_ms * 1e-3),
-        "kept_columns": None,
+        "autotune": {"row_variant": tuned[0], "col_variant": tuned[1]},
         "time_to_tol": ttt,
         "roofline": roofline,
         "cpu_baseline": cpu,

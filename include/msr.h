@@ -183,22 +183,28 @@ msr_status msr_default_lambda(msr_ctx* ctx, int step, int cycle, double c, doubl
 #define MSR_MAX_VARIANTS 4
 
 /* Picks, by timing, the kernel variant (elements per thread, hence radix
- * schedule and LDS footprint) of the column pass and of the fused row pass for
- * this context's size, using the step-1 PSF set with msr_set_dirty_psf: each
- * built variant is run `reps` times and the fastest kept.  Results of later
- * solves differ from the default variant's only by rounding.  Writes the
- * chosen variants (0 = default) to *row_variant / *col_variant and, if
- * times_ms is not NULL, the mean times in ms to times_ms[2*v] (column pass)
- * and times_ms[2*v + 1] (row pass) for v < MSR_MAX_VARIANTS (-1: not built).
- * Any output pointer may be NULL. */
+ * schedule and LDS footprint) of the column PSF pass and of the fused row pass
+ * of each step whose PSF is set with msr_set_dirty_psf, and, once the filters
+ * are set, of the step-2 low-band filter pass: each built variant is run
+ * `reps` times and the fastest kept.  Results of later solves differ from the
+ * default variant's only by rounding.  Writes the step-1 choices (0 = default)
+ * to *row_variant / *col_variant and, if times_ms is not NULL, the step-1 mean
+ * times in ms to times_ms[2*v] (column pass) and times_ms[2*v + 1] (row pass)
+ * for v < MSR_MAX_VARIANTS (-1: not built).  Any output pointer may be NULL. */
 msr_status msr_autotune(msr_ctx* ctx, int reps, int* row_variant, int* col_variant, double* times_ms,
                         void* stream);
 
-/* Runs one kernel of the iteration `reps` times back to back on `stream` and
- * returns its mean device time in milliseconds, plus the algorithmic bytes one
- * launch moves.  which: 0 = column convolution pass, 1 = residual row pass,
- * 2 = fused update row pass (step 1 shapes, current state).  For measurement. */
-msr_status msr_time_pass(msr_ctx* ctx, int which, int reps, double* ms, double* bytes, void* stream);
+/* Runs one kernel of an iteration of step s `reps` times back to back on
+ * `stream` (on the context's current state, which it overwrites: call it
+ * outside a solve) and returns its mean device time in milliseconds, plus the
+ * algorithmic bytes and flops one launch moves / performs.  which: 0 = column
+ * PSF pass, 1 = residual row pass, 2 = fused update row pass, 3 = step-2
+ * low-band filter pass (C_w and C_{g_L^2}, Eq. 12; step 2 only, filters
+ * set).  Flops count
+ * 5 n log2 n per complex transform of length P.  Any output may be NULL.  For
+ * measurement. */
+msr_status msr_time_pass(msr_ctx* ctx, int step, int which, int reps, double* ms, double* bytes, double* flops,
+                         void* stream);
 
 #ifdef __cplusplus
 }

@@ -86,7 +86,8 @@ SYMBOLS = {
     "msr_get_spectrum": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _P]),
     "msr_estimate_sigma2": (_ST, [_P, _P, C.POINTER(C.c_double), _P]),
     "msr_default_lambda": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), _P]),
-    "msr_time_pass": (_ST, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), _P]),
+    "msr_time_pass": (_ST, [_P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                            C.POINTER(C.c_double), _P]),
     "msr_autotune": (_ST, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double), _P]),
 }
 
@@ -273,8 +274,11 @@ class Solver:
         times = {v: (t[2 * v], t[2 * v + 1]) for v in range(4) if t[2 * v] >= 0}
         return vr.value, vc.value, times
 
-    def time_pass(self, which, reps=20, stream=None):
+    def time_pass(self, which, reps=20, step=1, stream=None):
+        """(mean ms, algorithmic bytes, algorithmic flops) of one pass launch."""
         ms = C.c_double()
         by = C.c_double()
-        self._check(self._lib.msr_time_pass(self._h, which, reps, C.byref(ms), C.byref(by), _stream(stream)))
-        return ms.value, by.value
+        fl = C.c_double()
+        self._check(self._lib.msr_time_pass(self._h, step, which, reps, C.byref(ms), C.byref(by), C.byref(fl),
+                                            _stream(stream)))
+        return ms.value, by.value, fl.value

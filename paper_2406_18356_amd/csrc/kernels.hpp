@@ -38,6 +38,16 @@ struct LineCfg {
     static constexpr int HALF = PT / 2;             // last half-plane column index
 };
 
+// Workgroups are handed to the 8 XCDs of the chip round robin (block b runs on
+// XCD b % 8), and each XCD has its own L2.  Remapping the block index so that
+// consecutive logical blocks run on the same XCD lets neighbours share the L2
+// lines of the tiled spectra (a 128-byte line holds several rows of a tile).
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+    constexpr int NX = 8;
+    if (nblocks % NX) return b;
+    return (b % NX) * (nblocks / NX) + b / NX;
+}
+
 __device__ __forceinline__ size_t spec_idx(int kx, int row, int NR, int T) {
     return ((size_t)(kx / T) * NR + row) * T + (kx % T);
 }
@@ -88,7 +98,7 @@ row_kernel(RowArgs<R> a, Epi epi) {
     const int tid = threadIdx.x;
     const int pair = tid / TPF;
     const int t = tid - pair * TPF;
-    const int row0 = blockIdx.x * (2 * PAIRS);
+    const int row0 = xcd_block(blockIdx.x, gridDim.x) * (2 * PAIRS);
     const int ra = row0 + 2 * pair;
     const LdsView<1, C> zv{lds + pair * ZLEN, 0};
     LdsView<1, C> hv[NH];
@@ -365,14 +375,14 @@ struct ColArgs {
     int NR;      // rows of the spectra (L)
     int K;       // columns processed: tiles 0 .. ceil(K/T)-1; columns >= K read as zero
     int reduce;  // accumulate the mode's FP64 sums
+    R in_scale;  // the transformed column is in_scale * spec_in - spec_in2
 };
 
-// A block transforms CB adjacent columns (CB divides the tile width T): block
-// b covers columns b*CB .. b*CB + CB - 1 of tile (b*CB)/T.
+// A block transforms CB adjacent columns (CB divides the tile width T): logical
+// block b covers columns b*CB .. b*CB + CB - 1 of tile (b*CB)/T.
 template <typename R, int L, bool PADDED, int EMAX, int T, int CB, class Mode>
-__global__ void __launch_bounds__((CB * LineCfg<L, PADDED, R, EMAX>::TPF))
-MSR_WAVES_ATTR(EMAX, R)
-col_kernel(ColArgs<R> a, Mode md) {
+__device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, int lblock, int pblock,
+                                         cplx<R>* lds, double* red) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     using C = cplx<R>;
     constexpr int E = Cf::E, TPF = Cf::TPF, NH = Cf::NH;
@@ -380,13 +390,11 @@ col_kernel(ColArgs<R> a, Mode md) {
     constexpr int NQ = Mode::NQ;
     constexpr int HL = padded_len(L);
     static_assert(T % CB == 0, "CB must divide T");
-    __shared__ C lds[NH * CB * HL];
-    __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
 
     const int tid = threadIdx.x;
     const int cl = tid % CB;
     const int t = tid / CB;
-    const int kx = blockIdx.x * CB + cl;
+    const int kx = lblock * CB + cl;
     const int tile = kx / T;
     const int c = kx % T;
     const bool live = kx < a.K;
@@ -403,7 +411,7 @@ col_kernel(ColArgs<R> a, Mode md) {
         const int i = t + m * TPF;
         C y = mk<C>(zero, zero);
         if (live) {
-            y = a.spec_in[base + (size_t)i * T];
+            y = cscale(a.spec_in[base + (size_t)i * T], a.in_scale);
             if (a.spec_in2) y = csub(y, a.spec_in2[base + (size_t)i * T]);
         }
         v[0][m] = y;
@@ -445,9 +453,38 @@ col_kernel(ColArgs<R> a, Mode md) {
             block_sum<NQ, NT>(acc, red, tot);
             if (tid == 0)
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) a.partials[(size_t)blockIdx.x * NQ + q] = tot[q];
+                for (int q = 0; q < NQ; ++q) a.partials[(size_t)pblock * NQ + q] = tot[q];
         }
     }
+}
+
+template <typename R, int L, bool PADDED, int EMAX, int T, int CB, class Mode>
+__global__ void __launch_bounds__((CB * LineCfg<L, PADDED, R, EMAX>::TPF))
+MSR_WAVES_ATTR(EMAX, R)
+col_kernel(ColArgs<R> a, Mode md) {
+    using Cf = LineCfg<L, PADDED, R, EMAX>;
+    constexpr int NT = CB * Cf::TPF;
+    constexpr int NQ = Mode::NQ;
+    __shared__ cplx<R> lds[Cf::NH * CB * padded_len(L)];
+    __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
+    col_body<R, L, PADDED, EMAX, T, CB, Mode>(a, md, xcd_block(blockIdx.x, gridDim.x), blockIdx.x, lds, red);
+}
+
+// Two independent column passes in one launch: blocks [0, g1) run (a1, m1),
+// the rest run (a2, m2).  Used for the two narrow low-band passes of step 2.
+// Partial sums, if any, land at the launch-wide block index.
+template <typename R, int L, bool PADDED, int EMAX, int T, int CB, class M1, class M2>
+__global__ void __launch_bounds__((CB * LineCfg<L, PADDED, R, EMAX>::TPF))
+MSR_WAVES_ATTR(EMAX, R)
+col_dual_kernel(ColArgs<R> a1, M1 m1, int g1, ColArgs<R> a2, M2 m2) {
+    using Cf = LineCfg<L, PADDED, R, EMAX>;
+    constexpr int NT = CB * Cf::TPF;
+    constexpr int NQ = M1::NQ > M2::NQ ? M1::NQ : M2::NQ;
+    __shared__ cplx<R> lds[Cf::NH * CB * padded_len(L)];
+    __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (b < g1) col_body<R, L, PADDED, EMAX, T, CB, M1>(a1, m1, b, b, lds, red);
+    else col_body<R, L, PADDED, EMAX, T, CB, M2>(a2, m2, b - g1, b, lds, red);
 }
 
 // Multiply by the cached PSF spectrum (already scaled by 1/P^2), tiled like
@@ -509,17 +546,20 @@ struct FilterCoef {
 
 __device__ __forceinline__ double col_weight(int kx, int P) { return (kx == 0 || kx == P / 2) ? 1.0 : 2.0; }
 
-// Multiply by g_H^2 / P^2; accumulates sum w_kx g_H^2 |Y|^2 over the half plane
-// (= P^2 ||G_H r||^2 over the full plane).
+// Multiply by w / P^2 with w = 1/sigma^2 - g_H^2, which vanishes for
+// r > ell + delta, so only the columns k_x <= ell + delta are processed.
+// Accumulates sum w_kx w |Y|^2 over the half plane.  Because
+// g_H^2 = 1/sigma^2 - w everywhere, E^T C_{g_H^2} E r = r / sigma^2 - E^T C_w E r
+// and ||G_H r||^2 = ||r||^2 / sigma^2 - (1/P^2) sum w |Y|^2.
 template <typename R>
-struct ModeFilterH {
+struct ModeFilterW {
     static constexpr int NQ = 1;
     static constexpr bool INVERSE = true;
     static constexpr bool STORE_SPECTRUM = false;
     FilterCoef<R> f;
     R inv_p2;
     __device__ __forceinline__ cplx<R> apply(int, int, int kx, int ky, bool acc_on, cplx<R> y, double* acc) const {
-        const R g = f.sq(kx, ky).y;
+        const R g = f.inv_sigma2 - f.sq(kx, ky).y;
         if (acc_on) acc[0] += col_weight(kx, f.P) * (double)g * ((double)y.x * y.x + (double)y.y * y.y);
         return cscale(y, g * inv_p2);
     }

@@ -9,14 +9,14 @@
 //     row  SB -> SC        r = H alpha - i_L, forward
 //     col  SC -> SB        x h_hat_L                         (H^T r)
 //     row  SB -> SA        FISTA update (Alg. 1), forward alpha_k
-//   step 2 iteration (Eq. 12):
-//     col  SA -> SB        x h_hat_H
-//     row  SB -> SC        r = H alpha - i_H, forward (all columns)
-//     col  SC -> SB        x g_H^2                           (C_{g_H^2} E r)
-//     row  SB -> SC        crop, re-embed, forward (K_H columns)
-//     col  SC -> SB        x h_hat_H                         (H^T ...)
-//     col  SA - SL -> SC   x g_L^2 (k_x < K_L only)           (C_{g_L^2} E (alpha - l))
-//     row  SB + SC -> SA   FISTA update, forward alpha_k
+//   step 2 iteration (Eq. 12), with g_H^2 = 1/sigma^2 - w, w = 0 beyond ell + delta:
+//     col  SA -> SB        x h_hat_H                                  (H alpha)
+//     row  SB -> SC        r = H alpha - i_H, forward (K_H columns)
+//     col  SC -> SB        x w (k_x < K_L only)                       (C_w E r)
+//     col  SA - SL -> SG   x g_L^2 (k_x < K_L only, same launch as C_w) (C_{g_L^2} E (alpha - l))
+//     row  SB -> SB        crop, re-embed, forward (K_H columns)
+//     col  SC/s2 - SB -> SB  x h_hat_H    (H^T E^T C_{g_H^2} E r = H^T (r/sigma^2 - E^T C_w E r))
+//     row  SB + SG -> SA   FISTA update, forward alpha_k
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -81,7 +81,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t tw, SA, SB, SC, SL, hh1, hh2, d1, d2, b0, b1, t0, t1, partials, scal, colmax, total;
+    size_t tw, SA, SB, SC, SL, SG, hh1, hh2, d1, d2, b0, b1, t0, t1, partials, scal, colmax, total;
 };
 
 struct Shapes {
@@ -161,6 +161,7 @@ Layout make_layout(const Shapes& s) {
     l.SB = take(sbc);
     l.SC = l.SB + align_up(s.cs * s.spec_elems, kAlign);
     l.SL = take(s.cs * s.spec_elems);
+    l.SG = take(s.cs * s.spec_elems);
     l.hh1 = take(s.rs * s.hh_elems);
     l.hh2 = take(s.rs * s.hh_elems);
     l.d1 = take(s.rs * s.img_elems);
@@ -193,6 +194,7 @@ struct msr_ctx {
     double ell = 0, delta = 0, sigma2 = 0, eta2 = 0;
     int KL = 0;  // columns with g_L != 0
     int var_row[2] = {0, 0}, var_col[2] = {0, 0};  // kernel variants per step (autotuned)
+    int var_filt = -1;  // variant of the step-2 low-band filter pass (-1: that of the step-2 column pass)
     std::string err;
 };
 
@@ -238,6 +240,7 @@ struct Impl {
     msr_ctx* c;
     const Ops<R>* opr_[2];  // N-length row passes per step (padded or circular)
     const Ops<R>* opc_[2];  // N-length column passes per step
+    const Ops<R>* opf_;     // step-2 low-band filter pass (C_w and C_{g_L^2} in one launch)
     const Ops<R>* opp;      // P-length unpadded (PSF spectrum)
 
     static const Ops<R>* variant_or_default(int L, bool padded, int v) {
@@ -249,6 +252,7 @@ struct Impl {
             opr_[s] = variant_or_default(ctx->sh.N, ctx->sh.padded, ctx->var_row[s]);
             opc_[s] = variant_or_default(ctx->sh.N, ctx->sh.padded, ctx->var_col[s]);
         }
+        opf_ = ctx->var_filt < 0 ? opc_[1] : variant_or_default(ctx->sh.N, ctx->sh.padded, ctx->var_filt);
     }
     const Ops<R>* opr(int step) const { return opr_[step - 1]; }
     const Ops<R>* opc(int step) const { return opc_[step - 1]; }
@@ -260,6 +264,7 @@ struct Impl {
     C* SB() const { return at<C>(c->lay.SB); }
     C* SC() const { return at<C>(c->lay.SC); }
     C* SL() const { return at<C>(c->lay.SL); }
+    C* SG() const { return at<C>(c->lay.SG); }
     R* hh(int step) const { return at<R>(step == 1 ? c->lay.hh1 : c->lay.hh2); }
     R* dirty(int step) const { return at<R>(step == 1 ? c->lay.d1 : c->lay.d2); }
     R* beta(int k) const { return at<R>((k & 1) ? c->lay.b1 : c->lay.b0); }
@@ -301,8 +306,9 @@ struct Impl {
         a.reduce = reduce ? 1 : 0;
         return a;
     }
-    ColArgs<R> col_args(const C* in, const C* in2, C* out, int K, bool reduce = false) const {
+    ColArgs<R> col_args(const C* in, const C* in2, C* out, int K, bool reduce = false, R in_scale = (R)1) const {
         ColArgs<R> a{};
+        a.in_scale = in_scale;
         a.spec_in = in;
         a.spec_in2 = in2;
         a.spec_out = out;
@@ -343,13 +349,15 @@ struct Impl {
         return MSR_OK;
     }
 
-    msr_status col_psf(int step, const C* in, C* out, hipStream_t s) {
-        opc(step)->col_psf(col_args(in, nullptr, out, c->K[step - 1]), ModePsf<R>{hh(step), P(), c->sh.T}, s);
+    // out = IDFT_y(h_hat . DFT_y(in_scale * in - in2)) on the kept columns of PSF `step`.
+    msr_status col_psf(int step, const C* in, C* out, hipStream_t s, const C* in2 = nullptr, R in_scale = (R)1) {
+        opc(step)->col_psf(col_args(in, in2, out, c->K[step - 1], false, in_scale), ModePsf<R>{hh(step), P(), c->sh.T},
+                           s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
-    msr_status col_filth(const C* in, C* out, bool red, hipStream_t s) {
-        opc(2)->col_filth(col_args(in, nullptr, out, c->sh.Cfull, red), ModeFilterH<R>{filters(), inv_p2()}, s);
+    msr_status col_filtw(const C* in, C* out, bool red, hipStream_t s) {
+        opc(2)->col_filtw(col_args(in, nullptr, out, c->KL, red), ModeFilterW<R>{filters(), inv_p2()}, s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
@@ -359,22 +367,34 @@ struct Impl {
         return MSR_OK;
     }
 
+    // C_w on (SC -> SB) and C_{g_L^2} on (SA - SL -> SG), k_x < K_L, one launch.
+    msr_status col_filt_wl(const C* l, hipStream_t s) {
+        const ModeFilterW<R> mw{filters(), inv_p2()};
+        const ModeFilterL<R> ml{filters(), inv_p2()};
+        opf_->col_filt_wl(col_args(SC(), nullptr, SB(), c->KL), mw, col_args(SA(), l, SG(), c->KL), ml, s);
+        LAUNCHCHK(c);
+        return MSR_OK;
+    }
+
     // The gradient chain of step s applied to the spectrum in SA (alpha); leaves
-    // the half-gradient spectrum in SB (+ SC for k_x < K_L in step 2).  `y` is
+    // the half-gradient spectrum in SB (+ SG for k_x < K_L in step 2).  `y` is
     // the data image (null for the normal operator alone); step 2 subtracts the
     // spectrum of l (SL) when `use_l`.
     msr_status grad_chain(int step, const R* y, bool use_l, hipStream_t s) {
         const int Ks = c->K[step - 1];
         TRY(col_psf(step, SA(), SB(), s));
-        const int kr = step == 1 ? Ks : c->sh.Cfull;
-        opr(step)->row_resid_fwd(row_args(SB(), Ks, nullptr, 0, SC(), kr), EpiResid<R>{y, nullptr, N()}, s);
+        if (step == 1) {
+            opr(1)->row_resid_fwd(row_args(SB(), Ks, nullptr, 0, SC(), Ks), EpiResid<R>{y, nullptr, N()}, s);
+            LAUNCHCHK(c);
+            return col_psf(1, SC(), SB(), s);
+        }
+        const int kr = std::max(Ks, c->KL);
+        opr(2)->row_resid_fwd(row_args(SB(), Ks, nullptr, 0, SC(), kr), EpiResid<R>{y, nullptr, N()}, s);
         LAUNCHCHK(c);
-        if (step == 1) return col_psf(1, SC(), SB(), s);
-        TRY(col_filth(SC(), SB(), false, s));
-        opr(step)->row_resid_fwd(row_args(SB(), c->sh.Cfull, nullptr, 0, SC(), Ks), EpiResid<R>{nullptr, nullptr, N()}, s);
+        TRY(col_filt_wl(use_l ? SL() : nullptr, s));
+        opr(2)->row_resid_fwd(row_args(SB(), c->KL, nullptr, 0, SB(), Ks), EpiResid<R>{nullptr, nullptr, N()}, s);
         LAUNCHCHK(c);
-        TRY(col_psf(2, SC(), SB(), s));
-        return col_filtl(SA(), use_l ? SL() : nullptr, SC(), false, s);
+        return col_psf(2, SC(), SB(), s, SB(), (R)(1.0 / c->sigma2));
     }
 
     static double momentum(int k) { return k >= 1 ? (k - 1.0) / (k + 2.0) : 0.0; }
@@ -393,7 +413,7 @@ struct Impl {
         u.positivity = c->cfg.positivity;
         const int Ks = c->K[step - 1];
         RowArgs<R> a = step == 1 ? row_args(SB(), Ks, nullptr, 0, SA(), KA(1))
-                                 : row_args(SB(), Ks, SC(), c->KL, SA(), KA(2));
+                                 : row_args(SB(), Ks, SG(), c->KL, SA(), KA(2));
         opr(step)->row_update_fwd(a, u, s);
         LAUNCHCHK(c);
         return MSR_OK;
@@ -410,17 +430,20 @@ struct Impl {
             LAUNCHCHK(c);
             TRY(reduce(row_grid(1), 1, 0, &data, s));
         } else {
-            double dh = 0.0, dl = 0.0;
+            // ||G_H r||^2 = ||r||^2 / sigma^2 - (1/P^2) sum w |R|^2, ||G_L (l - x)||^2 = (1/P^2) sum g_L^2 |.|^2
+            double dr = 0.0, dw = 0.0, dl = 0.0;
             TRY(fwd_image(2, x, (R)1, SB(), KA(2), s));
             TRY(col_psf(2, SB(), SC(), s));
-            opr(2)->row_resid_fwd(row_args(SC(), c->K[1], nullptr, 0, SC(), c->sh.Cfull),
-                              EpiResid<R>{dirty(2), nullptr, N()}, s);
+            opr(2)->row_resid_fwd(row_args(SC(), c->K[1], nullptr, 0, SC(), c->KL, true),
+                                  EpiResid<R>{dirty(2), nullptr, N()}, s);
             LAUNCHCHK(c);
-            TRY(col_filth(SC(), SC(), true, s));
-            TRY(reduce(col_grid(2, c->sh.Cfull), 1, 0, &dh, s));
+            TRY(reduce(row_grid(2), 1, 0, &dr, s));
+            TRY(col_filtw(SC(), SC(), true, s));
+            TRY(reduce(col_grid(2, c->KL), 1, 0, &dw, s));
             TRY(col_filtl(SB(), SL(), SC(), true, s));
             TRY(reduce(col_grid(2, c->KL), 1, 0, &dl, s));
-            data = (dh + dl) / ((double)P() * (double)P());
+            const double ip2 = 1.0 / ((double)P() * (double)P());
+            data = dr / c->sigma2 + (dl - dw) * ip2;
         }
         double l1 = 0.0;
         TRY(image_reduce(x, nullptr, 0, &l1, s));
@@ -449,7 +472,7 @@ struct Impl {
             TRY(grad_chain(step, nullptr, false, s));
             EpiPower<R> ep{v, w, N(), (R)scale};
             RowArgs<R> a = step == 1 ? row_args(SB(), c->K[0], nullptr, 0, nullptr, 0, true)
-                                     : row_args(SB(), c->K[1], SC(), c->KL, nullptr, 0, true);
+                                     : row_args(SB(), c->K[1], SG(), c->KL, nullptr, 0, true);
             opr(step)->row_power(a, ep, s);
             LAUNCHCHK(c);
             double sums[2];
@@ -508,6 +531,7 @@ struct Impl {
         opp->row_loadshift_fwd(ra, EpiLoadShift<R>{psf, Pn}, s);
         LAUNCHCHK(c);
         ColArgs<R> ca{};
+        ca.in_scale = (R)1;
         ca.spec_in = tmpspec;
         ca.spec_out = tmpspec;
         ca.tw = tw();
@@ -646,7 +670,7 @@ struct Impl {
         TRY(fwd_image(step, x, (R)1, SA(), KA(step), s));
         TRY(grad_chain(step, dirty(step), true, s));
         RowArgs<R> a = step == 1 ? row_args(SB(), c->K[0], nullptr, 0, nullptr, 0)
-                                 : row_args(SB(), c->K[1], SC(), c->KL, nullptr, 0);
+                                 : row_args(SB(), c->K[1], SG(), c->KL, nullptr, 0);
         opr(step)->row_store(a, EpiStore<R>{g, N(), (R)2}, s);
         LAUNCHCHK(c);
         HIPCHK(c, hipStreamSynchronize(s));
@@ -702,27 +726,53 @@ struct Impl {
                 c->var_col[step - 1] = v;
                 Impl<R> im(c);
                 double ms = 0.0;
-                TRY(im.time_pass(0, step, reps, &ms, nullptr, s));
+                TRY(im.time_pass(0, step, reps, &ms, nullptr, nullptr, s));
                 if (times && step == 1) times[2 * v] = ms;
                 if (ms < best_c) best_c = ms, vc = v;
-                TRY(im.time_pass(2, step, reps, &ms, nullptr, s));
+                TRY(im.time_pass(2, step, reps, &ms, nullptr, nullptr, s));
                 if (times && step == 1) times[2 * v + 1] = ms;
                 if (ms < best_r) best_r = ms, vr = v;
             }
             c->var_row[step - 1] = vr;
             c->var_col[step - 1] = vc;
+            if (step == 2 && c->have_filters) {
+                double best_f = 1e30;
+                int vf = vc;
+                for (int v = 0; v < kVariants; ++v) {
+                    const Ops<R>* o = ops_for<R>(N(), c->sh.padded, v);
+                    if (!o || !o->row_update_fwd) continue;
+                    c->var_filt = v;
+                    Impl<R> im(c);
+                    double ms = 0.0;
+                    TRY(im.time_pass(3, 2, reps, &ms, nullptr, nullptr, s));
+                    if (ms < best_f) best_f = ms, vf = v;
+                }
+                c->var_filt = vf;
+            }
         }
         return MSR_OK;
     }
 
-    msr_status time_pass(int which, int step, int reps, double* ms_out, double* bytes_out, hipStream_t s) {
+    // Times one pass of an iteration of `step` (current state, `reps` launches)
+    // and returns its algorithmic bytes and flops per launch.  which: 0 = column
+    // PSF pass, 1 = residual row pass, 2 = fused update row pass, 3 = the step-2
+    // low-band filter pass (C_w and C_{g_L^2} on K_L columns each).  Flops count
+    // 5 n log2 n per complex transform of length n (P here), one inverse and one
+    // forward transform per row pair or per column.
+    msr_status time_pass(int which, int step, int reps, double* ms_out, double* bytes_out, double* flops_out,
+                         hipStream_t s) {
         const int Nn = N(), Pn = P(), K = c->K[step - 1];
+        const int Kin2 = step == 2 ? c->KL : 0;
+        const int Kout = step == 2 ? KA(2) : K;
         const double es = (double)c->sh.cs, rs = (double)c->sh.rs;
-        const double spec = (double)Nn * K * es, img = (double)Nn * Nn * rs;
+        const double img = (double)Nn * Nn * rs;
+        const double fft_p = 5.0 * Pn * std::log2((double)Pn);
         auto launch = [&]() -> msr_status {
             if (which == 0) return col_psf(step, SA(), SB(), s);
+            if (which == 3) return col_filt_wl(SL(), s);
             if (which == 1) {
-                opr(step)->row_resid_fwd(row_args(SB(), K, nullptr, 0, SC(), K), EpiResid<R>{dirty(step), nullptr, Nn}, s);
+                opr(step)->row_resid_fwd(row_args(SB(), K, nullptr, 0, SC(), K), EpiResid<R>{dirty(step), nullptr, Nn},
+                                         s);
                 LAUNCHCHK(c);
                 return MSR_OK;
             }
@@ -731,14 +781,24 @@ struct Impl {
             u.b2 = beta(1);
             u.ld = Nn;
             u.positivity = c->cfg.positivity;
-            opr(step)->row_update_fwd(row_args(SB(), K, nullptr, 0, SC(), K), u, s);
+            opr(step)->row_update_fwd(row_args(SB(), K, Kin2 ? SL() : nullptr, Kin2, SC(), Kout), u, s);
             LAUNCHCHK(c);
             return MSR_OK;
         };
-        double bytes;
-        if (which == 0) bytes = 2 * spec + (double)Pn * K * rs;
-        else if (which == 1) bytes = 2 * spec + img;
-        else bytes = 2 * spec + 3 * img;
+        double bytes, flops;
+        if (which == 0) {
+            bytes = 2.0 * Nn * K * es + (double)Pn * K * rs;
+            flops = 2.0 * K * fft_p;
+        } else if (which == 3) {
+            bytes = 5.0 * Nn * Kin2 * es;  // C_w: SC in, SB out; C_{g_L^2}: SA, SL in, SG out
+            flops = 4.0 * Kin2 * fft_p;
+        } else if (which == 1) {
+            bytes = 2.0 * Nn * K * es + img;
+            flops = 2.0 * (Nn / 2) * fft_p;
+        } else {
+            bytes = (double)Nn * (K + Kin2 + Kout) * es + 3 * img;
+            flops = 2.0 * (Nn / 2) * fft_p;
+        }
         TRY(launch());  // warm
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
@@ -757,6 +817,7 @@ struct Impl {
         if (st != MSR_OK) return st;
         if (ms_out) *ms_out = ms / reps;
         if (bytes_out) *bytes_out = bytes;
+        if (flops_out) *flops_out = flops;
         return MSR_OK;
     }
 };
@@ -978,10 +1039,15 @@ msr_status msr_autotune(msr_ctx* c, int reps, int* row_variant, int* col_variant
     return MSR_OK;
 }
 
-msr_status msr_time_pass(msr_ctx* c, int which, int reps, double* ms_out, double* bytes_out, void* stream) {
-    TRY(check_step(c, 1, false));
-    if (reps <= 0 || which < 0 || which > 2) return fail(c, MSR_ERR_INVALID, "bad arguments");
-    return with_impl(c, [&](auto& im) { return im.time_pass(which, 1, reps, ms_out, bytes_out, S(stream)); });
+msr_status msr_time_pass(msr_ctx* c, int step, int which, int reps, double* ms_out, double* bytes_out,
+                         double* flops_out, void* stream) {
+    TRY(check_step(c, step, true));
+    if (reps <= 0 || which < 0 || which > 3) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    if (which == 3 && (step != 2 || !c->have_filters))
+        return fail(c, MSR_ERR_STATE, "the filter pass needs step 2 with filters set");
+    return with_impl(c, [&](auto& im) {
+        return im.time_pass(which, step, reps, ms_out, bytes_out, flops_out, S(stream));
+    });
 }
 
 }  // extern "C"

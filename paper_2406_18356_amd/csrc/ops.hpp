@@ -81,9 +81,12 @@ struct Ops {
     void (*row_update_fwd)(const RowArgs<R>&, const EpiUpdate<R>&, hipStream_t) = nullptr;  // FISTA update
     void (*row_power)(const RowArgs<R>&, const EpiPower<R>&, hipStream_t) = nullptr;        // power iteration
     void (*col_psf)(const ColArgs<R>&, const ModePsf<R>&, hipStream_t) = nullptr;
-    void (*col_filth)(const ColArgs<R>&, const ModeFilterH<R>&, hipStream_t) = nullptr;
+    void (*col_filtw)(const ColArgs<R>&, const ModeFilterW<R>&, hipStream_t) = nullptr;
     void (*col_filtl)(const ColArgs<R>&, const ModeFilterL<R>&, hipStream_t) = nullptr;
     void (*col_forward)(const ColArgs<R>&, const ModeForward<R>&, hipStream_t) = nullptr;  // unpadded forward only
+    // the w and g_L^2 passes of a step-2 iteration in one launch
+    void (*col_filt_wl)(const ColArgs<R>&, const ModeFilterW<R>&, const ColArgs<R>&, const ModeFilterL<R>&,
+                        hipStream_t) = nullptr;
 };
 
 // Tables per line length (L = 8 .. 16384) and variant; nullptr where not built.

@@ -31,6 +31,15 @@ struct Inst {
         hipLaunchKernelGGL((col_kernel<R, L, PADDED, EMAX, T, CB, Mode>), dim3(grid), dim3(CT), 0, s, a, m);
     }
 
+    template <class M1, class M2>
+    static void col_dual(const ColArgs<R>& a1, const M1& m1, const ColArgs<R>& a2, const M2& m2, hipStream_t s) {
+        const int g1 = (a1.K + CB - 1) / CB;
+        const int g2 = (a2.K + CB - 1) / CB;
+        if (g1 + g2 <= 0) return;
+        hipLaunchKernelGGL((col_dual_kernel<R, L, PADDED, EMAX, T, CB, M1, M2>), dim3(g1 + g2), dim3(CT), 0, s, a1, m1,
+                           g1, a2, m2);
+    }
+
     static Ops<R> make(bool full) {
         Ops<R> o;
         o.L = L;
@@ -54,8 +63,9 @@ struct Inst {
             o.row_update_fwd = &row<true, true, EpiUpdate<R>>;
             o.row_power = &row<true, false, EpiPower<R>>;
             o.col_psf = &col<ModePsf<R>>;
-            o.col_filth = &col<ModeFilterH<R>>;
+            o.col_filtw = &col<ModeFilterW<R>>;
             o.col_filtl = &col<ModeFilterL<R>>;
+            o.col_filt_wl = &col_dual<ModeFilterW<R>, ModeFilterL<R>>;
         }
         return o;
     }

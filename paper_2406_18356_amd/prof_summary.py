@@ -1,0 +1,124 @@
+"""Summaries of rocprofv3 CSV output for the ``profiles/`` directory.
+
+    python -m paper_2406_18356_amd.prof_summary stats DIR PREFIX OUT.txt --command "..."
+    python -m paper_2406_18356_amd.prof_summary traffic DIR FETCH_PREFIX WRITE_PREFIX OUT.json \
+        --kernel SUBSTRING --bytes ALGORITHMIC_BYTES --command "..."
+
+``stats`` condenses ``<PREFIX>_kernel_stats.csv`` (rocprofv3 --kernel-trace
+--stats --output-format csv) into a table.  ``traffic`` reads two --pmc runs
+(FETCH_SIZE, WRITE_SIZE, in KiB per dispatch), calibrates each counter against
+the largest device-to-device copy in the same run (a copy of B bytes must read
+and write B bytes) and records the scaled per-launch HBM traffic of the kernel
+whose name contains SUBSTRING, with a hash of the kernel sources so that the
+benchmark can tell whether the figure still describes the current code.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/fft_engine.hpp", "csrc/kernels.hpp", "csrc/ops.hpp", "csrc/ops_inst.hip")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _short(name: str) -> str:
+    n = re.sub(r"void msr::", "", name)
+    n = re.sub(r"msr::(RowArgs|ColArgs)<(float|double)>, ", "", n)
+    n = re.sub(r"\(.*", "", n)
+    return n
+
+
+def stats(d, prefix, out, command, top=16):
+    rows = list(csv.DictReader(open(os.path.join(d, f"{prefix}_kernel_stats.csv"))))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+             f"{'kernel':90s} {'calls':>7s} {'avg_us':>9s} {'total_ms':>9s} {'pct':>6s}"]
+    for r in rows[:top]:
+        lines.append(f"{_short(r['Name'])[:90]:90s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:9.2f} {float(r['Percentage']):6.1f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    return out
+
+
+def _per_dispatch(d, prefix, counter):
+    out = []
+    for f in glob.glob(os.path.join(d, f"{prefix}_counter_collection.csv")):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter:
+                out.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return out
+
+
+def _copy_scale(rows, copy_bytes):
+    copies = [v for n, g, v in rows if "copyBuffer" in n]
+    if not copies:
+        raise SystemExit("no device copy kernel in the counter run")
+    big = max(copies)
+    return copy_bytes / 1024.0 / big, big
+
+
+def traffic(d, fprefix, wprefix, out, kernel, alg_bytes, copy_bytes, command, last=0):
+    fr = _per_dispatch(d, fprefix, "FETCH_SIZE")
+    wr = _per_dispatch(d, wprefix, "WRITE_SIZE")
+    fs, fbig = _copy_scale(fr, copy_bytes)
+    ws, wbig = _copy_scale(wr, copy_bytes)
+    fk = [v for n, g, v in fr if kernel in n]
+    wk = [v for n, g, v in wr if kernel in n]
+    if last:
+        fk, wk = fk[-last:], wk[-last:]
+    if not fk or not wk:
+        raise SystemExit(f"kernel {kernel!r} not found")
+    fetch = sum(fk) / len(fk) * fs * 1024.0
+    write = sum(wk) / len(wk) * ws * 1024.0
+    rec = {
+        "kernel": kernel, "source_sha256": kernel_source_hash(), "command": command,
+        "fetch_kib_raw": sum(fk) / len(fk), "write_kib_raw": sum(wk) / len(wk),
+        "copy_bytes": copy_bytes, "copy_fetch_kib": fbig, "copy_write_kib": wbig,
+        "fetch_scale": fs, "write_scale": ws,
+        "dispatches": len(fk), "traffic_bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+        "algorithmic_bytes": alg_bytes,
+    }
+    json.dump(rec, open(out, "w"), indent=1)
+    return rec
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("prefix")
+    s.add_argument("out")
+    s.add_argument("--command", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("dir")
+    t.add_argument("fetch_prefix")
+    t.add_argument("write_prefix")
+    t.add_argument("out")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--bytes", type=float, required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--last", type=int, default=0, help="average only the last N dispatches of the kernel")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        print(stats(a.dir, a.prefix, a.out, a.command))
+    else:
+        print(json.dumps(traffic(a.dir, a.fetch_prefix, a.write_prefix, a.out, a.kernel, a.bytes, a.copy_bytes,
+                                 a.command, a.last), indent=1))
+
+
+if __name__ == "__main__":
+    main()
