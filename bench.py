@@ -12,7 +12,7 @@ step 2 from a cold start and from the low-resolution image as a warm start,
 the dominant kernel against the HBM roofline (timed live with HIP events),
 and the FP64 CPU oracle timed on this host.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--size 2048]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--size 4096]
 """
 from __future__ import annotations
 
@@ -92,14 +92,15 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--size", type=int, default=2048, choices=sorted(WORKLOADS))
+    ap.add_argument("--size", type=int, default=4096, choices=sorted(WORKLOADS))
     ap.add_argument("--iters", type=int, default=None, help="FISTA iterations per step (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--ttt-ref-iters", type=int, default=20000)
-    ap.add_argument("--profile-pass", type=int, nargs=3, default=None, metavar=("STEP", "WHICH", "REPS"),
-                    help="profiling aid: after setup, run only msr_time_pass(STEP, WHICH, REPS) and one "
-                         "64 MiB device copy (counter calibration), then exit")
+    ap.add_argument("--profile-pass", type=int, nargs=3, action="append", default=None,
+                    metavar=("STEP", "WHICH", "REPS"),
+                    help="profiling aid (repeatable): after setup, run one 64 MiB device copy (counter "
+                         "calibration) and msr_time_pass(STEP, WHICH, REPS) for each triple, then exit")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="K",
                     help="profiling aid: set up the workload, autotune, run K iterations of each step and exit")
     args = ap.parse_args(argv)
@@ -124,11 +125,12 @@ def main(argv=None):
     s = Solver(pr.n, pad=2, positivity=True, prune_tol=1e-6)
     s.set_dirty_psf(1, tensors[0], tensors[1])
     s.set_dirty_psf(2, tensors[2], tensors[3])
+    sig2 = s.estimate_sigma2(tensors[2])
+    s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)  # so that the low-band filter pass is tuned too
     tuned = s.autotune(reps=20)
     log("autotune (row variant, column variant, {variant: (col ms, row ms)}):", tuned)
     torch.cuda.synchronize()
     if args.profile_pass:
-        step, which, reps = args.profile_pass
         s.lipschitz(1)
         b1, iL, _ = s.step1(s.default_lambda(1, 1, 0.05), 10, image=True)
         sig2 = s.estimate_sigma2(tensors[2])
@@ -139,9 +141,10 @@ def main(argv=None):
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
-        ms, by, fl = s.time_pass(which, reps=reps, step=step)
-        torch.cuda.synchronize()
-        log(f"profile-pass step {step} which {which}: {ms * 1e3:.2f} us, {by:.0f} bytes, {fl:.0f} flops")
+        for step, which, reps in args.profile_pass:
+            ms, by, fl = s.time_pass(which, reps=reps, step=step)
+            torch.cuda.synchronize()
+            log(f"profile-pass step {step} which {which}: {ms * 1e3:.2f} us, {by:.0f} bytes, {fl:.0f} flops")
         return 0
     if args.kernels_only:
         s.lipschitz(1)

@@ -3,6 +3,8 @@
     python -m paper_2406_18356_amd.prof_summary stats DIR PREFIX OUT.txt --command "..."
     python -m paper_2406_18356_amd.prof_summary traffic DIR FETCH_PREFIX WRITE_PREFIX OUT.json \
         --kernel SUBSTRING --bytes ALGORITHMIC_BYTES --command "..."
+    python -m paper_2406_18356_amd.prof_summary passes DIR PREFIX OUT.txt --command "..." \
+        --pass NAME SUBSTRING LAST [--pass ...]
 
 ``stats`` condenses ``<PREFIX>_kernel_stats.csv`` (rocprofv3 --kernel-trace
 --stats --output-format csv) into a table.  ``traffic`` reads two --pmc runs
@@ -11,6 +13,9 @@ the largest device-to-device copy in the same run (a copy of B bytes must read
 and write B bytes) and records the scaled per-launch HBM traffic of the kernel
 whose name contains SUBSTRING, with a hash of the kernel sources so that the
 benchmark can tell whether the figure still describes the current code.
+``passes`` reads ``<PREFIX>_kernel_trace.csv`` and reports, per named pass, the
+mean duration of the last LAST dispatches whose kernel name contains SUBSTRING
+(the back-to-back launches of one pass at the end of a profiling run).
 """
 from __future__ import annotations
 
@@ -48,6 +53,23 @@ def stats(d, prefix, out, command, top=16):
     for r in rows[:top]:
         lines.append(f"{_short(r['Name'])[:90]:90s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:9.2f} {float(r['Percentage']):6.1f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    return out
+
+
+def passes(d, prefix, out, command, specs):
+    rows = list(csv.DictReader(open(os.path.join(d, f"{prefix}_kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    lines = [f"# rocprofv3 kernel trace: mean duration of the last dispatches of each pass",
+             f"# command: {command}", "",
+             f"{'pass':18s} {'dispatches':>10s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}  kernel"]
+    for name, sub, last in specs:
+        ds = [r for r in rows if sub in r["Kernel_Name"]][-int(last):]
+        if not ds:
+            raise SystemExit(f"no dispatch matching {sub!r}")
+        us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in ds]
+        lines.append(f"{name:18s} {len(us):10d} {sum(us) / len(us):9.2f} {min(us):9.2f} {max(us):9.2f}  "
+                     f"{_short(ds[-1]['Kernel_Name'])[:100]}")
     open(out, "w").write("\n".join(lines) + "\n")
     return out
 
@@ -112,9 +134,18 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--command", required=True)
     t.add_argument("--last", type=int, default=0, help="average only the last N dispatches of the kernel")
+    q = sub.add_parser("passes")
+    q.add_argument("dir")
+    q.add_argument("prefix")
+    q.add_argument("out")
+    q.add_argument("--command", required=True)
+    q.add_argument("--pass", dest="specs", nargs=3, action="append", required=True,
+                   metavar=("NAME", "SUBSTRING", "LAST"))
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats(a.dir, a.prefix, a.out, a.command))
+    elif a.cmd == "passes":
+        print(passes(a.dir, a.prefix, a.out, a.command, a.specs))
     else:
         print(json.dumps(traffic(a.dir, a.fetch_prefix, a.write_prefix, a.out, a.kernel, a.bytes, a.copy_bytes,
                                  a.command, a.last), indent=1))

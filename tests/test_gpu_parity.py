@@ -374,44 +374,65 @@ def test_errors(torch_dev):
 
 
 # ----------------------------------------------------------------- full size
-@pytest.fixture(scope="module")
-def big(torch_dev):
-    pr = synth.make_problem(synth.preset("sky2048"), with_full=False)
+# The benchmark workloads (2048^2 image on a 4096^2 grid; 4096^2 on 8192^2), in
+# the launch configuration the benchmark times (autotuned variants).
+@pytest.fixture(scope="module", params=["sky2048", "sky4096"])
+def big(torch_dev, request):
+    print(f"full-size workload {request.param}", flush=True)
+    pr = synth.make_problem(synth.preset(request.param), with_full=False)
     s = _solver(torch_dev, pr, positivity=True)
     return pr, s
 
 
 def test_full_size_psf_sampled(torch_dev, big):
-    """2048^2 image, 4096^2 grid: H x at sampled pixels against the defining spatial sum."""
+    """H x at sampled pixels against the defining spatial sum (both PSFs)."""
     pr, s = big
     n, P = pr.n, pr.P
     x = np.zeros((n, n))
     rng = np.random.default_rng(7)
     idx = rng.integers(0, n, (64, 2))
     x[idx[:, 0], idx[:, 1]] = rng.normal(size=64)
-    x[900:1100, 900:1100] = rng.normal(size=(200, 200))
-    y = s.apply_psf(1, _t(torch_dev, x)).cpu().numpy()
+    x[n // 2 - 100:n // 2 + 100, n // 2 - 100:n // 2 + 100] = rng.normal(size=(200, 200))
+    x[n - 7:, :9] = rng.normal(size=(7, 9))  # a corner: wrap-around would show here
     c = P // 2
     xs = x.astype(np.float32).astype(np.float64)
     qi, qj = np.nonzero(xs)
     vals = xs[qi, qj]
-    peak = np.max(np.abs(y))
-    for p in rng.integers(0, n, (24, 2)):
-        ref = float(np.sum(pr.psf_L[c + p[0] - qi, c + p[1] - qj] * vals))
-        assert abs(y[p[0], p[1]] - ref) <= OP_TOL * peak
+    xt = _t(torch_dev, x)
+    for step, psf in ((1, pr.psf_L), (2, pr.psf_H)):
+        y = s.apply_psf(step, xt).cpu().numpy()
+        peak = np.max(np.abs(y))
+        pts = np.concatenate([rng.integers(0, n, (24, 2)), [[0, 0], [n - 1, n - 1], [0, n - 1], [n - 1, 0]]])
+        for p in pts:
+            ref = float(np.sum(psf[c + p[0] - qi, c + p[1] - qj] * vals))
+            assert abs(y[p[0], p[1]] - ref) <= OP_TOL * peak, (step, p)
 
 
 def test_full_size_one_step_map(torch_dev, big):
-    """One FISTA step at 2048^2 from a nonzero x0, against the FP64 FFT oracle on the full grid."""
+    """One FISTA step of each step from a nonzero x0, against the FP64 FFT oracle on the full grid."""
     from oracle import objectives, fista
 
     pr, s = big
     n = pr.n
+    s.autotune(reps=3)
+    rng = np.random.default_rng(2)
+    x0 = (np.abs(rng.normal(size=(n, n))) * 1e-3).astype(np.float32)
     s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
-    th = 2.5e9
+    th = 2.0 * float(np.max(np.abs(s1.H.h))) ** 2
     s.set_lipschitz(1, th)
     lam = 0.05 * np.linalg.norm(pr.dirty_L)
-    x0 = (np.abs(np.random.default_rng(2).normal(size=(n, n))) * 1e-3).astype(np.float32)
     b, _ = s.step1(lam, 1, x0=_t(torch_dev, x0))
     bo, _ = fista.fista(s1.grad, x0.astype(np.float64), 1 / th, lam, 1, positivity=True)
     assert rel(b.cpu().numpy(), bo) <= TOL
+    del s1
+
+    low = (np.abs(rng.normal(size=(n, n))) * 1e-2).astype(np.float32)
+    sig2 = 0.5
+    s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+    s2 = objectives.Step2(pr.dirty_H, pr.psf_H, low.astype(np.float64), pr.ell, pr.delta, sig2, 1e-3 * sig2)
+    th2 = 2.0 * (float(np.max(s2.gH2)) * float(np.max(np.abs(s2.H.h))) ** 2 + float(np.max(s2.gL2)))
+    s.set_lipschitz(2, th2)
+    lam2 = 0.05 * np.linalg.norm(pr.dirty_H)
+    b2, _ = s.step2(lam2, _t(torch_dev, low), 1, x0=_t(torch_dev, x0))
+    bo2, _ = fista.fista(s2.grad, x0.astype(np.float64), 1 / th2, lam2, 1, positivity=True)
+    assert rel(b2.cpu().numpy(), bo2) <= TOL
