@@ -1,8 +1,8 @@
-"""The PSF convolution operator H (Sect. 3.2: "the operator detailing the
-convolution by the PSF"; Sect. 3.3 for H_H).
+"""The PSF convolution operator H (Sect. 3.2 defines H_L as convolution by the
+low-resolution PSF; Sect. 3.3 does the same for H_H).
 
-Discretisation (the paper does not fix it; see the readings in the design
-notes): an N x N image x is zero-embedded into a P x P grid at offset
+Discretisation (the paper does not fix it; this is the reading used
+throughout): an N x N image x is zero-embedded into a P x P grid at offset
 o = (P - N) // 2 (operator E), circularly convolved with the P x P PSF whose
 phase centre sits at (P/2, P/2), and cropped back (E^T):
 
