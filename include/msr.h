@@ -206,6 +206,61 @@ msr_status msr_autotune(msr_ctx* ctx, int reps, int* row_variant, int* col_varia
 msr_status msr_time_pass(msr_ctx* ctx, int step, int which, int reps, double* ms, double* bytes, double* flops,
                          void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched solves.  A batch holds C channels: independent instances of the
+ * two-step problem, e.g. the frequency channels of one observation (the
+ * paper partitions visibilities per channel as well as by baseline length,
+ * Sect. 3.1), of possibly different image sizes.  Channels of equal size are
+ * solved by the same launches (one launch per pass for all of them), and the
+ * iterations of all channels are captured once into a HIP graph and replayed.
+ * Results equal those of msr_step1_low_res / msr_step2_full_res on each
+ * channel alone (same kernels, same arithmetic order), apart from the
+ * stopping rule: a batched solve runs a fixed number of iterations.
+ * ------------------------------------------------------------------------- */
+typedef struct msr_batch msr_batch;
+
+/* Bytes of device workspace a batch of these channel configurations needs
+ * (0 if the configurations are invalid: all channels must share pad,
+ * precision, positivity and device). */
+size_t msr_batch_workspace_bytes(int channels, const msr_config* cfgs);
+
+/* Creates a batch of `channels` contexts configured by cfgs[0..channels-1]. */
+msr_status msr_batch_init(int channels, const msr_config* cfgs, msr_batch** out);
+
+/* Frees the batch, its contexts, streams and graph (not the workspace). */
+void msr_batch_destroy(msr_batch* batch);
+
+/* Text of the last failed batch call. */
+const char* msr_batch_last_error(const msr_batch* batch);
+
+/* Number of channels. */
+int msr_batch_channels(const msr_batch* batch);
+
+/* Channel c's context, owned by the batch: set its dirty images and PSFs
+ * (msr_set_dirty_psf), filters (msr_set_filters) and, optionally, its
+ * Lipschitz constants with the single-context calls.  Do not give it a
+ * workspace or destroy it.  NULL if c is out of range. */
+msr_ctx* msr_batch_channel(msr_batch* batch, int c);
+
+/* Hands over the caller-allocated workspace (256-byte aligned, at least
+ * msr_batch_workspace_bytes) and places every channel's context in it. */
+msr_status msr_batch_set_workspace(msr_batch* batch, void* dev, size_t bytes);
+
+/* msr_autotune on the first channel of each size and the choice copied to the
+ * others of that size. */
+msr_status msr_batch_autotune(msr_batch* batch, int reps, void* stream);
+
+/* `iters` FISTA iterations of step s (1: Eq. 4, 2: Eq. 5) for every channel:
+ * lambda[c] its regularisation weight, low_res[c] its constraint image (step 2),
+ * x0 NULL or x0[c] its start (NULL entries: 0), model_out[c] its result
+ * beta_iters (device, N_c x N_c).  res, if not NULL, receives per channel the
+ * exact objective of the result (FP64), theta and the elapsed time of the whole
+ * batched iteration loop.  Channels without a cached theta get one by power
+ * iteration first.  The first call for a given (step, iters, kept columns,
+ * variants) captures the graph; later calls replay it.  Blocks until done. */
+msr_status msr_batch_solve(msr_batch* batch, int step, const double* lambda, int iters, const void* const* low_res,
+                           const void* const* x0, void* const* model_out, msr_result* res, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

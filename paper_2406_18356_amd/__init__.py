@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     SolveOptions,
     Result,
     Solver,
+    Batch,
     lib,
     library_path,
     abi_version,

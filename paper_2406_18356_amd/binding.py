@@ -89,6 +89,16 @@ SYMBOLS = {
     "msr_time_pass": (_ST, [_P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), _P]),
     "msr_autotune": (_ST, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double), _P]),
+    "msr_batch_workspace_bytes": (C.c_size_t, [C.c_int, C.POINTER(Config)]),
+    "msr_batch_init": (_ST, [C.c_int, C.POINTER(Config), C.POINTER(_P)]),
+    "msr_batch_destroy": (None, [_P]),
+    "msr_batch_last_error": (C.c_char_p, [_P]),
+    "msr_batch_channels": (C.c_int, [_P]),
+    "msr_batch_channel": (_P, [_P, C.c_int]),
+    "msr_batch_set_workspace": (_ST, [_P, _P, C.c_size_t]),
+    "msr_batch_autotune": (_ST, [_P, C.c_int, _P]),
+    "msr_batch_solve": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(_P), C.POINTER(_P),
+                              C.POINTER(_P), C.POINTER(Result), _P]),
 }
 
 _lib = None
@@ -154,10 +164,17 @@ class Solver:
     """
 
     def __init__(self, n: int, pad: int = 2, positivity: bool = False, device: int = 0, seed: int = 0,
-                 prune_tol: float = 1e-6, precision: int = 32):
+                 prune_tol: float = 1e-6, precision: int = 32, _borrowed=None):
         import torch
 
         self._lib = lib()
+        self._owned = _borrowed is None
+        if _borrowed is not None:  # a channel context owned by a Batch
+            self.n, self.P, self.precision = n, pad * n, precision
+            self.dtype = torch.float32 if precision == 32 else torch.float64
+            self.device = torch.device("cuda", device)
+            self._h = C.c_void_p(_borrowed)
+            return
         self.n = n
         self.P = pad * n
         self.precision = precision
@@ -179,7 +196,7 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if getattr(self, "_owned", False) and h is not None and h.value:
             self._lib.msr_destroy(h)
             self._h = None
 
@@ -282,3 +299,72 @@ class Solver:
         self._check(self._lib.msr_time_pass(self._h, step, which, reps, C.byref(ms), C.byref(by), C.byref(fl),
                                             _stream(stream)))
         return ms.value, by.value, fl.value
+
+
+class Batch:
+    """Many channels (independent two-step problems, possibly of different
+    sizes) solved together: ``msr_batch_*`` of the C ABI.
+
+    >>> b = Batch([2048, 1024, 1024, 512], positivity=True)
+    >>> for c, ch in enumerate(b.channels): ch.set_dirty_psf(1, dirty[c], psf[c])
+    >>> models, results = b.solve(1, lambdas, iters=500)
+    """
+
+    def __init__(self, sizes, pad: int = 2, positivity: bool = False, device: int = 0, seed: int = 0,
+                 prune_tol: float = 1e-6, precision: int = 32):
+        import torch
+
+        self._lib = lib()
+        self.sizes = [int(n) for n in sizes]
+        self.precision = precision
+        self.dtype = torch.float32 if precision == 32 else torch.float64
+        self.device = torch.device("cuda", device)
+        cfgs = (Config * len(self.sizes))(*[_cfg(n, pad, positivity, device, seed, prune_tol, precision)
+                                            for n in self.sizes])
+        h = C.c_void_p()
+        st = self._lib.msr_batch_init(len(self.sizes), cfgs, C.byref(h))
+        if st != OK:
+            raise MsrError(st, "msr_batch_init rejected the configurations")
+        self._h = h
+        nbytes = int(self._lib.msr_batch_workspace_bytes(len(self.sizes), cfgs))
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._ws.data_ptr() + 255) // 256 * 256
+        self._check(self._lib.msr_batch_set_workspace(self._h, C.c_void_p(aligned), nbytes))
+        self.workspace_bytes = nbytes
+        self.channels = [Solver(n, pad, positivity, device, seed, prune_tol, precision,
+                                _borrowed=self._lib.msr_batch_channel(self._h, c))
+                         for c, n in enumerate(self.sizes)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.channels = []
+            self._lib.msr_batch_destroy(h)
+            self._h = None
+
+    def _check(self, st):
+        if st != OK:
+            msg = self._lib.msr_batch_last_error(self._h)
+            raise MsrError(st, msg.decode() if msg else "")
+
+    def autotune(self, reps=10, stream=None):
+        self._check(self._lib.msr_batch_autotune(self._h, int(reps), _stream(stream)))
+
+    def solve(self, step, lambdas, iters, low_res=None, x0=None, out=None, stream=None):
+        """Runs `iters` iterations of `step` on every channel; returns (models, results)."""
+        import torch
+
+        C_ = len(self.sizes)
+        lam = (C.c_double * C_)(*[float(v) for v in lambdas])
+        outs = out if out is not None else [torch.empty((n, n), dtype=self.dtype, device=self.device)
+                                            for n in self.sizes]
+
+        def arr(ts):
+            if ts is None:
+                return None
+            return (_P * C_)(*[_ptr(t, self.dtype) for t in ts])
+
+        res = (Result * C_)()
+        self._check(self._lib.msr_batch_solve(self._h, int(step), lam, int(iters), arr(low_res), arr(x0),
+                                              arr(outs), res, _stream(stream)))
+        return outs, [res[c] for c in range(C_)]

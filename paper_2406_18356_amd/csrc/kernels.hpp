@@ -23,6 +23,8 @@
 // Reductions (objective terms, power-iteration sums) are FP64 per-block
 // partials, computed only when the launch asks for them (`reduce`).
 #pragma once
+#include <cstdint>
+
 #include "fft_engine.hpp"
 
 namespace msr {
@@ -53,6 +55,27 @@ __device__ __forceinline__ size_t spec_idx(int kx, int row, int NR, int T) {
 }
 
 // ===========================================================================
+// Batched launches.  The channels of one launch (blockIdx.y) have identical
+// workspace layouts spaced `cstride` bytes apart, so every workspace pointer of
+// channel c is the first channel's plus c * cstride; what differs in value per
+// channel (step size, threshold, filters) comes from small per-channel arrays.
+// ===========================================================================
+template <typename R>
+struct ChanScalars {
+    R two_mu;      // 2 mu
+    R thr;         // mu lambda
+    R inv_sigma2;  // 1 / sigma^2 (step 2)
+    R unused;
+};
+template <typename R>
+struct FilterCoef;
+
+template <typename T>
+__device__ __forceinline__ T* shifted(T* p, long long off) {
+    return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + off) : p;
+}
+
+// ===========================================================================
 // Row pass
 // ===========================================================================
 template <typename R>
@@ -68,6 +91,16 @@ struct RowArgs {
     int K_in2;                       // columns of spec_in2 (0: none)
     int K_out;                       // columns to write (the tile tail is zero-filled)
     int reduce;                      // accumulate the epilogue's FP64 sums
+    int nch;                         // channels of a batched launch (grid y); 0 or 1: one
+    long long cstride;               // batched: bytes between two channels' workspaces (0: not batched)
+    const ChanScalars<R>* __restrict__ chan;  // batched: per-channel scalars (or null)
+    __device__ __forceinline__ void to_channel(long long off) {
+        spec_in = shifted(spec_in, off);
+        spec_in2 = shifted(spec_in2, off);
+        spec_out = shifted(spec_out, off);
+        tw = shifted(tw, off);
+        partials = shifted(partials, off);
+    }
 };
 
 // Waves per SIMD the register allocation is made for: what the LDS footprint
@@ -85,7 +118,7 @@ constexpr int waves_per_eu() {
 template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
 __global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R, EMAX>::TPF))
 MSR_WAVES_ATTR(EMAX, R)
-row_kernel(RowArgs<R> a, Epi epi) {
+row_kernel(RowArgs<R> a0, Epi epi0) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     using C = cplx<R>;
     constexpr int E = Cf::E, TPF = Cf::TPF, NH = Cf::NH, PT = Cf::PT, HALF = Cf::HALF;
@@ -94,6 +127,15 @@ row_kernel(RowArgs<R> a, Epi epi) {
     constexpr int NQ = Epi::NQ;
     __shared__ C lds[PAIRS * ZLEN];
     __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
+
+    RowArgs<R> a = a0;
+    Epi epi = epi0;
+    if (a.cstride) {
+        const long long off = (long long)blockIdx.y * a.cstride;
+        a.to_channel(off);
+        epi.to_channel(off);
+    }
+    if (a.chan) epi.use(a.chan[blockIdx.y]);
 
     const int tid = threadIdx.x;
     const int pair = tid / TPF;
@@ -252,6 +294,8 @@ struct EpiLoad {
     const R* __restrict__ img;
     int ld;
     R scale;
+    __device__ __forceinline__ void to_channel(long long off) { img = shifted(img, off); }
+    __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R>, double*) const {
         return mk<cplx<R>>(scale * img[(size_t)r * ld + i], scale * img[(size_t)(r + 1) * ld + i]);
     }
@@ -263,6 +307,8 @@ struct EpiLoadShift {
     static constexpr int NQ = 0;
     const R* __restrict__ img;
     int P;
+    __device__ __forceinline__ void to_channel(long long off) { img = shifted(img, off); }
+    __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R>, double*) const {
         const int h = P / 2;
         const int c = (i + h) & (P - 1);
@@ -277,6 +323,8 @@ struct EpiStore {
     R* __restrict__ out;
     int ld;
     R scale;
+    __device__ __forceinline__ void to_channel(long long off) { out = shifted(out, off); }
+    __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double*) const {
         out[(size_t)r * ld + i] = scale * z.x;
         out[(size_t)(r + 1) * ld + i] = scale * z.y;
@@ -291,6 +339,11 @@ struct EpiResid {
     const R* __restrict__ y;
     R* __restrict__ r_out;
     int ld;
+    __device__ __forceinline__ void to_channel(long long off) {
+        y = shifted(y, off);
+        r_out = shifted(r_out, off);
+    }
+    __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc) const {
         if (y) {
             z.x -= y[(size_t)r * ld + i];
@@ -320,6 +373,14 @@ struct EpiUpdate {
     R thr;        // mu * lambda
     R t_prev, t_cur;
     int positivity;
+    __device__ __forceinline__ void to_channel(long long off) {
+        b1 = shifted(b1, off);
+        b2 = shifted(b2, off);
+    }
+    __device__ __forceinline__ void use(const ChanScalars<R>& c) {
+        two_mu = c.two_mu;
+        thr = c.thr;
+    }
     __device__ __forceinline__ R upd(R s, R p1, R& p2) const {
         const R alpha = fmaR(t_prev, p1 - p2, p1);
         const R zz = fmaR(-two_mu, s, alpha);
@@ -350,6 +411,11 @@ struct EpiPower {
     R* __restrict__ w_out;
     int ld;
     R vscale;  // v = vscale * vprev
+    __device__ __forceinline__ void to_channel(long long off) {
+        vprev = shifted(vprev, off);
+        w_out = shifted(w_out, off);
+    }
+    __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc) const {
         const size_t ia = (size_t)r * ld + i, ib = ia + ld;
         acc[0] += (double)z.x * z.x + (double)z.y * z.y;
@@ -376,7 +442,31 @@ struct ColArgs {
     int K;       // columns processed: tiles 0 .. ceil(K/T)-1; columns >= K read as zero
     int reduce;  // accumulate the mode's FP64 sums
     R in_scale;  // the transformed column is in_scale * spec_in - spec_in2
+    int nch;                                    // channels of a batched launch (grid y); 0 or 1: one
+    int chan_scale;                             // batched: in_scale = chan[c].inv_sigma2
+    long long cstride;                          // batched: bytes between two channels' workspaces
+    const ChanScalars<R>* __restrict__ chan;    // batched: per-channel scalars (or null)
+    const FilterCoef<R>* __restrict__ chanf;    // batched: per-channel filters (or null)
+    __device__ __forceinline__ void to_channel(long long off) {
+        spec_in = shifted(spec_in, off);
+        spec_in2 = shifted(spec_in2, off);
+        spec_out = shifted(spec_out, off);
+        tw = shifted(tw, off);
+        partials = shifted(partials, off);
+    }
 };
+
+// Moves a column launch's arguments to channel blockIdx.y of a batched launch.
+template <typename R, class Mode>
+__device__ __forceinline__ void col_channel(ColArgs<R>& a, Mode& md) {
+    if (a.cstride) {
+        const long long off = (long long)blockIdx.y * a.cstride;
+        a.to_channel(off);
+        md.to_channel(off);
+    }
+    if (a.chan && a.chan_scale) a.in_scale = a.chan[blockIdx.y].inv_sigma2;
+    if (a.chanf) md.use(a.chanf[blockIdx.y]);
+}
 
 // A block transforms CB adjacent columns (CB divides the tile width T): logical
 // block b covers columns b*CB .. b*CB + CB - 1 of tile (b*CB)/T.
@@ -461,12 +551,15 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
 template <typename R, int L, bool PADDED, int EMAX, int T, int CB, class Mode>
 __global__ void __launch_bounds__((CB * LineCfg<L, PADDED, R, EMAX>::TPF))
 MSR_WAVES_ATTR(EMAX, R)
-col_kernel(ColArgs<R> a, Mode md) {
+col_kernel(ColArgs<R> a0, Mode m0) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     constexpr int NT = CB * Cf::TPF;
     constexpr int NQ = Mode::NQ;
     __shared__ cplx<R> lds[Cf::NH * CB * padded_len(L)];
     __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
+    ColArgs<R> a = a0;
+    Mode md = m0;
+    col_channel(a, md);
     col_body<R, L, PADDED, EMAX, T, CB, Mode>(a, md, xcd_block(blockIdx.x, gridDim.x), blockIdx.x, lds, red);
 }
 
@@ -477,6 +570,8 @@ template <typename R, int L, bool PADDED, int EMAX, int T, int CB, class M1, cla
 __global__ void __launch_bounds__((CB * LineCfg<L, PADDED, R, EMAX>::TPF))
 MSR_WAVES_ATTR(EMAX, R)
 col_dual_kernel(ColArgs<R> a1, M1 m1, int g1, ColArgs<R> a2, M2 m2) {
+    col_channel(a1, m1);
+    col_channel(a2, m2);
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     constexpr int NT = CB * Cf::TPF;
     constexpr int NQ = M1::NQ > M2::NQ ? M1::NQ : M2::NQ;
@@ -497,6 +592,8 @@ struct ModePsf {
     const R* __restrict__ hh;
     int P;
     int T;
+    __device__ __forceinline__ void to_channel(long long off) { hh = shifted(hh, off); }
+    __device__ __forceinline__ void use(const FilterCoef<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int tile, int c, int, int ky, bool, cplx<R> y, double*) const {
         return cscale(y, hh[((size_t)tile * P + ky) * T + c]);
     }
@@ -558,6 +655,8 @@ struct ModeFilterW {
     static constexpr bool STORE_SPECTRUM = false;
     FilterCoef<R> f;
     R inv_p2;
+    __device__ __forceinline__ void to_channel(long long) {}
+    __device__ __forceinline__ void use(const FilterCoef<R>& c) { f = c; }
     __device__ __forceinline__ cplx<R> apply(int, int, int kx, int ky, bool acc_on, cplx<R> y, double* acc) const {
         const R g = f.inv_sigma2 - f.sq(kx, ky).y;
         if (acc_on) acc[0] += col_weight(kx, f.P) * (double)g * ((double)y.x * y.x + (double)y.y * y.y);
@@ -574,6 +673,8 @@ struct ModeFilterL {
     static constexpr bool STORE_SPECTRUM = false;
     FilterCoef<R> f;
     R inv_p2;
+    __device__ __forceinline__ void to_channel(long long) {}
+    __device__ __forceinline__ void use(const FilterCoef<R>& c) { f = c; }
     __device__ __forceinline__ cplx<R> apply(int, int, int kx, int ky, bool acc_on, cplx<R> y, double* acc) const {
         const R g = f.sq(kx, ky).x;
         if (acc_on) acc[0] += col_weight(kx, f.P) * (double)g * ((double)y.x * y.x + (double)y.y * y.y);
@@ -587,6 +688,8 @@ struct ModeForward {
     static constexpr int NQ = 0;
     static constexpr bool INVERSE = false;
     static constexpr bool STORE_SPECTRUM = true;
+    __device__ __forceinline__ void to_channel(long long) {}
+    __device__ __forceinline__ void use(const FilterCoef<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int, int, int, int, bool, cplx<R> y, double*) const { return y; }
 };
 

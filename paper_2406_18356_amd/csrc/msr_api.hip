@@ -242,6 +242,28 @@ struct Impl {
     const Ops<R>* opc_[2];  // N-length column passes per step
     const Ops<R>* opf_;     // step-2 low-band filter pass (C_w and C_{g_L^2} in one launch)
     const Ops<R>* opp;      // P-length unpadded (PSF spectrum)
+    // A batched group: nch_ channels whose workspaces follow this context's at
+    // cstride_ bytes; kept-column counts are the group's maxima (the PSF and
+    // filter factors are zero beyond each channel's own count).
+    int nch_ = 1;
+    long long cstride_ = 0;
+    const ChanScalars<R>* chan_ = nullptr;
+    const FilterCoef<R>* chanf_ = nullptr;
+    int gK_[2] = {0, 0}, gKL_ = 0;
+
+    void set_group(int nch, long long cstride, const ChanScalars<R>* chan, const FilterCoef<R>* chanf, int K1, int K2,
+                   int KL) {
+        nch_ = nch;
+        cstride_ = cstride;
+        chan_ = chan;
+        chanf_ = chanf;
+        gK_[0] = K1;
+        gK_[1] = K2;
+        gKL_ = KL;
+    }
+    bool grouped() const { return chan_ != nullptr; }
+    int Ks(int step) const { return grouped() ? gK_[step - 1] : c->K[step - 1]; }
+    int KLs() const { return grouped() ? gKL_ : c->KL; }
 
     static const Ops<R>* variant_or_default(int L, bool padded, int v) {
         const Ops<R>* o = ops_for<R>(L, padded, v);
@@ -304,6 +326,9 @@ struct Impl {
         a.K_in2 = in2 ? kin2 : 0;
         a.K_out = kout;
         a.reduce = reduce ? 1 : 0;
+        a.nch = nch_;
+        a.cstride = cstride_;
+        a.chan = chan_;
         return a;
     }
     ColArgs<R> col_args(const C* in, const C* in2, C* out, int K, bool reduce = false, R in_scale = (R)1) const {
@@ -317,11 +342,15 @@ struct Impl {
         a.NR = N();
         a.K = K;
         a.reduce = reduce ? 1 : 0;
+        a.nch = nch_;
+        a.cstride = cstride_;
+        a.chan = chan_;
+        a.chanf = chanf_;
         return a;
     }
     int row_grid(int step) const { return N() / opr(step)->row_rows; }
     int col_grid(int step, int K) const { return (K + opc(step)->col_cb - 1) / opc(step)->col_cb; }
-    int KA(int step) const { return step == 1 ? c->K[0] : std::max(c->K[1], c->KL); }
+    int KA(int step) const { return step == 1 ? Ks(1) : std::max(Ks(2), KLs()); }
 
     // Sum `nq` quantities over `nblocks` partial rows into scal[off..]; copies them to host.
     msr_status reduce(int nblocks, int nq, int off, double* host, hipStream_t s) {
@@ -350,9 +379,12 @@ struct Impl {
     }
 
     // out = IDFT_y(h_hat . DFT_y(in_scale * in - in2)) on the kept columns of PSF `step`.
-    msr_status col_psf(int step, const C* in, C* out, hipStream_t s, const C* in2 = nullptr, R in_scale = (R)1) {
-        opc(step)->col_psf(col_args(in, in2, out, c->K[step - 1], false, in_scale), ModePsf<R>{hh(step), P(), c->sh.T},
-                           s);
+    // chan_scale: in a batched group each channel takes in_scale = its 1 / sigma^2.
+    msr_status col_psf(int step, const C* in, C* out, hipStream_t s, const C* in2 = nullptr, R in_scale = (R)1,
+                       bool chan_scale = false) {
+        ColArgs<R> a = col_args(in, in2, out, Ks(step), false, in_scale);
+        a.chan_scale = chan_scale ? 1 : 0;
+        opc(step)->col_psf(a, ModePsf<R>{hh(step), P(), c->sh.T}, s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
@@ -371,7 +403,7 @@ struct Impl {
     msr_status col_filt_wl(const C* l, hipStream_t s) {
         const ModeFilterW<R> mw{filters(), inv_p2()};
         const ModeFilterL<R> ml{filters(), inv_p2()};
-        opf_->col_filt_wl(col_args(SC(), nullptr, SB(), c->KL), mw, col_args(SA(), l, SG(), c->KL), ml, s);
+        opf_->col_filt_wl(col_args(SC(), nullptr, SB(), KLs()), mw, col_args(SA(), l, SG(), KLs()), ml, s);
         LAUNCHCHK(c);
         return MSR_OK;
     }
@@ -381,20 +413,20 @@ struct Impl {
     // the data image (null for the normal operator alone); step 2 subtracts the
     // spectrum of l (SL) when `use_l`.
     msr_status grad_chain(int step, const R* y, bool use_l, hipStream_t s) {
-        const int Ks = c->K[step - 1];
+        const int K = Ks(step);
         TRY(col_psf(step, SA(), SB(), s));
         if (step == 1) {
-            opr(1)->row_resid_fwd(row_args(SB(), Ks, nullptr, 0, SC(), Ks), EpiResid<R>{y, nullptr, N()}, s);
+            opr(1)->row_resid_fwd(row_args(SB(), K, nullptr, 0, SC(), K), EpiResid<R>{y, nullptr, N()}, s);
             LAUNCHCHK(c);
             return col_psf(1, SC(), SB(), s);
         }
-        const int kr = std::max(Ks, c->KL);
-        opr(2)->row_resid_fwd(row_args(SB(), Ks, nullptr, 0, SC(), kr), EpiResid<R>{y, nullptr, N()}, s);
+        const int kr = std::max(K, KLs());
+        opr(2)->row_resid_fwd(row_args(SB(), K, nullptr, 0, SC(), kr), EpiResid<R>{y, nullptr, N()}, s);
         LAUNCHCHK(c);
         TRY(col_filt_wl(use_l ? SL() : nullptr, s));
-        opr(2)->row_resid_fwd(row_args(SB(), c->KL, nullptr, 0, SB(), Ks), EpiResid<R>{nullptr, nullptr, N()}, s);
+        opr(2)->row_resid_fwd(row_args(SB(), KLs(), nullptr, 0, SB(), K), EpiResid<R>{nullptr, nullptr, N()}, s);
         LAUNCHCHK(c);
-        return col_psf(2, SC(), SB(), s, SB(), (R)(1.0 / c->sigma2));
+        return col_psf(2, SC(), SB(), s, SB(), (R)(1.0 / c->sigma2), grouped());
     }
 
     static double momentum(int k) { return k >= 1 ? (k - 1.0) / (k + 2.0) : 0.0; }
@@ -411,9 +443,9 @@ struct Impl {
         u.t_prev = (R)momentum(k - 1);
         u.t_cur = (R)momentum(k);
         u.positivity = c->cfg.positivity;
-        const int Ks = c->K[step - 1];
-        RowArgs<R> a = step == 1 ? row_args(SB(), Ks, nullptr, 0, SA(), KA(1))
-                                 : row_args(SB(), Ks, SG(), c->KL, SA(), KA(2));
+        const int K = Ks(step);
+        RowArgs<R> a = step == 1 ? row_args(SB(), K, nullptr, 0, SA(), KA(1))
+                                 : row_args(SB(), K, SG(), KLs(), SA(), KA(2));
         opr(step)->row_update_fwd(a, u, s);
         LAUNCHCHK(c);
         return MSR_OK;
@@ -570,13 +602,23 @@ struct Impl {
                 if (cm[k] > thr) keep = k + 1;
         }
         c->K[step - 1] = keep;
+        // Pruned columns are exactly zero (a batched launch may cover more
+        // columns than this channel keeps).
+        if (keep < c->sh.Cpad) {
+            hipLaunchKernelGGL(zero_hh_cols<R>, dim3(blocks_for(Pn)), dim3(256), 0, s, h, Pn, c->sh.T, keep, c->sh.Cpad);
+            LAUNCHCHK(c);
+        }
         c->have_psf[step - 1] = true;
         c->have_theta[step - 1] = false;
         return MSR_OK;
     }
 
-    msr_status solve(int step, const msr_solve* opt, const R* low_res, const R* x0, R* model_out, R* image_out,
-                     msr_result* res, hipStream_t s) {
+    // Before the iterations of `step`: theta (power iteration unless set),
+    // beta_0 = beta_{-1} = x0 (or 0), the low-resolution constraint (step 2) and
+    // the spectrum of alpha_0.  Returns mu = 1 / theta.  ka / kl (0: this
+    // context's own counts) widen the spectra of alpha_0 and of the constraint
+    // to the columns a batched launch reads.
+    msr_status prepare(int step, const R* low_res, const R* x0, double* mu, hipStream_t s, int ka = 0, int kl = 0) {
         if (!c->have_theta[step - 1]) {
             double th = 0.0;
             TRY(power_iteration(step, 200, 1e-6, &th, nullptr, s));
@@ -584,8 +626,7 @@ struct Impl {
             c->theta[step - 1] = kThetaMargin * th;
             c->have_theta[step - 1] = true;
         }
-        const double theta = c->theta[step - 1];
-        const double mu = 1.0 / theta;
+        *mu = 1.0 / c->theta[step - 1];
         const size_t nb = c->sh.rs * c->sh.img_elems;
         if (x0) {
             HIPCHK(c, hipMemcpyAsync(beta(0), x0, nb, hipMemcpyDeviceToDevice, s));
@@ -593,8 +634,38 @@ struct Impl {
             HIPCHK(c, hipMemsetAsync(beta(0), 0, nb, s));
         }
         HIPCHK(c, hipMemcpyAsync(beta(1), beta(0), nb, hipMemcpyDeviceToDevice, s));
-        if (step == 2) TRY(set_low_res(low_res, s));
-        TRY(fwd_image(step, beta(0), (R)1, SA(), KA(step), s));
+        if (step == 2) TRY(fwd_image(2, low_res, (R)1, SL(), std::max(kl, KLs()), s));
+        return fwd_image(step, beta(0), (R)1, SA(), std::max(ka, KA(step)), s);
+    }
+
+    // After `done` iterations: the exact objective of beta_done (F, data term,
+    // l1 norm), the model copied out and, if asked, i_L = beta + (i~ - H beta).
+    msr_status finish(int step, double lambda, int done, R* model_out, R* image_out, double F[3], hipStream_t s) {
+        const size_t nb = c->sh.rs * c->sh.img_elems;
+        const R* bK = beta(done);
+        TRY(objective_at(step, lambda, bK, F, s));
+        if (!std::isfinite(F[0])) return fail(c, MSR_ERR_NUMERIC, "objective is not finite after %d iterations", done);
+        HIPCHK(c, hipMemcpyAsync(model_out, bK, nb, hipMemcpyDeviceToDevice, s));
+        if (image_out) {
+            // i_L = beta + (i~ - H beta) = beta - r
+            TRY(fwd_image(step, bK, (R)1, SB(), c->K[step - 1], s));
+            TRY(col_psf(step, SB(), SC(), s));
+            opr(step)->row_resid(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0),
+                                 EpiResid<R>{dirty(step), tmp(0), N()}, s);
+            LAUNCHCHK(c);
+            const size_t n = c->sh.img_elems;
+            hipLaunchKernelGGL(image_axpby<R>, dim3(blocks_for(n)), dim3(256), 0, s, image_out, bK, (const R*)tmp(0),
+                               (R)1, (R)-1, n);
+            LAUNCHCHK(c);
+        }
+        return MSR_OK;
+    }
+
+    msr_status solve(int step, const msr_solve* opt, const R* low_res, const R* x0, R* model_out, R* image_out,
+                     msr_result* res, hipStream_t s) {
+        double mu = 0.0;
+        TRY(prepare(step, low_res, x0, &mu, s));
+        const double theta = c->theta[step - 1];
 
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
@@ -635,22 +706,7 @@ struct Impl {
         hipEventDestroy(e1);
         if (res) res->iters = done;
         if (st != MSR_OK) return st;
-        const R* bK = beta(done);
-        TRY(objective_at(step, opt->lambda, bK, F, s));
-        if (!std::isfinite(F[0])) return fail(c, MSR_ERR_NUMERIC, "objective is not finite after %d iterations", done);
-        HIPCHK(c, hipMemcpyAsync(model_out, bK, nb, hipMemcpyDeviceToDevice, s));
-        if (image_out) {
-            // i_L = beta + (i~ - H beta) = beta - r
-            TRY(fwd_image(step, bK, (R)1, SB(), c->K[step - 1], s));
-            TRY(col_psf(step, SB(), SC(), s));
-            opr(step)->row_resid(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0), EpiResid<R>{dirty(step), tmp(0), N()},
-                          s);
-            LAUNCHCHK(c);
-            const size_t n = c->sh.img_elems;
-            hipLaunchKernelGGL(image_axpby<R>, dim3(blocks_for(n)), dim3(256), 0, s, image_out, bK, (const R*)tmp(0),
-                               (R)1, (R)-1, n);
-            LAUNCHCHK(c);
-        }
+        TRY(finish(step, opt->lambda, done, model_out, image_out, F, s));
         HIPCHK(c, hipStreamSynchronize(s));
         if (res) {
             res->iters = done;
@@ -1048,6 +1104,373 @@ msr_status msr_time_pass(msr_ctx* c, int step, int which, int reps, double* ms_o
     return with_impl(c, [&](auto& im) {
         return im.time_pass(which, step, reps, ms_out, bytes_out, flops_out, S(stream));
     });
+}
+
+}  // extern "C"
+
+// =============================================================================
+// Batched solves: many channels (frequency channels of one observation, each
+// its own two-step problem) advanced together.  Channels of equal image size
+// form a group; a group's workspaces are laid out back to back with one
+// stride, so each pass of an iteration is ONE launch for the whole group
+// (grid y = channel).  The fixed-count iteration loop of all groups is
+// captured once into a HIP graph (one branch per group, so groups of
+// different sizes overlap) and replayed.
+// =============================================================================
+struct msr_batch {
+    struct Group {
+        std::vector<int> members;  // channel indices, all of one image size
+        size_t base = 0;           // workspace offset of the first member
+        size_t stride = 0;         // bytes between consecutive members
+        size_t chan_off = 0;       // ChanScalars[members]
+        size_t chanf_off = 0;      // FilterCoef[members]
+    };
+    std::vector<msr_ctx*> ch;
+    std::vector<Group> groups;
+    int prec = 32, device = 0;
+    size_t total = 0;
+    char* ws = nullptr;
+    static constexpr int kStreams = 4;
+    hipStream_t st[kStreams] = {};
+    hipEvent_t fork = nullptr, join[kStreams] = {}, t0 = nullptr, t1 = nullptr, done = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<long long> key;      // what the cached graph was captured for
+    std::string err;
+};
+
+namespace {
+
+msr_status bfail(msr_batch* b, msr_status s, const char* fmt, ...) {
+    if (b) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        b->err = buf;
+    }
+    return s;
+}
+
+#define BHIPCHK(b, expr)                                                                              \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return bfail(b, MSR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// A failure inside a channel: keep the channel's message.
+msr_status bchan(msr_batch* b, int c, msr_status s) {
+    if (s != MSR_OK && b) b->err = "channel " + std::to_string(c) + ": " + b->ch[c]->err;
+    return s;
+}
+
+template <typename R>
+size_t param_bytes(size_t nch) {
+    return align_up(nch * sizeof(ChanScalars<R>), kAlign) + align_up(nch * sizeof(FilterCoef<R>), kAlign);
+}
+
+// Groups (largest images first) and the workspace layout of a batch.
+bool plan_batch(int nch, const msr_config* cfgs, std::vector<msr_batch::Group>& groups, size_t& total,
+                std::string* why) {
+    if (nch <= 0 || !cfgs) {
+        if (why) *why = "need at least one channel";
+        return false;
+    }
+    for (int i = 0; i < nch; ++i) {
+        Shapes s;
+        if (!make_shapes(&cfgs[i], s, why)) return false;
+        if (cfgs[i].pad != cfgs[0].pad || cfgs[i].precision != cfgs[0].precision ||
+            cfgs[i].positivity != cfgs[0].positivity || cfgs[i].device != cfgs[0].device) {
+            if (why) *why = "all channels need the same pad, precision, positivity and device";
+            return false;
+        }
+    }
+    std::vector<int> order(nch);
+    for (int i = 0; i < nch; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cfgs[a].n > cfgs[b].n; });
+    groups.clear();
+    for (int i : order) {
+        if (groups.empty() || cfgs[groups.back().members[0]].n != cfgs[i].n) groups.emplace_back();
+        groups.back().members.push_back(i);
+    }
+    size_t off = 0;
+    for (auto& g : groups) {
+        Shapes s;
+        make_shapes(&cfgs[g.members[0]], s, nullptr);
+        g.base = off;
+        g.stride = align_up(make_layout(s).total, kAlign);
+        off += g.stride * g.members.size();
+    }
+    for (auto& g : groups) {
+        const size_t m = g.members.size();
+        g.chan_off = off;
+        const size_t pb = cfgs[0].precision == 64 ? param_bytes<double>(m) : param_bytes<float>(m);
+        g.chanf_off = off + (cfgs[0].precision == 64 ? align_up(m * sizeof(ChanScalars<double>), kAlign)
+                                                     : align_up(m * sizeof(ChanScalars<float>), kAlign));
+        off += pb;
+    }
+    total = off;
+    return true;
+}
+
+void drop_graph(msr_batch* b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->key.clear();
+}
+
+template <typename R>
+struct BatchImpl {
+    msr_batch* b;
+
+    // Group g's launches: the first member's context, spread over the group.
+    Impl<R> group_impl(const msr_batch::Group& g) const {
+        msr_ctx* c0 = b->ch[g.members[0]];
+        Impl<R> im(c0);
+        int K1 = 0, K2 = 0, KL = 0;
+        for (int m : g.members) {
+            K1 = std::max(K1, b->ch[m]->K[0]);
+            K2 = std::max(K2, b->ch[m]->K[1]);
+            KL = std::max(KL, b->ch[m]->KL);
+        }
+        im.set_group((int)g.members.size(), (long long)g.stride,
+                     reinterpret_cast<const ChanScalars<R>*>(b->ws + g.chan_off),
+                     reinterpret_cast<const FilterCoef<R>*>(b->ws + g.chanf_off), K1, K2, KL);
+        return im;
+    }
+
+    std::vector<long long> graph_key(int step, int iters) const {
+        std::vector<long long> k{step, iters};
+        for (const auto& g : b->groups) {
+            Impl<R> im = group_impl(g);
+            msr_ctx* c0 = b->ch[g.members[0]];
+            k.insert(k.end(), {(long long)g.members.size(), im.Ks(1), im.Ks(2), im.KLs(), c0->var_row[step - 1],
+                               c0->var_col[step - 1], c0->var_filt});
+        }
+        return k;
+    }
+
+    // Captures `iters` iterations of every group into b->exec.
+    msr_status capture(int step, int iters) {
+        hipStream_t s0 = b->st[0];
+        BHIPCHK(b, hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+        msr_status st = MSR_OK;
+        const int ns = std::min<int>((int)b->groups.size(), msr_batch::kStreams);
+        if (hipEventRecord(b->fork, s0) != hipSuccess) st = bfail(b, MSR_ERR_HIP, "fork event");
+        for (int i = 1; i < ns && st == MSR_OK; ++i)
+            if (hipStreamWaitEvent(b->st[i], b->fork, 0) != hipSuccess) st = bfail(b, MSR_ERR_HIP, "fork wait");
+        for (size_t gi = 0; gi < b->groups.size() && st == MSR_OK; ++gi) {
+            Impl<R> im = group_impl(b->groups[gi]);
+            hipStream_t s = b->st[gi % ns];
+            for (int k = 1; k <= iters && st == MSR_OK; ++k) st = bchan(b, b->groups[gi].members[0], im.iterate(step, k, 0.0, 0.0, s));
+        }
+        for (int i = 1; i < ns && st == MSR_OK; ++i) {
+            if (hipEventRecord(b->join[i], b->st[i]) != hipSuccess || hipStreamWaitEvent(s0, b->join[i], 0) != hipSuccess)
+                st = bfail(b, MSR_ERR_HIP, "join");
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s0, &graph);
+        if (st == MSR_OK && ee != hipSuccess) st = bfail(b, MSR_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+        if (st == MSR_OK) {
+            const hipError_t ei = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                b->exec = nullptr;
+                st = bfail(b, MSR_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+            }
+        }
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+
+    msr_status solve(int step, const double* lambda, int iters, const void* const* low_res, const void* const* x0,
+                     void* const* model_out, msr_result* res, hipStream_t s) {
+        const int C = (int)b->ch.size();
+        // 1. per channel: theta, beta_0, constraint, spectrum of alpha_0 (on
+        //    every column its group's launches read: nothing unwritten is read,
+        //    not even where a zero factor would cancel it)
+        std::vector<double> mu(C);
+        for (const auto& g : b->groups) {
+            const Impl<R> gi = group_impl(g);
+            for (int c : g.members) {
+                Impl<R> im(b->ch[c]);
+                TRY(bchan(b, c, im.prepare(step, step == 2 ? static_cast<const R*>(low_res[c]) : nullptr,
+                                           x0 ? static_cast<const R*>(x0[c]) : nullptr, &mu[c], s, gi.KA(step),
+                                           gi.KLs())));
+            }
+        }
+        // 2. per-channel parameters of every group
+        for (const auto& g : b->groups) {
+            const size_t m = g.members.size();
+            std::vector<ChanScalars<R>> cs(m);
+            std::vector<FilterCoef<R>> cf(m);
+            for (size_t j = 0; j < m; ++j) {
+                const int c = g.members[j];
+                cs[j].two_mu = (R)(2.0 * mu[c]);
+                cs[j].thr = (R)(mu[c] * lambda[c]);
+                cs[j].inv_sigma2 = step == 2 ? (R)(1.0 / b->ch[c]->sigma2) : (R)1;
+                cs[j].unused = (R)0;
+                if (step == 2) cf[j] = Impl<R>(b->ch[c]).filters();
+            }
+            BHIPCHK(b, hipMemcpyAsync(b->ws + g.chan_off, cs.data(), m * sizeof(ChanScalars<R>), hipMemcpyHostToDevice, s));
+            BHIPCHK(b, hipMemcpyAsync(b->ws + g.chanf_off, cf.data(), m * sizeof(FilterCoef<R>), hipMemcpyHostToDevice, s));
+            BHIPCHK(b, hipStreamSynchronize(s));  // the host arrays go out of scope
+        }
+        // 3. the iterations: one graph for all groups
+        float ms = 0.f;
+        if (iters > 0) {
+            const std::vector<long long> key = graph_key(step, iters);
+            if (!b->exec || key != b->key) {
+                drop_graph(b);
+                TRY(capture(step, iters));
+                b->key = key;
+            }
+            BHIPCHK(b, hipEventRecord(b->done, s));
+            BHIPCHK(b, hipStreamWaitEvent(b->st[0], b->done, 0));
+            BHIPCHK(b, hipEventRecord(b->t0, b->st[0]));
+            BHIPCHK(b, hipGraphLaunch(b->exec, b->st[0]));
+            BHIPCHK(b, hipEventRecord(b->t1, b->st[0]));
+            BHIPCHK(b, hipStreamWaitEvent(s, b->t1, 0));
+            BHIPCHK(b, hipEventSynchronize(b->t1));
+            BHIPCHK(b, hipEventElapsedTime(&ms, b->t0, b->t1));
+        }
+        // 4. per channel: objective, model out
+        for (int c = 0; c < C; ++c) {
+            Impl<R> im(b->ch[c]);
+            double F[3] = {0, 0, 0};
+            TRY(bchan(b, c, im.finish(step, lambda[c], iters, static_cast<R*>(model_out[c]), nullptr, F, s)));
+            if (res) {
+                res[c].iters = iters;
+                res[c].converged = 0;
+                res[c].objective = F[0];
+                res[c].data_term = F[1];
+                res[c].l1_norm = F[2];
+                res[c].theta = b->ch[c]->theta[step - 1];
+                res[c].elapsed_ms = ms;
+                res[c].time_to_tol_ms = -1.0;
+            }
+        }
+        BHIPCHK(b, hipStreamSynchronize(s));
+        return MSR_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t msr_batch_workspace_bytes(int channels, const msr_config* cfgs) {
+    std::vector<msr_batch::Group> g;
+    size_t total = 0;
+    if (!plan_batch(channels, cfgs, g, total, nullptr)) return 0;
+    return total;
+}
+
+msr_status msr_batch_init(int channels, const msr_config* cfgs, msr_batch** out) {
+    if (!out) return MSR_ERR_INVALID;
+    *out = nullptr;
+    std::vector<msr_batch::Group> groups;
+    size_t total = 0;
+    if (!plan_batch(channels, cfgs, groups, total, nullptr)) return MSR_ERR_INVALID;
+    msr_batch* b = new (std::nothrow) msr_batch();
+    if (!b) return MSR_ERR_OOM;
+    b->groups = std::move(groups);
+    b->total = total;
+    b->prec = cfgs[0].precision;
+    b->device = cfgs[0].device;
+    b->ch.assign(channels, nullptr);
+    for (int i = 0; i < channels; ++i) {
+        const msr_status st = msr_init(&cfgs[i], &b->ch[i]);
+        if (st != MSR_OK) {
+            msr_batch_destroy(b);
+            return st;
+        }
+    }
+    bool ok = hipSetDevice(b->device) == hipSuccess;
+    for (int i = 0; i < msr_batch::kStreams && ok; ++i)
+        ok = hipStreamCreateWithFlags(&b->st[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&b->done, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreate(&b->t0) == hipSuccess && hipEventCreate(&b->t1) == hipSuccess;
+    if (!ok) {
+        msr_batch_destroy(b);
+        return MSR_ERR_HIP;
+    }
+    *out = b;
+    return MSR_OK;
+}
+
+void msr_batch_destroy(msr_batch* b) {
+    if (!b) return;
+    hipSetDevice(b->device);
+    drop_graph(b);
+    for (int i = 0; i < msr_batch::kStreams; ++i) {
+        if (b->st[i]) hipStreamDestroy(b->st[i]);
+        if (b->join[i]) hipEventDestroy(b->join[i]);
+    }
+    for (hipEvent_t e : {b->fork, b->done, b->t0, b->t1})
+        if (e) hipEventDestroy(e);
+    for (msr_ctx* c : b->ch) msr_destroy(c);
+    delete b;
+}
+
+const char* msr_batch_last_error(const msr_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+int msr_batch_channels(const msr_batch* b) { return b ? (int)b->ch.size() : 0; }
+
+msr_ctx* msr_batch_channel(msr_batch* b, int c) {
+    if (!b || c < 0 || c >= (int)b->ch.size()) return nullptr;
+    return b->ch[c];
+}
+
+msr_status msr_batch_set_workspace(msr_batch* b, void* dev, size_t bytes) {
+    if (!b) return MSR_ERR_INVALID;
+    if (!dev || bytes < b->total) return bfail(b, MSR_ERR_OOM, "workspace needs %zu bytes", b->total);
+    if (reinterpret_cast<uintptr_t>(dev) % kAlign) return bfail(b, MSR_ERR_INVALID, "workspace must be 256-byte aligned");
+    drop_graph(b);
+    b->ws = static_cast<char*>(dev);
+    for (const auto& g : b->groups)
+        for (size_t j = 0; j < g.members.size(); ++j) {
+            const int c = g.members[j];
+            TRY(bchan(b, c, msr_set_workspace(b->ch[c], b->ws + g.base + j * g.stride, g.stride)));
+        }
+    return MSR_OK;
+}
+
+msr_status msr_batch_autotune(msr_batch* b, int reps, void* stream) {
+    if (!b || !b->ws) return b ? bfail(b, MSR_ERR_OOM, "no workspace") : MSR_ERR_INVALID;
+    for (const auto& g : b->groups) {
+        msr_ctx* c0 = b->ch[g.members[0]];
+        TRY(bchan(b, g.members[0], msr_autotune(c0, reps, nullptr, nullptr, nullptr, stream)));
+        for (int m : g.members) {
+            b->ch[m]->var_row[0] = c0->var_row[0];
+            b->ch[m]->var_row[1] = c0->var_row[1];
+            b->ch[m]->var_col[0] = c0->var_col[0];
+            b->ch[m]->var_col[1] = c0->var_col[1];
+            b->ch[m]->var_filt = c0->var_filt;
+        }
+    }
+    drop_graph(b);
+    return MSR_OK;
+}
+
+msr_status msr_batch_solve(msr_batch* b, int step, const double* lambda, int iters, const void* const* low_res,
+                           const void* const* x0, void* const* model_out, msr_result* res, void* stream) {
+    if (!b) return MSR_ERR_INVALID;
+    if (!b->ws) return bfail(b, MSR_ERR_OOM, "no workspace");
+    if (step != 1 && step != 2) return bfail(b, MSR_ERR_INVALID, "step must be 1 or 2");
+    if (!lambda || !model_out || iters < 0 || (step == 2 && !low_res)) return bfail(b, MSR_ERR_INVALID, "bad arguments");
+    for (size_t c = 0; c < b->ch.size(); ++c) {
+        msr_ctx* cx = b->ch[c];
+        if (!cx->have_psf[step - 1]) return bfail(b, MSR_ERR_STATE, "channel %zu: set_dirty_psf(%d) first", c, step);
+        if (step == 2 && (!cx->have_filters || !low_res[c]))
+            return bfail(b, MSR_ERR_STATE, "channel %zu: step 2 needs filters and low_res", c);
+        if (!model_out[c] || !(lambda[c] >= 0) || !std::isfinite(lambda[c]))
+            return bfail(b, MSR_ERR_INVALID, "channel %zu: bad lambda or output", c);
+    }
+    BHIPCHK(b, hipSetDevice(b->device));
+    if (b->prec == 64) return BatchImpl<double>{b}.solve(step, lambda, iters, low_res, x0, model_out, res, S(stream));
+    return BatchImpl<float>{b}.solve(step, lambda, iters, low_res, x0, model_out, res, S(stream));
 }
 
 }  // extern "C"

@@ -9,6 +9,9 @@
 namespace msr {
 namespace {
 
+// Grid y of a launch: the channels of a batched launch, else one.
+inline unsigned chans(int nch) { return nch > 1 ? (unsigned)nch : 1u; }
+
 template <typename R, int L, bool PADDED, int EMAX, bool ONECOL>
 struct Inst {
     static constexpr int ES = (int)sizeof(cplx<R>);
@@ -22,13 +25,15 @@ struct Inst {
     template <bool INV_IN, bool FWD_OUT, class Epi>
     static void row(const RowArgs<R>& a, const Epi& e, hipStream_t s) {
         const int grid = a.NR / (2 * PAIRS);
-        hipLaunchKernelGGL((row_kernel<R, L, PADDED, EMAX, PAIRS, T, INV_IN, FWD_OUT, Epi>), dim3(grid), dim3(RT), 0, s, a, e);
+        hipLaunchKernelGGL((row_kernel<R, L, PADDED, EMAX, PAIRS, T, INV_IN, FWD_OUT, Epi>), dim3(grid, chans(a.nch)),
+                           dim3(RT), 0, s, a, e);
     }
     template <class Mode>
     static void col(const ColArgs<R>& a, const Mode& m, hipStream_t s) {
         const int grid = (a.K + CB - 1) / CB;
         if (grid <= 0) return;
-        hipLaunchKernelGGL((col_kernel<R, L, PADDED, EMAX, T, CB, Mode>), dim3(grid), dim3(CT), 0, s, a, m);
+        hipLaunchKernelGGL((col_kernel<R, L, PADDED, EMAX, T, CB, Mode>), dim3(grid, chans(a.nch)), dim3(CT), 0, s, a,
+                           m);
     }
 
     template <class M1, class M2>
@@ -36,8 +41,8 @@ struct Inst {
         const int g1 = (a1.K + CB - 1) / CB;
         const int g2 = (a2.K + CB - 1) / CB;
         if (g1 + g2 <= 0) return;
-        hipLaunchKernelGGL((col_dual_kernel<R, L, PADDED, EMAX, T, CB, M1, M2>), dim3(g1 + g2), dim3(CT), 0, s, a1, m1,
-                           g1, a2, m2);
+        hipLaunchKernelGGL((col_dual_kernel<R, L, PADDED, EMAX, T, CB, M1, M2>), dim3(g1 + g2, chans(a1.nch)), dim3(CT),
+                           0, s, a1, m1, g1, a2, m2);
     }
 
     static Ops<R> make(bool full) {

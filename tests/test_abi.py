@@ -75,3 +75,30 @@ def test_init_rejects_bad_config_before_touching_a_device(lib):
     assert not h.value
     lib.msr_destroy(None)
     assert lib.msr_last_error(None) == b"null context"
+
+
+def test_batch_workspace_bytes_host_only(lib):
+    from paper_2406_18356_amd import binding
+
+    def ws(sizes, **kw):
+        cfgs = (binding.Config * len(sizes))(*[binding._cfg(n, **kw) for n in sizes])
+        return int(lib.msr_batch_workspace_bytes(len(sizes), cfgs))
+
+    one = {n: binding.workspace_bytes(n) for n in (64, 128, 256)}
+    tot = ws([256, 64, 128, 64])
+    # every channel's own workspace plus a small per-channel parameter area
+    assert sum(one[n] for n in (256, 64, 128, 64)) <= tot <= sum(one[n] for n in (256, 64, 128, 64)) + 4 * 4096
+    assert ws([64]) >= one[64]
+    assert ws([]) == 0
+    assert ws([64, 12]) == 0  # one invalid channel
+    cfgs = (binding.Config * 2)(binding._cfg(64), binding._cfg(64, pad=1))
+    assert lib.msr_batch_workspace_bytes(2, cfgs) == 0  # mixed padding
+    cfgs = (binding.Config * 2)(binding._cfg(64), binding._cfg(64, precision=64))
+    assert lib.msr_batch_workspace_bytes(2, cfgs) == 0  # mixed precision
+    h = C.c_void_p(1)
+    assert lib.msr_batch_init(2, cfgs, C.byref(h)) == binding.ERR_INVALID
+    assert not h.value
+    lib.msr_batch_destroy(None)
+    assert lib.msr_batch_last_error(None) == b"null batch"
+    assert lib.msr_batch_channels(None) == 0
+    assert lib.msr_batch_channel(None, 0) is None
