@@ -26,6 +26,7 @@ from .generator import (
     preset,
     PRESETS,
     tiny,
+    channel_set,
 )
 
 __all__ = [
@@ -42,4 +43,5 @@ __all__ = [
     "preset",
     "PRESETS",
     "tiny",
+    "channel_set",
 ]

@@ -326,6 +326,31 @@ def preset(name: str, **overrides) -> ProblemConfig:
     return cfg.replace(**overrides) if overrides else cfg
 
 
+def channel_set(count: int, sizes=(512, 1024, 2048, 4096), seed: int = 4, cut: float = 0.15,
+                nu_lo: float = 350.0, nu_hi: float = 1050.0, n_ant: int = 64, hours: float = 4.0,
+                dt_s: float = 120.0) -> list:
+    """Frequency channels of one observation with uneven image sizes.
+
+    Channel c observes at nu_c = nu_lo + (nu_hi - nu_lo) c / (count - 1) MHz
+    with one array layout; baselines in wavelengths scale with nu, so its
+    longest baseline lands at (nu_c / nu_hi) P/4 cells and its cut is taken
+    from that radius.  Image sizes are drawn uniformly from `sizes`; the sky
+    density (sources per pixel) is that of the small preset.
+    """
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(sizes), size=count)
+    out = []
+    for c, n in enumerate(ns):
+        nu = nu_lo + (nu_hi - nu_lo) * c / max(count - 1, 1)
+        dens = (int(n) / 256.0) ** 2
+        out.append(ProblemConfig(
+            n=int(n), sky=SkyConfig(max(2, int(20 * dens)), max(1, int(3 * dens))),
+            array=ArrayConfig(n_ant, hours, dt_s, layout_seed=seed), cut=cut, uv_fill=0.25 * nu / nu_hi,
+            seed=1000 * seed + c, iters=500,
+        ))
+    return out
+
+
 def tiny(n: int, seed: int = 11, cut: float = 0.25, n_ant: int = 16) -> ProblemConfig:
     """A small problem for tests: density ~ that of the small preset."""
     pts = max(2, (20 * n * n) // (256 * 256))
