@@ -15,6 +15,9 @@ from .binding import (  # noqa: F401
     Result,
     Solver,
     Batch,
+    UNet,
+    unet_layers,
+    unet_init_params,
     lib,
     library_path,
     abi_version,

@@ -64,6 +64,14 @@ class Result(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class UNetConfig(C.Structure):
+    _fields_ = [("in_channels", C.c_int32), ("base_width", C.c_int32), ("levels", C.c_int32), ("device", C.c_int32)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 # exported symbol -> (restype, argtypes)
 _P = C.c_void_p
 _ST = C.c_int
@@ -99,6 +107,17 @@ SYMBOLS = {
     "msr_batch_autotune": (_ST, [_P, C.c_int, _P]),
     "msr_batch_solve": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(_P), C.POINTER(_P),
                               C.POINTER(_P), C.POINTER(Result), _P]),
+    "msr_unet_param_count": (C.c_size_t, [C.POINTER(UNetConfig)]),
+    "msr_unet_workspace_bytes": (C.c_size_t, [C.POINTER(UNetConfig), C.c_int, C.c_int, C.c_int]),
+    "msr_unet_init": (_ST, [C.POINTER(UNetConfig), C.POINTER(_P)]),
+    "msr_unet_destroy": (None, [_P]),
+    "msr_unet_last_error": (C.c_char_p, [_P]),
+    "msr_unet_set_workspace": (_ST, [_P, _P, C.c_size_t, C.c_int, C.c_int, C.c_int]),
+    "msr_unet_set_params": (_ST, [_P, _P, _P]),
+    "msr_unet_get_params": (_ST, [_P, _P, _P]),
+    "msr_unet_forward": (_ST, [_P, _P, _P, _P, C.c_int, _P]),
+    "msr_unet_loss_grad": (_ST, [_P, _P, _P, _P, C.c_int, C.POINTER(C.c_double), _P, _P]),
+    "msr_unet_train_step": (_ST, [_P, _P, _P, _P, C.c_int, C.POINTER(Adam), C.POINTER(C.c_double), _P]),
 }
 
 _lib = None
@@ -368,3 +387,124 @@ class Batch:
         self._check(self._lib.msr_batch_solve(self._h, int(step), lam, int(iters), arr(low_res), arr(x0),
                                               arr(outs), res, _stream(stream)))
         return outs, [res[c] for c in range(C_)]
+
+
+def unet_layers(base_width=32, levels=4, cin0=8):
+    """(cin, cout, kpad) of the 3x3 convolutions in parameter order, as
+    include/msr_unet.h lays them out."""
+    out, prev = [], cin0
+    for j in range(levels):
+        w = base_width << j
+        out += [(prev, w), (w, w)]
+        prev = w
+    for j in range(levels - 2, -1, -1):
+        w = base_width << j
+        out += [(prev + w, w), (w, w)]
+        prev = w
+    return [(ci, co, (9 * ci + 31) // 32 * 32) for ci, co in out]
+
+
+def unet_init_params(base_width=32, levels=4, in_channels=2, seed=0):
+    """He-normal weights (fan-in of the real input channels), zero biases, as
+    a float32 numpy vector in the library's layout."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, (ci, co, kpad) in enumerate(unet_layers(base_width, levels)):
+        real = in_channels if i == 0 else ci
+        w = np.zeros((co, kpad), np.float32)
+        blk = rng.normal(0.0, np.sqrt(2.0 / (9 * real)), size=(co, 9, ci)).astype(np.float32)
+        if i == 0:
+            blk[:, :, real:] = 0.0
+        w[:, : 9 * ci] = blk.reshape(co, 9 * ci)
+        parts += [w.ravel(), np.zeros(co, np.float32)]
+    parts += [rng.normal(0.0, np.sqrt(1.0 / base_width), size=base_width).astype(np.float32),
+              np.zeros(1, np.float32)]
+    return np.concatenate(parts)
+
+
+class UNet:
+    """The learned warm start (include/msr_unet.h) with a torch-owned workspace
+    sized for batches of up to `batch` images of height x width."""
+
+    def __init__(self, batch, height, width=None, base_width=32, levels=4, in_channels=2, device=0):
+        import torch
+
+        self._lib = lib()
+        width = height if width is None else width
+        self.cfg = UNetConfig(in_channels, base_width, levels, device)
+        self.batch, self.height, self.width = batch, height, width
+        self.device = torch.device("cuda", device)
+        self.nparam = int(self._lib.msr_unet_param_count(C.byref(self.cfg)))
+        h = C.c_void_p()
+        st = self._lib.msr_unet_init(C.byref(self.cfg), C.byref(h))
+        if st != OK:
+            raise MsrError(st, "msr_unet_init rejected the configuration")
+        self._h = h
+        nbytes = int(self._lib.msr_unet_workspace_bytes(C.byref(self.cfg), batch, height, width))
+        if nbytes == 0:
+            self._lib.msr_unet_destroy(h)
+            self._h = None
+            raise MsrError(ERR_INVALID, f"no workspace for batch {batch} of {height}x{width}")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._ws.data_ptr() + 255) // 256 * 256
+        self._check(self._lib.msr_unet_set_workspace(self._h, C.c_void_p(aligned), nbytes, batch, height, width))
+        self.workspace_bytes = nbytes
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.msr_unet_destroy(h)
+            self._h = None
+
+    def _check(self, st):
+        if st != OK:
+            msg = self._lib.msr_unet_last_error(self._h)
+            raise MsrError(st, msg.decode() if msg else "")
+
+    def _p(self, t):
+        return _ptr(t, __import__("torch").float32)
+
+    def set_params(self, params, stream=None):
+        import torch
+
+        t = params if isinstance(params, torch.Tensor) else torch.from_numpy(params)
+        t = t.to(self.device, torch.float32).contiguous()
+        if t.numel() != self.nparam:
+            raise ValueError(f"expected {self.nparam} parameters, got {t.numel()}")
+        self._check(self._lib.msr_unet_set_params(self._h, self._p(t), _stream(stream)))
+
+    def get_params(self, stream=None):
+        import torch
+
+        out = torch.empty(self.nparam, dtype=torch.float32, device=self.device)
+        self._check(self._lib.msr_unet_get_params(self._h, self._p(out), _stream(stream)))
+        return out
+
+    def forward(self, dirty_h, low_res, out=None, stream=None):
+        import torch
+
+        b = dirty_h.shape[0] if dirty_h.dim() == 3 else 1
+        x0 = out if out is not None else torch.empty_like(dirty_h)
+        self._check(self._lib.msr_unet_forward(self._h, self._p(dirty_h), self._p(low_res), self._p(x0), b,
+                                               _stream(stream)))
+        return x0
+
+    def loss_grad(self, dirty_h, low_res, target, stream=None):
+        import torch
+
+        b = dirty_h.shape[0] if dirty_h.dim() == 3 else 1
+        g = torch.empty(self.nparam, dtype=torch.float32, device=self.device)
+        loss = C.c_double()
+        self._check(self._lib.msr_unet_loss_grad(self._h, self._p(dirty_h), self._p(low_res), self._p(target), b,
+                                                 C.byref(loss), self._p(g), _stream(stream)))
+        return loss.value, g
+
+    def train_step(self, dirty_h, low_res, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        b = dirty_h.shape[0] if dirty_h.dim() == 3 else 1
+        opt = Adam(lr, beta1, beta2, eps)
+        loss = C.c_double()
+        self._check(self._lib.msr_unet_train_step(self._h, self._p(dirty_h), self._p(low_res), self._p(target), b,
+                                                  C.byref(opt), C.byref(loss), _stream(stream)))
+        return loss.value

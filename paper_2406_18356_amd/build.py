@@ -51,8 +51,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for L in LENGTHS:
         obj = os.path.join(BUILD, f"ops_{L}.o")
         units.append([cc, *CXXFLAGS, f"-DMSR_L={L}", "-c", os.path.join(CSRC, "ops_inst.hip"), "-o", obj])
-    api_obj = os.path.join(BUILD, "msr_api.o")
-    units.append([cc, *CXXFLAGS, "-c", os.path.join(CSRC, "msr_api.hip"), "-o", api_obj])
+    for name in ("msr_api", "unet"):
+        units.append([cc, *CXXFLAGS, "-c", os.path.join(CSRC, name + ".hip"), "-o", os.path.join(BUILD, name + ".o")])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         outs = list(ex.map(_run, units))
     if verbose:

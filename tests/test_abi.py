@@ -1,6 +1,7 @@
 """The C ABI library loads without a GPU and exports every function that
 include/msr.h declares; pure host calls behave."""
 import ctypes as C
+import glob
 import os
 import re
 import subprocess
@@ -9,12 +10,15 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "msr.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(msr_[a-z0-9_]+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(msr_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -102,3 +106,22 @@ def test_batch_workspace_bytes_host_only(lib):
     assert lib.msr_batch_last_error(None) == b"null batch"
     assert lib.msr_batch_channels(None) == 0
     assert lib.msr_batch_channel(None, 0) is None
+
+
+def test_unet_sizes_host_only(lib):
+    from oracle import unet as ou
+    from paper_2406_18356_amd import binding
+
+    for width, levels in ((32, 4), (8, 2), (16, 3)):
+        cfg = binding.UNetConfig(2, width, levels, 0)
+        n = sum(o * ((9 * c + 31) // 32 * 32 + 1) for c, o, *_ in ou.layer_table(width, levels)) + width + 1
+        assert lib.msr_unet_param_count(C.byref(cfg)) == n == binding.unet_init_params(width, levels).size
+    cfg = binding.UNetConfig(2, 32, 4, 0)
+    assert lib.msr_unet_workspace_bytes(C.byref(cfg), 1, 64, 64) > 4 * 3 * n
+    assert lib.msr_unet_workspace_bytes(C.byref(cfg), 1, 60, 64) == 0  # not a multiple of 8
+    assert lib.msr_unet_workspace_bytes(C.byref(cfg), 0, 64, 64) == 0
+    for bad in ((2, 12, 4), (2, 32, 1), (2, 32, 7), (0, 32, 4), (2, 256, 4)):
+        assert lib.msr_unet_param_count(C.byref(binding.UNetConfig(*bad, 0))) == 0
+    h = C.c_void_p(1)
+    assert lib.msr_unet_init(C.byref(binding.UNetConfig(2, 12, 4, 0)), C.byref(h)) == binding.ERR_INVALID
+    assert lib.msr_unet_last_error(None) == b"null network"
