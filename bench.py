@@ -114,6 +114,62 @@ def batch_bench(torch, dev, count, iters, seed=4):
     }
 
 
+def train_warm_start(torch, n=256, ntrain=256, epochs=20, iters2=3000, neval=4, seed=11):
+    """Trains the learned warm start on two-step results of skies observed like
+    the benchmark workload (same array and track, sky density and cut) at
+    n x n, and measures step-2 time to a 1e-6 relative objective from zero
+    and from the network's prediction on held-out skies.  Returns (trained
+    parameters, report)."""
+    import synth
+    from synth.generator import SkyConfig
+    from paper_2406_18356_amd import Solver, UNet, unet_init_params, warmstart as ws
+
+    dev = torch.device("cuda:0")
+    f = (n / 4096) ** 2
+    cfg = synth.preset("sky4096").replace(n=n, sky=SkyConfig(max(2, int(8000 * f)), max(1, int(200 * f))), seed=seed)
+    t0 = time.perf_counter()
+    base = synth.make_problem(cfg, with_full=False)
+    train_p, eval_p = synth.sky_set(base, ntrain, 100), synth.sky_set(base, neval, 200)
+    t1 = time.perf_counter()
+    dh, il, b2, _ = ws.solve_pairs(train_p, iters2=iters2)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    net = UNet(8, n)
+    net.set_params(unet_init_params(seed=0))
+    losses = ws.train(net, dh, il, b2, epochs=epochs, batch=8, lr=1e-3)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    params = net.get_params()
+    del net, dh, il, b2
+    edh, eil, _, elam = ws.solve_pairs(eval_p, iters2=1)
+    net1 = UNet(1, n)
+    net1.set_params(params)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
+    evals = []
+    for i, p in enumerate(eval_p):
+        s = Solver(n, positivity=True)
+        s.set_dirty_psf(1, T(p.dirty_L), T(p.psf_L))
+        s.set_dirty_psf(2, T(p.dirty_H), T(p.psf_H))
+        sig2 = s.estimate_sigma2(edh[i])
+        s.set_filters(p.ell, p.delta, sig2, 1e-3 * sig2)
+        _, rref = s.step2(elam[i], eil[i], 20000)
+        fstar = rref.objective
+        cold = ws.time_to_tol(s, elam[i], eil[i], fstar)
+        x0, fms = ws.timed_forward(net1, edh[i:i + 1].contiguous(), eil[i:i + 1].contiguous())
+        warm = ws.time_to_tol(s, elam[i], eil[i], fstar, x0=x0[0].contiguous(), warm_ms=fms)
+        g0 = s.objective(2, elam[i], torch.zeros_like(edh[i]), eil[i])[0]
+        gw = s.objective(2, elam[i], x0[0].contiguous(), eil[i])[0]
+        evals.append({"cold": cold, "unet_warm": warm, "initial_gap_cold": (g0 - fstar) / abs(fstar),
+                      "initial_gap_unet": (gw - fstar) / abs(fstar)})
+    report = {
+        "train": {"image": n, "pairs": ntrain, "target_iters": iters2, "epochs": epochs, "batch": 8,
+                  "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
+                  "generate_s": t1 - t0, "solve_pairs_s": t2 - t1, "train_s": t3 - t2},
+        "eval_held_out": evals,
+    }
+    return params, report
+
+
 def cpu_baseline(pr, budget_s=15.0):
     """FP64 oracle step-1 FISTA iterations on this host (bounded sample)."""
     from oracle import objectives, fista
@@ -148,6 +204,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-unet", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=8)
     ap.add_argument("--ttt-ref-iters", type=int, default=20000)
     ap.add_argument("--profile-pass", type=int, nargs=3, action="append", default=None,
@@ -260,6 +317,11 @@ def main(argv=None):
                      "launch_ms": d["ms"], "hbm_gbs": d["gbs"], "hbm_frac": hbm_frac})
     log("passes:", json.dumps(passes))
 
+    unet_report, unet_params = None, None
+    if not args.no_unet and not args.no_ttt:
+        unet_params, unet_report = train_warm_start(torch)
+        log("learned warm start:", json.dumps(unet_report))
+
     ttt = None
     if not args.no_ttt:
         # F* from a long cold run of step 2 (same problem and lambda); then the
@@ -271,6 +333,16 @@ def main(argv=None):
         for name, x0 in (("cold", None), ("low_res_warm", iL), ("step1_model_warm", b1)):
             _, rc = s.step2(lam2, iL, args.ttt_ref_iters, x0=x0, check_every=10, tol=1e-6, f_ref=fstar)
             ttt[name] = {"ms": rc.time_to_tol_ms, "iters": rc.iters, "converged": bool(rc.converged)}
+        if unet_params is not None:
+            from paper_2406_18356_amd import UNet, warmstart as ws
+
+            net = UNet(1, pr.n)
+            net.set_params(unet_params)
+            x0, fms = ws.timed_forward(net, tensors[2][None].contiguous(), iL[None].contiguous())
+            ttt["unet_warm"] = ws.time_to_tol(s, lam2, iL, fstar, x0=x0[0].contiguous(), warm_ms=fms,
+                                              max_iters=args.ttt_ref_iters)
+            ttt["unet_warm"]["trained_at"] = unet_report["train"]["image"]
+            del net
         log("time to tolerance:", json.dumps(ttt))
 
     batch = None
@@ -302,6 +374,7 @@ def main(argv=None):
         "step2_loop_iters_per_s": r2.iters / (r2.elapsed_ms * 1e-3),
         "autotune": {"row_variant": tuned[0], "col_variant": tuned[1]},
         "time_to_tol": ttt,
+        "learned_warm_start": unet_report,
         "batch": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,

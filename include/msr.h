@@ -253,13 +253,16 @@ msr_status msr_batch_autotune(msr_batch* batch, int reps, void* stream);
 /* `iters` FISTA iterations of step s (1: Eq. 4, 2: Eq. 5) for every channel:
  * lambda[c] its regularisation weight, low_res[c] its constraint image (step 2),
  * x0 NULL or x0[c] its start (NULL entries: 0), model_out[c] its result
- * beta_iters (device, N_c x N_c).  res, if not NULL, receives per channel the
+ * beta_iters (device, N_c x N_c); image_out (step 1 only, may be NULL) receives
+ * each channel's low-resolution image beta + (i~_L - H_L beta) (Sect. 3.2, as
+ * msr_step1_low_res).  res, if not NULL, receives per channel the
  * exact objective of the result (FP64), theta and the elapsed time of the whole
  * batched iteration loop.  Channels without a cached theta get one by power
  * iteration first.  The first call for a given (step, iters, kept columns,
  * variants) captures the graph; later calls replay it.  Blocks until done. */
 msr_status msr_batch_solve(msr_batch* batch, int step, const double* lambda, int iters, const void* const* low_res,
-                           const void* const* x0, void* const* model_out, msr_result* res, void* stream);
+                           const void* const* x0, void* const* model_out, void* const* image_out, msr_result* res,
+                           void* stream);
 
 #ifdef __cplusplus
 }

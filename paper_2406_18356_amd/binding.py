@@ -106,7 +106,7 @@ SYMBOLS = {
     "msr_batch_set_workspace": (_ST, [_P, _P, C.c_size_t]),
     "msr_batch_autotune": (_ST, [_P, C.c_int, _P]),
     "msr_batch_solve": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(_P), C.POINTER(_P),
-                              C.POINTER(_P), C.POINTER(Result), _P]),
+                              C.POINTER(_P), C.POINTER(_P), C.POINTER(Result), _P]),
     "msr_unet_param_count": (C.c_size_t, [C.POINTER(UNetConfig)]),
     "msr_unet_workspace_bytes": (C.c_size_t, [C.POINTER(UNetConfig), C.c_int, C.c_int, C.c_int]),
     "msr_unet_init": (_ST, [C.POINTER(UNetConfig), C.POINTER(_P)]),
@@ -369,8 +369,9 @@ class Batch:
     def autotune(self, reps=10, stream=None):
         self._check(self._lib.msr_batch_autotune(self._h, int(reps), _stream(stream)))
 
-    def solve(self, step, lambdas, iters, low_res=None, x0=None, out=None, stream=None):
-        """Runs `iters` iterations of `step` on every channel; returns (models, results)."""
+    def solve(self, step, lambdas, iters, low_res=None, x0=None, out=None, image=False, stream=None):
+        """Runs `iters` iterations of `step` on every channel; returns (models,
+        results), or (models, low-resolution images, results) with image=True (step 1)."""
         import torch
 
         C_ = len(self.sizes)
@@ -383,9 +384,12 @@ class Batch:
                 return None
             return (_P * C_)(*[_ptr(t, self.dtype) for t in ts])
 
+        imgs = [torch.empty_like(o) for o in outs] if image else None
         res = (Result * C_)()
         self._check(self._lib.msr_batch_solve(self._h, int(step), lam, int(iters), arr(low_res), arr(x0),
-                                              arr(outs), res, _stream(stream)))
+                                              arr(outs), arr(imgs), res, _stream(stream)))
+        if image:
+            return outs, imgs, [res[c] for c in range(C_)]
         return outs, [res[c] for c in range(C_)]
 
 

@@ -1283,7 +1283,7 @@ struct BatchImpl {
     }
 
     msr_status solve(int step, const double* lambda, int iters, const void* const* low_res, const void* const* x0,
-                     void* const* model_out, msr_result* res, hipStream_t s) {
+                     void* const* model_out, void* const* image_out, msr_result* res, hipStream_t s) {
         const int C = (int)b->ch.size();
         // 1. per channel: theta, beta_0, constraint, spectrum of alpha_0 (on
         //    every column its group's launches read: nothing unwritten is read,
@@ -1337,7 +1337,8 @@ struct BatchImpl {
         for (int c = 0; c < C; ++c) {
             Impl<R> im(b->ch[c]);
             double F[3] = {0, 0, 0};
-            TRY(bchan(b, c, im.finish(step, lambda[c], iters, static_cast<R*>(model_out[c]), nullptr, F, s)));
+            R* img = image_out ? static_cast<R*>(image_out[c]) : nullptr;
+            TRY(bchan(b, c, im.finish(step, lambda[c], iters, static_cast<R*>(model_out[c]), img, F, s)));
             if (res) {
                 res[c].iters = iters;
                 res[c].converged = 0;
@@ -1455,11 +1456,13 @@ msr_status msr_batch_autotune(msr_batch* b, int reps, void* stream) {
 }
 
 msr_status msr_batch_solve(msr_batch* b, int step, const double* lambda, int iters, const void* const* low_res,
-                           const void* const* x0, void* const* model_out, msr_result* res, void* stream) {
+                           const void* const* x0, void* const* model_out, void* const* image_out, msr_result* res,
+                           void* stream) {
     if (!b) return MSR_ERR_INVALID;
     if (!b->ws) return bfail(b, MSR_ERR_OOM, "no workspace");
     if (step != 1 && step != 2) return bfail(b, MSR_ERR_INVALID, "step must be 1 or 2");
-    if (!lambda || !model_out || iters < 0 || (step == 2 && !low_res)) return bfail(b, MSR_ERR_INVALID, "bad arguments");
+    if (!lambda || !model_out || iters < 0 || (step == 2 && !low_res) || (step == 2 && image_out))
+        return bfail(b, MSR_ERR_INVALID, "bad arguments");
     for (size_t c = 0; c < b->ch.size(); ++c) {
         msr_ctx* cx = b->ch[c];
         if (!cx->have_psf[step - 1]) return bfail(b, MSR_ERR_STATE, "channel %zu: set_dirty_psf(%d) first", c, step);
@@ -1469,8 +1472,9 @@ msr_status msr_batch_solve(msr_batch* b, int step, const double* lambda, int ite
             return bfail(b, MSR_ERR_INVALID, "channel %zu: bad lambda or output", c);
     }
     BHIPCHK(b, hipSetDevice(b->device));
-    if (b->prec == 64) return BatchImpl<double>{b}.solve(step, lambda, iters, low_res, x0, model_out, res, S(stream));
-    return BatchImpl<float>{b}.solve(step, lambda, iters, low_res, x0, model_out, res, S(stream));
+    if (b->prec == 64)
+        return BatchImpl<double>{b}.solve(step, lambda, iters, low_res, x0, model_out, image_out, res, S(stream));
+    return BatchImpl<float>{b}.solve(step, lambda, iters, low_res, x0, model_out, image_out, res, S(stream));
 }
 
 }  // extern "C"

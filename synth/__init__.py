@@ -27,6 +27,7 @@ from .generator import (
     PRESETS,
     tiny,
     channel_set,
+    sky_set,
 )
 
 __all__ = [
@@ -44,4 +45,5 @@ __all__ = [
     "PRESETS",
     "tiny",
     "channel_set",
+    "sky_set",
 ]

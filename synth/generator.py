@@ -295,6 +295,23 @@ def make_problem(cfg: ProblemConfig, with_full: bool = True) -> Problem:
     )
 
 
+def sky_set(base: Problem, count: int, seed: int) -> list:
+    """`count` problems observed with `base`'s uv coverage (same PSFs and
+    partition) but new skies and noise, drawn from its sky configuration: many
+    fields, or many epochs, of one observation."""
+    out = []
+    for i in range(count):
+        s_sky, s_nL, s_nH = np.random.SeedSequence([seed, i]).spawn(3)
+        gen = lambda s: np.random.Generator(np.random.PCG64(s))  # noqa: E731
+        sky = make_sky(base.n, base.cfg.sky, gen(s_sky))
+        out.append(dataclasses.replace(
+            base, sky=sky, psf_full=None, dirty_full=None,
+            dirty_L=_dirty_from_weights(sky, base.w_L, base.cfg.noise_rel, gen(s_nL)),
+            dirty_H=_dirty_from_weights(sky, base.w_H, base.cfg.noise_rel, gen(s_nH)),
+        ))
+    return out
+
+
 # --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------

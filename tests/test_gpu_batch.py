@@ -81,12 +81,13 @@ def test_batch_matches_single_channel_solves(torch_dev, prec, positivity):
         _setup(torch_dev, s, pr, prec)
     K = 25
     lam1 = [0.05 * np.linalg.norm(pr.dirty_L) for pr in prs]
-    models1, res1 = b.solve(1, lam1, K)
+    models1, imgs1, res1 = b.solve(1, lam1, K, image=True)
     tol = TOL64 * 1e-3 if prec == 64 else SAME
     for c, (pr, s) in enumerate(zip(prs, singles)):
         s.set_lipschitz(1, res1[c].theta)  # same theta as the batch found by power iteration
-        bs, rs = s.step1(lam1[c], K)
+        bs, ims, rs = s.step1(lam1[c], K, image=True)
         assert rel(models1[c].cpu().numpy(), bs.cpu().numpy()) <= tol, c
+        assert rel(imgs1[c].cpu().numpy(), ims.cpu().numpy()) <= tol, c
         assert res1[c].objective == pytest.approx(rs.objective, rel=1e-12 if prec == 64 else 1e-6)
         assert res1[c].iters == K
     # step 2 with each channel's low-resolution image as the constraint
