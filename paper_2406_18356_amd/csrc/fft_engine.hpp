@@ -139,16 +139,27 @@ __host__ __device__ constexpr int elems_per_thread(int L, int EMAX) { return L >
 template <int NH, int E, typename C>
 using RegArr = C[NH][E];
 
+// MSR_TWIDDLE_LOADS = 1 loads every twiddle from the table instead.
+#ifndef MSR_TWIDDLE_LOADS
+#define MSR_TWIDDLE_LOADS 0
+#endif
+
 // One Stockham stage on NH arrays at once.  Butterfly b of thread t owns the
 // register slots b + r*NB (r < RD), so results go back into the same slots
 // (last stage) or straight to LDS (other stages): no second register copy.
-template <int L, int E, int NS, bool INV, int TWS, int NH, int S, typename C>
-__device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
-                                          const C* __restrict__ tw) {
+// With ping-pong buffers (PP) consecutive stages exchange through different
+// LDS arrays, so one barrier per stage suffices (a stage's writes cannot
+// overtake the previous stage's reads of the other array); otherwise one array
+// and two barriers.  Twiddles: w^r for power-of-two r come from the table,
+// the others are products of two earlier ones.
+template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, typename C>
+__device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
+                                          const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw) {
     constexpr int TPF = L / E;
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
     constexpr int NB = E / RD;
     constexpr bool LAST = (NS * RD == L);
+    const LdsView<S, C>(&lds)[NH] = (PP && BUF) ? lds1 : lds0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + b * TPF;
@@ -156,7 +167,11 @@ __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, 
         C w[RD];
         if constexpr (NS > 1) {
 #pragma unroll
-            for (int r = 1; r < RD; ++r) w[r] = tw[(jm * r * (L / (NS * RD))) * TWS];
+            for (int r = 1; r < RD; ++r) {
+                const int hb = 1 << (31 - __builtin_clz(r));  // highest power of two in r
+                if (hb == r || MSR_TWIDDLE_LOADS) w[r] = tw[(jm * r * (L / (NS * RD))) * TWS];
+                else w[r] = cmul(w[hb], w[r - hb]);
+            }
         }
         const int idxD = (j - jm) * RD + jm;
 #pragma unroll
@@ -184,25 +199,33 @@ __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, 
         for (int h = 0; h < NH; ++h)
 #pragma unroll
             for (int m = 0; m < E; ++m) v[h][m] = lds[h][t + m * TPF];
-        __syncthreads();
+        if constexpr (!PP) __syncthreads();
     }
 }
 
-template <int L, int E, int NS, bool INV, int TWS, int NH, int S, typename C>
-__device__ __forceinline__ void fft_from(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
-                                         const C* __restrict__ tw) {
+template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, typename C>
+__device__ __forceinline__ void fft_from(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
+                                         const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw) {
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
-    fft_stage<L, E, NS, INV, TWS, NH, S, C>(v, lds, t, tw);
-    if constexpr (NS * RD < L) fft_from<L, E, NS * RD, INV, TWS, NH, S, C>(v, lds, t, tw);
+    fft_stage<L, E, NS, INV, TWS, NH, S, BUF, PP, C>(v, lds0, lds1, t, tw);
+    if constexpr (NS * RD < L) fft_from<L, E, NS * RD, INV, TWS, NH, S, 1 - BUF, PP, C>(v, lds0, lds1, t, tw);
 }
 
 // Full transform of NH arrays (unnormalised; INV uses conjugate twiddles).
 // tw: the table of exp(-2 pi i k / (TWS * L)).  The caller must have a barrier
-// between any earlier use of the LDS views and this call.
+// between any earlier use of the LDS views and this call, and one between
+// this call and any later LDS write.
 template <int L, int E, bool INV, int TWS, int NH, int S, typename C>
 __device__ __forceinline__ void fft(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
                                     const C* __restrict__ tw) {
-    fft_from<L, E, 1, INV, TWS, NH, S, C>(v, lds, t, tw);
+    fft_from<L, E, 1, INV, TWS, NH, S, 0, false, C>(v, lds, lds, t, tw);
+}
+
+// The same with two LDS arrays used alternately (one barrier per stage).
+template <int L, int E, bool INV, int TWS, int NH, int S, typename C>
+__device__ __forceinline__ void fft_pp(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
+                                       const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw) {
+    fft_from<L, E, 1, INV, TWS, NH, S, 0, true, C>(v, lds0, lds1, t, tw);
 }
 
 // ---------------------------------------------------------------------------

@@ -115,6 +115,14 @@ constexpr int waves_per_eu() {
 #define MSR_WAVES_ATTR(EMAX, R)
 #endif
 
+// Row kernels exchange FFT stages through two LDS arrays (one barrier per
+// stage) when both fit in a CU's LDS next to nothing else (MSR_ROW_PINGPONG = 0
+// turns this off).
+#ifndef MSR_ROW_PINGPONG
+#define MSR_ROW_PINGPONG 1
+#endif
+constexpr size_t kLdsBytes = 160 * 1024;
+
 template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
 __global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R, EMAX>::TPF))
 MSR_WAVES_ATTR(EMAX, R)
@@ -125,7 +133,8 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     constexpr int ZLEN = padded_len(PT);
     constexpr int NT = PAIRS * TPF;
     constexpr int NQ = Epi::NQ;
-    __shared__ C lds[PAIRS * ZLEN];
+    constexpr bool PP = MSR_ROW_PINGPONG && 2 * PAIRS * ZLEN * sizeof(C) <= kLdsBytes;
+    __shared__ C lds[(PP ? 2 : 1) * PAIRS * ZLEN];
     __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
 
     RowArgs<R> a = a0;
@@ -143,9 +152,12 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     const int row0 = xcd_block(blockIdx.x, gridDim.x) * (2 * PAIRS);
     const int ra = row0 + 2 * pair;
     const LdsView<1, C> zv{lds + pair * ZLEN, 0};
-    LdsView<1, C> hv[NH];
+    LdsView<1, C> hv[NH], hw[NH];
 #pragma unroll
-    for (int h = 0; h < NH; ++h) hv[h] = LdsView<1, C>{lds + pair * ZLEN + h * padded_len(L), 0};
+    for (int h = 0; h < NH; ++h) {
+        hv[h] = LdsView<1, C>{lds + pair * ZLEN + h * padded_len(L), 0};
+        hw[h] = LdsView<1, C>{lds + (PP ? PAIRS * ZLEN : 0) + pair * ZLEN + h * padded_len(L), 0};
+    }
 
     C v[NH][E];
     C z[E];
@@ -208,7 +220,8 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 #pragma unroll
             for (int h = 0; h < NH; ++h) v[h][m] = zv[NH * (t + m * TPF) + h];
         __syncthreads();
-        fft<L, E, true, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
+        if constexpr (PP) fft_pp<L, E, true, Cf::TWS, NH, 1, C>(v, hv, hw, t, a.tw);
+        else fft<L, E, true, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             C s = v[0][m];
@@ -233,7 +246,8 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
             if constexpr (PADDED) v[1][m] = cmul(z[m], a.tw[t + m * TPF]);
         }
         __syncthreads();
-        fft<L, E, false, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
+        if constexpr (PP) fft_pp<L, E, false, Cf::TWS, NH, 1, C>(v, hv, hw, t, a.tw);
+        else fft<L, E, false, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < E; ++m)
