@@ -8,9 +8,8 @@
 // reads exactly the registers the forward's last stage wrote.  Stages are
 // Stockham auto-sort passes of radix R = min(E, remaining length); between
 // stages the data goes through LDS once (write, barrier, read, barrier).
-// Twiddles come from one table of exp(-2 pi i k / Pt), k < Pt, computed in
-// double precision on the host and rounded to the working precision
-// (Pt = the logical transform length, L or 2L).
+// Stage twiddles come from per-stage tables computed in double precision on
+// the host and rounded to the working precision (see stage_offset).
 //
 // Several independent arrays ("halves") can be transformed together so they
 // share the barriers; each has its own LDS view.
@@ -139,10 +138,27 @@ __host__ __device__ constexpr int elems_per_thread(int L, int EMAX) { return L >
 template <int NH, int E, typename C>
 using RegArr = C[NH][E];
 
-// MSR_TWIDDLE_LOADS = 1 loads every twiddle from the table instead.
-#ifndef MSR_TWIDDLE_LOADS
-#define MSR_TWIDDLE_LOADS 0
-#endif
+// Stage twiddle tables.  Stage NS (> 1) of a length-L transform with E
+// elements per thread has radix RD = min(E, L / NS); butterfly class
+// jm < NS needs w^r, r < RD, w = exp(-2 pi i jm / (NS RD)).  Its table row
+// holds w^1, w^2, w^4, w^8 (4 complex, aligned): the other powers are products
+// of two of these.  Rows of consecutive jm are adjacent, so a wave's loads
+// are contiguous.  The tables of E = 2, 4, 8, 16 (those not above L) for one
+// length are stored back to back.
+__host__ __device__ constexpr int stage_radix(int L, int E, int NS) { return (L / NS) >= E ? E : (L / NS); }
+__host__ __device__ constexpr int stage_offset(int L, int E, int NSq) {
+    int off = 0;
+    for (int NS = 1; NS < L && NS < NSq; NS *= stage_radix(L, E, NS))
+        if (NS > 1) off += 4 * NS;
+    return off;
+}
+__host__ __device__ constexpr int stage_table_len(int L, int E) { return stage_offset(L, E, L); }
+__host__ __device__ constexpr int stage_tables_offset(int L, int E) {
+    int off = 0;
+    for (int e = 2; e < E && e <= L; e *= 2) off += stage_table_len(L, e);
+    return off;
+}
+__host__ __device__ constexpr int stage_tables_len(int L) { return stage_tables_offset(L, 32); }
 
 // One Stockham stage on NH arrays at once.  Butterfly b of thread t owns the
 // register slots b + r*NB (r < RD), so results go back into the same slots
@@ -150,11 +166,11 @@ using RegArr = C[NH][E];
 // With ping-pong buffers (PP) consecutive stages exchange through different
 // LDS arrays, so one barrier per stage suffices (a stage's writes cannot
 // overtake the previous stage's reads of the other array); otherwise one array
-// and two barriers.  Twiddles: w^r for power-of-two r come from the table,
-// the others are products of two earlier ones.
+// and two barriers.  Twiddles come from the stage table `tws` of this
+// (L, E): w^r for power-of-two r directly, the others as products of two.
 template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, typename C>
 __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
-                                          const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw) {
+                                          const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tws) {
     constexpr int TPF = L / E;
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
     constexpr int NB = E / RD;
@@ -166,10 +182,12 @@ __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, 
         const int jm = j & (NS - 1);
         C w[RD];
         if constexpr (NS > 1) {
+            const C* row = tws + stage_offset(L, E, NS) + 4 * jm;
 #pragma unroll
             for (int r = 1; r < RD; ++r) {
-                const int hb = 1 << (31 - __builtin_clz(r));  // highest power of two in r
-                if (hb == r || MSR_TWIDDLE_LOADS) w[r] = tw[(jm * r * (L / (NS * RD))) * TWS];
+                const int lg = 31 - __builtin_clz(r);
+                const int hb = 1 << lg;  // highest power of two in r
+                if (hb == r) w[r] = row[lg];
                 else w[r] = cmul(w[hb], w[r - hb]);
             }
         }
@@ -212,20 +230,20 @@ __device__ __forceinline__ void fft_from(RegArr<NH, E, C>& v, const LdsView<S, C
 }
 
 // Full transform of NH arrays (unnormalised; INV uses conjugate twiddles).
-// tw: the table of exp(-2 pi i k / (TWS * L)).  The caller must have a barrier
-// between any earlier use of the LDS views and this call, and one between
-// this call and any later LDS write.
+// tw: the stage tables of length L (all E, see stage_tables_offset).  The
+// caller must have a barrier between any earlier use of the LDS views and
+// this call, and one between this call and any later LDS write.
 template <int L, int E, bool INV, int TWS, int NH, int S, typename C>
 __device__ __forceinline__ void fft(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
                                     const C* __restrict__ tw) {
-    fft_from<L, E, 1, INV, TWS, NH, S, 0, false, C>(v, lds, lds, t, tw);
+    fft_from<L, E, 1, INV, TWS, NH, S, 0, false, C>(v, lds, lds, t, tw + stage_tables_offset(L, E));
 }
 
 // The same with two LDS arrays used alternately (one barrier per stage).
 template <int L, int E, bool INV, int TWS, int NH, int S, typename C>
 __device__ __forceinline__ void fft_pp(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
                                        const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw) {
-    fft_from<L, E, 1, INV, TWS, NH, S, 0, true, C>(v, lds0, lds1, t, tw);
+    fft_from<L, E, 1, INV, TWS, NH, S, 0, true, C>(v, lds0, lds1, t, tw + stage_tables_offset(L, E));
 }
 
 // ---------------------------------------------------------------------------

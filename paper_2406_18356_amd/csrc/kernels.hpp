@@ -85,6 +85,7 @@ struct RowArgs {
     const C* __restrict__ spec_in2;  // optional second spectrum added for k_x < K_in2
     C* __restrict__ spec_out;        // tiled row spectrum (FWD_OUT)
     const C* __restrict__ tw;        // exp(-2 pi i k / P), k < P
+    const C* __restrict__ tws;       // FFT stage twiddle tables of length L
     double* __restrict__ partials;   // NQ doubles per block (when reduce)
     int NR;                          // rows of the spectra (= image rows)
     int K_in;                        // stored columns of spec_in
@@ -99,6 +100,7 @@ struct RowArgs {
         spec_in2 = shifted(spec_in2, off);
         spec_out = shifted(spec_out, off);
         tw = shifted(tw, off);
+        tws = shifted(tws, off);
         partials = shifted(partials, off);
     }
 };
@@ -220,8 +222,8 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 #pragma unroll
             for (int h = 0; h < NH; ++h) v[h][m] = zv[NH * (t + m * TPF) + h];
         __syncthreads();
-        if constexpr (PP) fft_pp<L, E, true, Cf::TWS, NH, 1, C>(v, hv, hw, t, a.tw);
-        else fft<L, E, true, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
+        if constexpr (PP) fft_pp<L, E, true, Cf::TWS, NH, 1, C>(v, hv, hw, t, a.tws);
+        else fft<L, E, true, Cf::TWS, NH, 1, C>(v, hv, t, a.tws);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             C s = v[0][m];
@@ -246,8 +248,8 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
             if constexpr (PADDED) v[1][m] = cmul(z[m], a.tw[t + m * TPF]);
         }
         __syncthreads();
-        if constexpr (PP) fft_pp<L, E, false, Cf::TWS, NH, 1, C>(v, hv, hw, t, a.tw);
-        else fft<L, E, false, Cf::TWS, NH, 1, C>(v, hv, t, a.tw);
+        if constexpr (PP) fft_pp<L, E, false, Cf::TWS, NH, 1, C>(v, hv, hw, t, a.tws);
+        else fft<L, E, false, Cf::TWS, NH, 1, C>(v, hv, t, a.tws);
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < E; ++m)
@@ -451,6 +453,7 @@ struct ColArgs {
     const C* __restrict__ spec_in2;  // subtracted from spec_in before the transform (or null)
     C* __restrict__ spec_out;
     const C* __restrict__ tw;
+    const C* __restrict__ tws;  // FFT stage twiddle tables of length L
     double* __restrict__ partials;
     int NR;      // rows of the spectra (L)
     int K;       // columns processed: tiles 0 .. ceil(K/T)-1; columns >= K read as zero
@@ -466,6 +469,7 @@ struct ColArgs {
         spec_in2 = shifted(spec_in2, off);
         spec_out = shifted(spec_out, off);
         tw = shifted(tw, off);
+        tws = shifted(tws, off);
         partials = shifted(partials, off);
     }
 };
@@ -521,7 +525,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
         v[0][m] = y;
         if constexpr (PADDED) v[1][m] = cmul(y, a.tw[i]);
     }
-    fft<L, E, false, Cf::TWS, NH, CB, C>(v, hv, t, a.tw);
+    fft<L, E, false, Cf::TWS, NH, CB, C>(v, hv, t, a.tws);
 
     double acc[NQ > 0 ? NQ : 1];
 #pragma unroll
@@ -537,7 +541,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
 
     if constexpr (Mode::INVERSE) {
         __syncthreads();
-        fft<L, E, true, Cf::TWS, NH, CB, C>(v, hv, t, a.tw);
+        fft<L, E, true, Cf::TWS, NH, CB, C>(v, hv, t, a.tws);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int i = t + m * TPF;

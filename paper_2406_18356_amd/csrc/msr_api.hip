@@ -81,7 +81,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t tw, SA, SB, SC, SL, SG, hh1, hh2, d1, d2, b0, b1, t0, t1, partials, scal, colmax, total;
+    size_t tw, stwN, stwP, SA, SB, SC, SL, SG, hh1, hh2, d1, d2, b0, b1, t0, t1, partials, scal, colmax, total;
 };
 
 struct Shapes {
@@ -155,6 +155,8 @@ Layout make_layout(const Shapes& s) {
         return o;
     };
     l.tw = take(s.cs * (size_t)s.P);
+    l.stwN = take(s.cs * (size_t)stage_tables_len(s.N));
+    l.stwP = take(s.cs * (size_t)stage_tables_len(s.P));
     l.SA = take(s.cs * s.spec_elems);
     // SB and SC are contiguous: together they hold the P-row PSF spectrum.
     const size_t sbc = std::max(align_up(s.cs * s.spec_elems, kAlign) * 2, s.cs * (size_t)s.P * s.Cpad_psf);
@@ -282,6 +284,8 @@ struct Impl {
     template <typename X>
     X* at(size_t off) const { return reinterpret_cast<X*>(c->ws + off); }
     C* tw() const { return at<C>(c->lay.tw); }
+    C* stwN() const { return at<C>(c->lay.stwN); }
+    C* stwP() const { return at<C>(c->lay.stwP); }
     C* SA() const { return at<C>(c->lay.SA); }
     C* SB() const { return at<C>(c->lay.SB); }
     C* SC() const { return at<C>(c->lay.SC); }
@@ -320,6 +324,7 @@ struct Impl {
         a.spec_in2 = in2;
         a.spec_out = out;
         a.tw = tw();
+        a.tws = stwN();
         a.partials = partials();
         a.NR = N();
         a.K_in = kin;
@@ -338,6 +343,7 @@ struct Impl {
         a.spec_in2 = in2;
         a.spec_out = out;
         a.tw = tw();
+        a.tws = stwN();
         a.partials = partials();
         a.NR = N();
         a.K = K;
@@ -535,6 +541,27 @@ struct Impl {
             t[k] = mk_host(std::cos(a), std::sin(a));
         }
         HIPCHK(c, hipMemcpy(tw(), t.data(), sizeof(C) * Pn, hipMemcpyHostToDevice));
+        TRY(stage_tables(N(), stwN()));
+        return stage_tables(Pn, stwP());
+    }
+    // The FFT stage twiddle rows (w, w^2, w^4, w^8), w = exp(-2 pi i jm / (NS RD)),
+    // of every stage of every E for transforms of length L (stage_offset).
+    msr_status stage_tables(int L, C* dst) {
+        std::vector<C> t(stage_tables_len(L), mk_host(0.0, 0.0));
+        for (int E = 2; E <= 16 && E <= L; E *= 2) {
+            const int base = stage_tables_offset(L, E);
+            for (int NS = 1; NS < L; NS *= stage_radix(L, E, NS)) {
+                if (NS == 1) continue;
+                const int RD = stage_radix(L, E, NS);
+                const int off = base + stage_offset(L, E, NS);
+                for (int jm = 0; jm < NS; ++jm)
+                    for (int q = 0; q < 4; ++q) {
+                        const double ang = -2.0 * M_PI * (double)jm * (double)(1 << q) / ((double)NS * RD);
+                        t[off + 4 * jm + q] = mk_host(std::cos(ang), std::sin(ang));
+                    }
+            }
+        }
+        HIPCHK(c, hipMemcpy(dst, t.data(), sizeof(C) * t.size(), hipMemcpyHostToDevice));
         return MSR_OK;
     }
     static C mk_host(double x, double y) {
@@ -557,6 +584,7 @@ struct Impl {
         RowArgs<R> ra{};
         ra.spec_out = tmpspec;
         ra.tw = tw();
+        ra.tws = stwP();
         ra.partials = partials();
         ra.NR = Pn;
         ra.K_out = c->sh.Cfull;
@@ -567,6 +595,7 @@ struct Impl {
         ca.spec_in = tmpspec;
         ca.spec_out = tmpspec;
         ca.tw = tw();
+        ca.tws = stwP();
         ca.partials = partials();
         ca.NR = Pn;
         ca.K = c->sh.Cfull;
