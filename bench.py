@@ -209,8 +209,9 @@ def main(argv=None):
     ap.add_argument("--ttt-ref-iters", type=int, default=20000)
     ap.add_argument("--profile-pass", type=int, nargs=3, action="append", default=None,
                     metavar=("STEP", "WHICH", "REPS"),
-                    help="profiling aid (repeatable): after setup, run one 64 MiB device copy (counter "
-                         "calibration) and msr_time_pass(STEP, WHICH, REPS) for each triple, then exit")
+                    help="profiling aid (repeatable): after setup, for each triple run one 64 MiB device "
+                         "copy (counter calibration and trace marker) and msr_time_pass(STEP, WHICH, REPS), "
+                         "then exit")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="K",
                     help="profiling aid: set up the workload, autotune, run K iterations of each step and exit")
     args = ap.parse_args(argv)
@@ -249,9 +250,12 @@ def main(argv=None):
         s.step2(s.default_lambda(2, 1, 0.05), iL, 10)
         src = torch.empty(16 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
         for step, which, reps in args.profile_pass:
+            # a 64 MiB device copy before each pass: counter calibration, and a
+            # marker that separates the passes in a kernel trace
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
             ms, by, fl = s.time_pass(which, reps=reps, step=step)
             torch.cuda.synchronize()
             log(f"profile-pass step {step} which {which}: {ms * 1e3:.2f} us, {by:.0f} bytes, {fl:.0f} flops")

@@ -2,9 +2,9 @@
 
     python -m paper_2406_18356_amd.prof_summary stats DIR PREFIX OUT.txt --command "..."
     python -m paper_2406_18356_amd.prof_summary traffic DIR FETCH_PREFIX WRITE_PREFIX OUT.json \
-        --kernel SUBSTRING --bytes ALGORITHMIC_BYTES --command "..."
+        --kernel SUBSTRING --segment I --bytes ALGORITHMIC_BYTES --command "..."
     python -m paper_2406_18356_amd.prof_summary passes DIR PREFIX OUT.txt --command "..." \
-        --pass NAME SUBSTRING LAST [--pass ...]
+        --pass NAME SUBSTRING I [--pass ...]
 
 ``stats`` condenses ``<PREFIX>_kernel_stats.csv`` (rocprofv3 --kernel-trace
 --stats --output-format csv) into a table.  ``traffic`` reads two --pmc runs
@@ -14,8 +14,12 @@ and write B bytes) and records the scaled per-launch HBM traffic of the kernel
 whose name contains SUBSTRING, with a hash of the kernel sources so that the
 benchmark can tell whether the figure still describes the current code.
 ``passes`` reads ``<PREFIX>_kernel_trace.csv`` and reports, per named pass, the
-mean duration of the last LAST dispatches whose kernel name contains SUBSTRING
-(the back-to-back launches of one pass at the end of a profiling run).
+mean duration of the dispatches whose kernel name contains SUBSTRING in
+segment I.  Segments: in a ``bench.py --profile-pass ...`` run every pass is
+preceded by one 64 MiB device copy; segment I holds the dispatches after such
+a copy up to the next one, counted from the end when negative (with n
+--profile-pass triples, pass i is segment i - n).  The first matching
+dispatch of a segment (the untimed warm launch) is dropped.
 """
 from __future__ import annotations
 
@@ -57,14 +61,39 @@ def stats(d, prefix, out, command, top=16):
     return out
 
 
+def _segments(rows, name_key):
+    """Dispatch lists that follow each marker copy (a device copy of the same
+    size as the last copy of the run), in order."""
+    copies = [i for i, r in enumerate(rows) if "copyBuffer" in r[name_key]]
+    if not copies:
+        raise SystemExit("no device copy in the run")
+    g_last = int(r_grid(rows[copies[-1]]))
+    marks = [i for i in copies if int(r_grid(rows[i])) == g_last]
+    segs = []
+    for k, i in enumerate(marks):
+        end = marks[k + 1] if k + 1 < len(marks) else len(rows)
+        segs.append(rows[i + 1:end])
+    return segs
+
+
+def r_grid(r):
+    return r.get("Grid_Size_X") or r.get("Grid_Size")
+
+
+def _pick(seg, sub, name_key):
+    ds = [r for r in seg if sub in r[name_key]]
+    return ds[1:] if len(ds) > 1 else ds
+
+
 def passes(d, prefix, out, command, specs):
     rows = list(csv.DictReader(open(os.path.join(d, f"{prefix}_kernel_trace.csv"))))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    segs = _segments(rows, "Kernel_Name")
     lines = [f"# rocprofv3 kernel trace: mean duration of the last dispatches of each pass",
              f"# command: {command}", "",
              f"{'pass':18s} {'dispatches':>10s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}  kernel"]
-    for name, sub, last in specs:
-        ds = [r for r in rows if sub in r["Kernel_Name"]][-int(last):]
+    for name, sub, seg in specs:
+        ds = _pick(segs[int(seg)], sub, "Kernel_Name")
         if not ds:
             raise SystemExit(f"no dispatch matching {sub!r}")
         us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in ds]
@@ -75,31 +104,32 @@ def passes(d, prefix, out, command, specs):
 
 
 def _per_dispatch(d, prefix, counter):
+    """(name, grid, value) per dispatch, in dispatch order."""
     out = []
     for f in glob.glob(os.path.join(d, f"{prefix}_counter_collection.csv")):
-        for r in csv.DictReader(open(f)):
-            if r["Counter_Name"] == counter:
-                out.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+        rows = [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0))
+        for r in rows:
+            out.append({"Kernel_Name": r["Kernel_Name"], "Grid_Size": int(r["Grid_Size"]),
+                        "value": float(r["Counter_Value"])})
     return out
 
 
 def _copy_scale(rows, copy_bytes):
-    copies = [v for n, g, v in rows if "copyBuffer" in n]
+    copies = [r["value"] for r in rows if "copyBuffer" in r["Kernel_Name"]]
     if not copies:
         raise SystemExit("no device copy kernel in the counter run")
     big = max(copies)
     return copy_bytes / 1024.0 / big, big
 
 
-def traffic(d, fprefix, wprefix, out, kernel, alg_bytes, copy_bytes, command, last=0):
+def traffic(d, fprefix, wprefix, out, kernel, alg_bytes, copy_bytes, command, segment):
     fr = _per_dispatch(d, fprefix, "FETCH_SIZE")
     wr = _per_dispatch(d, wprefix, "WRITE_SIZE")
     fs, fbig = _copy_scale(fr, copy_bytes)
     ws, wbig = _copy_scale(wr, copy_bytes)
-    fk = [v for n, g, v in fr if kernel in n]
-    wk = [v for n, g, v in wr if kernel in n]
-    if last:
-        fk, wk = fk[-last:], wk[-last:]
+    fk = [r["value"] for r in _pick(_segments(fr, "Kernel_Name")[segment], kernel, "Kernel_Name")]
+    wk = [r["value"] for r in _pick(_segments(wr, "Kernel_Name")[segment], kernel, "Kernel_Name")]
     if not fk or not wk:
         raise SystemExit(f"kernel {kernel!r} not found")
     fetch = sum(fk) / len(fk) * fs * 1024.0
@@ -133,14 +163,14 @@ def main(argv=None):
     t.add_argument("--bytes", type=float, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--command", required=True)
-    t.add_argument("--last", type=int, default=0, help="average only the last N dispatches of the kernel")
+    t.add_argument("--segment", type=int, required=True, help="pass index in the --profile-pass run")
     q = sub.add_parser("passes")
     q.add_argument("dir")
     q.add_argument("prefix")
     q.add_argument("out")
     q.add_argument("--command", required=True)
     q.add_argument("--pass", dest="specs", nargs=3, action="append", required=True,
-                   metavar=("NAME", "SUBSTRING", "LAST"))
+                   metavar=("NAME", "SUBSTRING", "SEGMENT"))
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats(a.dir, a.prefix, a.out, a.command))
@@ -148,7 +178,7 @@ def main(argv=None):
         print(passes(a.dir, a.prefix, a.out, a.command, a.specs))
     else:
         print(json.dumps(traffic(a.dir, a.fetch_prefix, a.write_prefix, a.out, a.kernel, a.bytes, a.copy_bytes,
-                                 a.command, a.last), indent=1))
+                                 a.command, a.segment), indent=1))
 
 
 if __name__ == "__main__":
