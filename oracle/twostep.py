@@ -47,3 +47,36 @@ def two_step(dirty_L, psf_L, dirty_H, psf_H, ell, delta, iters1, iters2, positiv
         "sigma2": s2_, "eta2": e2_,
         "F1": s1.objective(beta1, lam1)[0], "F2": s2.objective(beta2, lam2)[0],
     }
+
+
+def major_cycles(step, dirty, psf, cycles, iters, c=0.05, theta=None, positivity=False, low_res=None,
+                 ell=None, delta=None, sigma2=None, eta2=None, seed=0, margin=1.01):
+    """Several major cycles of one step (Sect. 3.2 for step 1, Sect. 3.3 for
+    step 2), the residual image of each cycle formed in the image domain.
+
+    Cycle n solves its step's problem on the residual image
+        i~_n = i~_1 - H sum_{j<n} i_j
+    (the paper recomputes it from the visibilities; here the PSF convolution
+    stands in for degridding and gridding), with lambda_n = c ||i~_n||_2 2^(n-1)
+    and, in step 2, the constraint l_n = l - sum_{j<n} i_j; FISTA starts from
+    zero and its result is the cycle's image i_n.  The step's image is
+    i~_{N+1} + sum_n i_n.  Returns (image, sum of the i_n, per-cycle records)."""
+    dirty = np.asarray(dirty, np.float64)
+    if step == 1:
+        make = lambda y, l: Step1(y, psf)  # noqa: E731
+    else:
+        low_res = np.asarray(low_res, np.float64)
+        make = lambda y, l: Step2(y, psf, l, ell, delta, sigma2, eta2)  # noqa: E731
+    msum = np.zeros_like(dirty)
+    resid = dirty
+    recs = []
+    for n in range(1, cycles + 1):
+        if n > 1:
+            resid = dirty - make(dirty, low_res).H.apply(msum)
+        lam = default_lambda(resid, c, cycle=n)
+        prob = make(resid, None if step == 1 else low_res - msum)
+        beta, _, theta = solve_step(prob, lam, iters, theta, positivity=positivity, seed=seed, margin=margin)
+        recs.append({"lambda": lam, "F": prob.objective(beta, lam)[0], "theta": theta})
+        msum = msum + beta
+    final_resid = dirty - make(dirty, low_res).H.apply(msum)
+    return final_resid + msum, msum, recs

@@ -7,7 +7,7 @@ import pytest
 
 import synth
 from synth.generator import tiny
-from oracle import helpers, twostep, objectives
+from oracle import helpers, twostep, objectives, lipschitz
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -65,3 +65,32 @@ def test_two_step_runs_and_improves():
     s2 = objectives.Step2(pr.dirty_H, pr.psf_H, r["i_L"], pr.ell, pr.delta, r["sigma2"], r["eta2"])
     assert s2.objective(r["beta2"], r["lambda2"])[0] < s2.objective(np.zeros((32, 32)), r["lambda2"])[0]
     assert np.all(r["beta2"] >= 0)
+
+
+def test_major_cycles_pins():
+    """One cycle is the single-cycle step; with a delta PSF the residual
+    bookkeeping returns the dirty image exactly; the lambda schedule doubles."""
+    pr = synth.make_problem(tiny(16, seed=3))
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    th = 2.0 * float(np.max(np.abs(s1.H.h))) ** 2
+    img, msum, recs = twostep.major_cycles(1, pr.dirty_L, pr.psf_L, 1, 30, theta=th, positivity=True)
+    beta, _, _ = twostep.solve_step(s1, helpers.default_lambda(pr.dirty_L, 0.05), 30, th, positivity=True)
+    np.testing.assert_allclose(msum, beta, atol=1e-14)
+    np.testing.assert_allclose(img, helpers.low_res_image(beta, pr.dirty_L, s1.H), atol=1e-12)
+    # delta PSF: H = I, so i~_{N+1} + sum i_n = i~_1 whatever the cycles do
+    P = pr.P
+    dpsf = np.zeros((P, P))
+    dpsf[P // 2, P // 2] = 1.0
+    img, msum, recs = twostep.major_cycles(1, pr.dirty_L, dpsf, 3, 20, theta=2.0)
+    np.testing.assert_allclose(img, pr.dirty_L, atol=1e-12)
+    assert np.abs(msum).max() > 0
+    # the first cycle's lambda is c ||i~_1||; later ones use their residuals and 2^(n-1)
+    assert recs[0]["lambda"] == pytest.approx(0.05 * np.linalg.norm(pr.dirty_L), rel=1e-12)
+    # step 2: one cycle equals the single-cycle step 2
+    l = pr.dirty_L * 0.5
+    s2 = objectives.Step2(pr.dirty_H, pr.psf_H, l, pr.ell, pr.delta, 1.0, 1e-3)
+    th2 = 1.01 * lipschitz.power_iteration(s2.normal, 16)[0]
+    img2, msum2, _ = twostep.major_cycles(2, pr.dirty_H, pr.psf_H, 1, 25, theta=th2, low_res=l, ell=pr.ell,
+                                          delta=pr.delta, sigma2=1.0, eta2=1e-3)
+    b2, _, _ = twostep.solve_step(s2, helpers.default_lambda(pr.dirty_H, 0.05), 25, th2)
+    np.testing.assert_allclose(msum2, b2, atol=1e-14)
