@@ -155,6 +155,20 @@ msr_status msr_step1_low_res(msr_ctx* ctx, const msr_solve* opt, const void* x0,
 msr_status msr_step2_full_res(msr_ctx* ctx, const msr_solve* opt, const void* low_res, const void* x0,
                               void* model_out, msr_result* res, void* stream);
 
+/* `cycles` major cycles of step s (Sect. 3.2 for step 1, Sect. 3.3 for step 2)
+ * with the residual image formed in the image domain: cycle n solves its
+ * problem (Eq. 4 or Eq. 5) on i~_n = i~_1 - H_s sum_{j<n} i_j -- the paper
+ * recomputes i~_n from the visibilities, which this library does not hold --
+ * with lambda_n = c ||i~_n||_2 2^(n-1) (Sect. 5) and, for step 2, the
+ * constraint l_n = low_res - sum_{j<n} i_j; each cycle runs `iters` FISTA
+ * iterations from zero and i_n is its result.  model_out (may be NULL)
+ * receives sum_n i_n, image_out (may be NULL) the step's image
+ * i~_{N+1} + sum_n i_n; res, if not NULL, holds one msr_result per cycle.
+ * i~_1 is the dirty image set with msr_set_dirty_psf and is left unchanged.
+ * Synchronises the stream. */
+msr_status msr_major_cycles(msr_ctx* ctx, int step, int cycles, double c, int iters, const void* low_res,
+                            void* model_out, void* image_out, msr_result* res, void* stream);
+
 /* Exact objective of step s at x: out[0] = F(x), out[1] = data term(s),
  * out[2] = ||x||_1 (FP64 accumulation).  low_res is required for step 2. */
 msr_status msr_objective(msr_ctx* ctx, int step, double lambda, const void* x, const void* low_res,

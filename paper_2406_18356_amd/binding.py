@@ -88,6 +88,7 @@ SYMBOLS = {
     "msr_set_lipschitz": (_ST, [_P, C.c_int, C.c_double]),
     "msr_step1_low_res": (_ST, [_P, C.POINTER(SolveOptions), _P, _P, _P, C.POINTER(Result), _P]),
     "msr_step2_full_res": (_ST, [_P, C.POINTER(SolveOptions), _P, _P, _P, C.POINTER(Result), _P]),
+    "msr_major_cycles": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.c_int, _P, _P, _P, C.POINTER(Result), _P]),
     "msr_objective": (_ST, [_P, C.c_int, C.c_double, _P, _P, C.POINTER(C.c_double), _P]),
     "msr_gradient": (_ST, [_P, C.c_int, _P, _P, _P, _P]),
     "msr_apply_psf": (_ST, [_P, C.c_int, _P, _P, _P]),
@@ -265,6 +266,16 @@ class Solver:
         self._check(self._lib.msr_step2_full_res(self._h, C.byref(opt), self._p(low_res), self._p(x0), self._p(beta),
                                                  C.byref(res), _stream(stream)))
         return beta, res
+
+    def major_cycles(self, step, cycles, iters, c=0.05, low_res=None, stream=None):
+        """(image, sum of the cycle images, per-cycle results) of `cycles`
+        major cycles of `step` (msr_major_cycles)."""
+        img, model = self._img(), self._img()
+        res = (Result * int(cycles))()
+        self._check(self._lib.msr_major_cycles(self._h, int(step), int(cycles), float(c), int(iters),
+                                               self._p(low_res), self._p(model), self._p(img), res,
+                                               _stream(stream)))
+        return img, model, [res[k] for k in range(int(cycles))]
 
     # -- single operators ------------------------------------------------------
     def objective(self, step, lam, x, low_res=None, stream=None):

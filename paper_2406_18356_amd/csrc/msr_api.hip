@@ -81,7 +81,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t tw, stwN, stwP, SA, SB, SC, SL, SG, hh1, hh2, d1, d2, b0, b1, t0, t1, partials, scal, colmax, total;
+    size_t tw, stwN, stwP, SA, SB, SC, SL, SG, hh1, hh2, d1, d2, b0, b1, t0, t1, mc0, mc1, mc2, mc3, partials, scal,
+        colmax, total;
 };
 
 struct Shapes {
@@ -172,6 +173,11 @@ Layout make_layout(const Shapes& s) {
     l.b1 = take(s.rs * s.img_elems);
     l.t0 = take(s.rs * s.img_elems);
     l.t1 = take(s.rs * s.img_elems);
+    // major cycles: original dirty image, sum of the cycle images, constraint, cycle image
+    l.mc0 = take(s.rs * s.img_elems);
+    l.mc1 = take(s.rs * s.img_elems);
+    l.mc2 = take(s.rs * s.img_elems);
+    l.mc3 = take(s.rs * s.img_elems);
     l.partials = take(sizeof(double) * s.partial_cnt);
     l.scal = take(sizeof(double) * 64);
     l.colmax = take(sizeof(double) * (size_t)s.Cfull);
@@ -295,6 +301,10 @@ struct Impl {
     R* dirty(int step) const { return at<R>(step == 1 ? c->lay.d1 : c->lay.d2); }
     R* beta(int k) const { return at<R>((k & 1) ? c->lay.b1 : c->lay.b0); }
     R* tmp(int i) const { return at<R>(i ? c->lay.t1 : c->lay.t0); }
+    R* mc(int i) const {
+        const size_t o[4] = {c->lay.mc0, c->lay.mc1, c->lay.mc2, c->lay.mc3};
+        return at<R>(o[i]);
+    }
     double* partials() const { return at<double>(c->lay.partials); }
     double* scal() const { return at<double>(c->lay.scal); }
     double* colmax() const { return at<double>(c->lay.colmax); }
@@ -750,6 +760,62 @@ struct Impl {
         return MSR_OK;
     }
 
+    // out = y - H_step x, in the image domain (may alias y).
+    msr_status residual_image(int step, const R* y, const R* x, R* out, hipStream_t s) {
+        TRY(fwd_image(step, x, (R)1, SB(), c->K[step - 1], s));
+        TRY(col_psf(step, SB(), SC(), s));
+        opr(step)->row_resid(row_args(SC(), c->K[step - 1], nullptr, 0, nullptr, 0), EpiResid<R>{y, out, N()}, s);
+        LAUNCHCHK(c);
+        return axpby(out, out, out, (R)-1, (R)0, s);  // (H x - y) -> y - H x
+    }
+    msr_status axpby(R* out, const R* x, const R* y, R a, R b, hipStream_t s) {
+        const size_t n = c->sh.img_elems;
+        hipLaunchKernelGGL(image_axpby<R>, dim3(blocks_for(n)), dim3(256), 0, s, out, x, y, a, b, n);
+        LAUNCHCHK(c);
+        return MSR_OK;
+    }
+
+    // `cycles` major cycles of step s (Sect. 3.2 / 3.3) with the residual image
+    // of cycle n formed in the image domain, i~_n = i~_1 - H sum_{j<n} i_j;
+    // lambda_n = cl ||i~_n|| 2^(n-1); in step 2 the constraint is
+    // l - sum_{j<n} i_j.  Each cycle runs `iters` FISTA iterations from zero.
+    // model_out = sum_n i_n, image_out = i~_{N+1} + sum_n i_n.  The context's
+    // dirty image is restored before returning.
+    msr_status multi_cycle(int step, int cycles, double cl, int iters, const R* low_res, R* model_out, R* image_out,
+                           msr_result* res, hipStream_t s) {
+        const size_t nb = c->sh.rs * c->sh.img_elems;
+        R* d = dirty(step);
+        R *d0 = mc(0), *msum = mc(1), *lcur = mc(2), *cyc = mc(3);
+        HIPCHK(c, hipMemcpyAsync(d0, d, nb, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemsetAsync(msum, 0, nb, s));
+        msr_status st = MSR_OK;
+        for (int k = 1; k <= cycles && st == MSR_OK; ++k) {
+            if (k > 1 && (st = residual_image(step, d0, msum, d, s)) != MSR_OK) break;
+            double s2 = 0.0;
+            if ((st = image_reduce(d, nullptr, 1, &s2, s)) != MSR_OK) break;
+            msr_solve opt{};
+            opt.lambda = cl * std::sqrt(s2) * std::ldexp(1.0, k - 1);
+            opt.max_iters = iters;
+            const R* l = nullptr;
+            if (step == 2) {
+                if ((st = axpby(lcur, low_res, msum, (R)1, (R)-1, s)) != MSR_OK) break;
+                l = lcur;
+            }
+            if ((st = solve(step, &opt, l, nullptr, cyc, nullptr, res ? &res[k - 1] : nullptr, s)) != MSR_OK) break;
+            st = axpby(msum, msum, cyc, (R)1, (R)1, s);
+        }
+        if (st == MSR_OK) st = residual_image(step, d0, msum, d, s);
+        if (st == MSR_OK && image_out) st = axpby(image_out, d, msum, (R)1, (R)1, s);
+        if (st == MSR_OK && model_out) {
+            const hipError_t e = hipMemcpyAsync(model_out, msum, nb, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) st = fail(c, MSR_ERR_HIP, "model copy: %s", hipGetErrorString(e));
+        }
+        const hipError_t e = hipMemcpyAsync(d, d0, nb, hipMemcpyDeviceToDevice, s);  // restore i~_1
+        if (st == MSR_OK && e != hipSuccess) st = fail(c, MSR_ERR_HIP, "restore: %s", hipGetErrorString(e));
+        if (st == MSR_OK) HIPCHK(c, hipStreamSynchronize(s));
+        return st;
+    }
+
     msr_status gradient(int step, const R* x, const R* low_res, R* g, hipStream_t s) {
         if (step == 2) TRY(set_low_res(low_res, s));
         TRY(fwd_image(step, x, (R)1, SA(), KA(step), s));
@@ -1054,6 +1120,19 @@ msr_status msr_step1_low_res(msr_ctx* c, const msr_solve* opt, const void* x0, v
 msr_status msr_step2_full_res(msr_ctx* c, const msr_solve* opt, const void* low_res, const void* x0, void* model_out,
                               msr_result* res, void* stream) {
     return solve_entry(c, 2, opt, low_res, x0, model_out, nullptr, res, stream);
+}
+
+msr_status msr_major_cycles(msr_ctx* c, int step, int cycles, double cl, int iters, const void* low_res,
+                            void* model_out, void* image_out, msr_result* res, void* stream) {
+    TRY(check_step(c, step, true));
+    if (cycles < 1 || iters < 0 || !(cl >= 0) || !std::isfinite(cl) || (step == 2 && !low_res) ||
+        (!model_out && !image_out))
+        return fail(c, MSR_ERR_INVALID, "bad arguments");
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        return im.multi_cycle(step, cycles, cl, iters, static_cast<const R*>(low_res), static_cast<R*>(model_out),
+                              static_cast<R*>(image_out), res, S(stream));
+    });
 }
 
 msr_status msr_objective(msr_ctx* c, int step, double lambda, const void* x, const void* low_res, double out[3],

@@ -436,3 +436,42 @@ def test_full_size_one_step_map(torch_dev, big):
     b2, _ = s.step2(lam2, _t(torch_dev, low), 1, x0=_t(torch_dev, x0))
     bo2, _ = fista.fista(s2.grad, x0.astype(np.float64), 1 / th2, lam2, 1, positivity=True)
     assert rel(b2.cpu().numpy(), bo2) <= TOL
+
+
+# ----------------------------------------------------------------- major cycles
+@pytest.mark.parametrize("prec,cycles,iters,tol", [(64, 3, 40, TOL64), (32, 2, SHORT_K, TOL)])
+@pytest.mark.parametrize("step", [1, 2])
+def test_major_cycles(torch_dev, prec, cycles, iters, tol, step):
+    """Major cycles with image-domain residuals (Sect. 3.2, 3.3) against the oracle."""
+    from oracle import objectives, lipschitz, twostep
+
+    print(f"major cycles prec={prec} step={step}", flush=True)
+    pr = _problem(64, 2, seed=9)
+    s = _solver(torch_dev, pr, positivity=True, prec=prec)
+    sig2 = float(np.var(pr.dirty_H))
+    low = np.asarray(pr.dirty_L, np.float32).astype(np.float64) * 0.5
+    if step == 1:
+        prob = objectives.Step1(pr.dirty_L, pr.psf_L)
+        dirty, psf, kw = pr.dirty_L, pr.psf_L, {}
+    else:
+        s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        prob = objectives.Step2(pr.dirty_H, pr.psf_H, low, pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        dirty, psf = pr.dirty_H, pr.psf_H
+        kw = dict(low_res=low, ell=pr.ell, delta=pr.delta, sigma2=sig2, eta2=1e-3 * sig2)
+    th = 1.01 * lipschitz.power_iteration(prob.normal, 64)[0]
+    s.set_lipschitz(step, th)
+    img, model, res = s.major_cycles(step, cycles, iters, low_res=_t(torch_dev, low, prec) if step == 2 else None)
+    ref_img, ref_model, recs = twostep.major_cycles(step, np.asarray(dirty, np.float32 if prec == 32 else np.float64),
+                                                    psf, cycles, iters, theta=th, positivity=True, **kw)
+    assert rel(model.cpu().numpy(), ref_model) <= tol
+    assert rel(img.cpu().numpy(), ref_img) <= tol
+    for r, rec in zip(res, recs):
+        assert r.objective == pytest.approx(rec["F"], rel=1e-10 if prec == 64 else 1e-5)
+        assert r.iters == iters
+    # the context's dirty image is unchanged: a plain solve still matches the oracle's first cycle
+    lam = 0.05 * np.linalg.norm(np.asarray(dirty, np.float64))
+    if step == 1:
+        _, r1 = s.step1(lam, iters)
+    else:
+        _, r1 = s.step2(lam, _t(torch_dev, low, prec), iters)
+    assert r1.objective == pytest.approx(recs[0]["F"], rel=1e-10 if prec == 64 else 1e-5)
