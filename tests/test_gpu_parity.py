@@ -475,3 +475,23 @@ def test_major_cycles(torch_dev, prec, cycles, iters, tol, step):
     else:
         _, r1 = s.step2(lam, _t(torch_dev, low, prec), iters)
     assert r1.objective == pytest.approx(recs[0]["F"], rel=1e-10 if prec == 64 else 1e-5)
+
+
+def test_two_step_with_major_cycles_f64(torch_dev):
+    """multistep.two_step (2 major cycles per step) against the oracle chain,
+    with the step sizes the library's power iteration chose."""
+    from oracle import twostep, helpers
+    from paper_2406_18356_amd import multistep
+
+    pr = _problem(32, 2, seed=4)
+    s = _solver(torch_dev, pr, positivity=True, prec=64)
+    img, i_L, rep = multistep.two_step(pr, cycles=2, iters=30, precision=64, solver=s)
+    th1 = 1.01 * s.lipschitz(1)[0]
+    th2 = 1.01 * s.lipschitz(2)[0]
+    ref_iL, _, _ = twostep.major_cycles(1, pr.dirty_L, pr.psf_L, 2, 30, theta=th1, positivity=True)
+    assert rel(i_L.cpu().numpy(), ref_iL) <= TOL64
+    sig2 = helpers.sigma2_hat(pr.dirty_H)
+    assert rep["sigma2"] == pytest.approx(sig2, rel=1e-12)
+    ref_img, _, _ = twostep.major_cycles(2, pr.dirty_H, pr.psf_H, 2, 30, theta=th2, positivity=True, low_res=ref_iL,
+                                         ell=pr.ell, delta=pr.delta, sigma2=sig2, eta2=1e-3 * sig2)
+    assert rel(img.cpu().numpy(), ref_img) <= 1e-8
