@@ -3,7 +3,9 @@
  * two-step radio-interferometric reconstruction of Wang, Prunet, Mignot and
  * Ferrari, "Multi-Step Reconstruction of Radio-Interferometric Images".
  *
- * The library solves, with the dictionary W = I,
+ * The library solves, with the dictionary W = I (msr_config.dictionary = 0;
+ * the wavelet dictionary of msr_dictionary_synthesis takes x = W alpha and
+ * penalises ||alpha||_1 instead),
  *   step 1 (Eq. 4):  min_x ||i_L - H_L x||^2 + lambda_L ||x||_1
  *   step 2 (Eq. 5):  min_x ||G_H (i_H - H_H x)||^2 + ||G_L (l - x)||^2 + lambda_H ||x||_1
  * with FISTA (Algorithm 1: momentum (k-1)/(k+2), soft threshold at mu*lambda),
@@ -71,7 +73,9 @@ typedef struct msr_config {
     double prune_tol;    /* spectral columns k_x whose |h_hat| stays below prune_tol * max|h_hat|
                             are treated as zero; 0 keeps every column */
     int32_t precision;   /* 32: float32 images and arithmetic; 64: float64 */
-    int32_t reserved;    /* must be 0 */
+    int32_t dictionary;  /* 0: W = I (the image itself is sparse); 1: W = the concatenation of the
+                            orthonormal Daubechies bases db1 .. db8 (Sect. 3, App. A.1): separable 2-D,
+                            periodic, 4 levels, needs N >= 16; positivity is not available with it */
 } msr_config;
 
 typedef struct msr_solve {
@@ -180,6 +184,24 @@ msr_status msr_gradient(msr_ctx* ctx, int step, const void* x, const void* low_r
 
 /* H_s x (N x N in, N x N out): the PSF convolution of step s alone. */
 msr_status msr_apply_psf(msr_ctx* ctx, int step, const void* x, void* out, void* stream);
+
+/* The wavelet dictionary (msr_config.dictionary = 1; Sect. 3 and App. A.1):
+ * x = W alpha = sum_{b=1..8} Psi_b alpha_b, where Psi_b is the orthonormal
+ * 2-D transform of db_b (2b taps, minimum phase, low-pass sum sqrt(2),
+ * high-pass g[k] = (-1)^k h[2b-1-k]), periodic, 4 levels; each level filters
+ * the rows, then the columns, of the top-left s x s block and stores
+ * [low | high] halves (the approximation of the coarsest level ends in the
+ * top-left (N/16) x (N/16) corner).  coeffs: 8 x N x N reals, alpha_b at
+ * offset b N^2.  W W^T = 8 I, so with the dictionary a solve runs FISTA on
+ * alpha (the gradient is W^T of the image gradient, the prox is the soft
+ * threshold of alpha, theta is 8 times the image operator's), x0 is an image
+ * (alpha_0 = W^T x0 / 8, so W alpha_0 = x0), model_out receives W alpha_K
+ * and msr_result.l1_norm is ||alpha_K||_1; msr_lipschitz returns the theta
+ * of the problem in alpha, msr_objective and msr_gradient keep working on
+ * images (W = I).  Both calls use workspace scratch and
+ * synchronise the stream; MSR_ERR_STATE on a context without the dictionary. */
+msr_status msr_dictionary_synthesis(msr_ctx* ctx, const void* coeffs, void* image, void* stream);
+msr_status msr_dictionary_analysis(msr_ctx* ctx, const void* image, void* coeffs, void* stream);
 
 /* Copies the cached h_hat of step s to host memory as P x (P/2 + 1) doubles
  * (rfft half plane, row = k_y, column = k_x), pruned columns as zeros, and

@@ -34,7 +34,7 @@ class Config(C.Structure):
         ("seed", C.c_uint64),
         ("prune_tol", C.c_double),
         ("precision", C.c_int32),
-        ("reserved", C.c_int32),
+        ("dictionary", C.c_int32),
     ]
 
 
@@ -92,6 +92,8 @@ SYMBOLS = {
     "msr_objective": (_ST, [_P, C.c_int, C.c_double, _P, _P, C.POINTER(C.c_double), _P]),
     "msr_gradient": (_ST, [_P, C.c_int, _P, _P, _P, _P]),
     "msr_apply_psf": (_ST, [_P, C.c_int, _P, _P, _P]),
+    "msr_dictionary_synthesis": (_ST, [_P, _P, _P, _P]),
+    "msr_dictionary_analysis": (_ST, [_P, _P, _P, _P]),
     "msr_get_spectrum": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _P]),
     "msr_estimate_sigma2": (_ST, [_P, _P, C.POINTER(C.c_double), _P]),
     "msr_default_lambda": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), _P]),
@@ -148,13 +150,13 @@ def abi_version() -> int:
     return lib().msr_abi_version()
 
 
-def _cfg(n, pad=2, positivity=False, device=0, seed=0, prune_tol=1e-6, precision=32) -> Config:
+def _cfg(n, pad=2, positivity=False, device=0, seed=0, prune_tol=1e-6, precision=32, dictionary=0) -> Config:
     return Config(int(n), int(pad), int(bool(positivity)), int(device), int(seed), float(prune_tol),
-                  int(precision), 0)
+                  int(precision), int(dictionary))
 
 
-def workspace_bytes(n, pad=2, positivity=False, seed=0, prune_tol=1e-6, precision=32) -> int:
-    c = _cfg(n, pad, positivity, 0, seed, prune_tol, precision)
+def workspace_bytes(n, pad=2, positivity=False, seed=0, prune_tol=1e-6, precision=32, dictionary=0) -> int:
+    c = _cfg(n, pad, positivity, 0, seed, prune_tol, precision, dictionary)
     return int(lib().msr_workspace_bytes(C.byref(c)))
 
 
@@ -184,7 +186,7 @@ class Solver:
     """
 
     def __init__(self, n: int, pad: int = 2, positivity: bool = False, device: int = 0, seed: int = 0,
-                 prune_tol: float = 1e-6, precision: int = 32, _borrowed=None):
+                 prune_tol: float = 1e-6, precision: int = 32, dictionary: int = 0, _borrowed=None):
         import torch
 
         self._lib = lib()
@@ -200,7 +202,8 @@ class Solver:
         self.precision = precision
         self.dtype = torch.float32 if precision == 32 else torch.float64
         self.device = torch.device("cuda", device)
-        cfg = _cfg(n, pad, positivity, device, seed, prune_tol, precision)
+        self.dictionary = int(dictionary)
+        cfg = _cfg(n, pad, positivity, device, seed, prune_tol, precision, dictionary)
         h = C.c_void_p()
         st = self._lib.msr_init(C.byref(cfg), C.byref(h))
         if st != OK:
@@ -292,6 +295,20 @@ class Solver:
         y = self._img()
         self._check(self._lib.msr_apply_psf(self._h, step, self._p(x), self._p(y), _stream(stream)))
         return y
+
+    def synthesis(self, coeffs, stream=None):
+        """W alpha: (8, n, n) coefficients -> n x n image (dictionary 1)."""
+        x = self._img()
+        self._check(self._lib.msr_dictionary_synthesis(self._h, self._p(coeffs), self._p(x), _stream(stream)))
+        return x
+
+    def analysis(self, x, stream=None):
+        """W^T x: n x n image -> (8, n, n) coefficients (dictionary 1)."""
+        import torch
+
+        a = torch.empty((8, self.n, self.n), dtype=self.dtype, device=self.device)
+        self._check(self._lib.msr_dictionary_analysis(self._h, self._p(x), self._p(a), _stream(stream)))
+        return a
 
     def spectrum(self, step, stream=None):
         import numpy as np

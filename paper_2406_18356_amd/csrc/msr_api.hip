@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <complex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -30,6 +31,7 @@
 #include "../../include/msr.h"
 #include "ops.hpp"
 #include "small_kernels.hpp"
+#include "wavelet_kernels.hpp"
 
 using namespace msr;
 static_assert(kVariants <= MSR_MAX_VARIANTS, "variant table larger than the ABI's timing array");
@@ -75,6 +77,81 @@ const Ops<double>* ops_for_f64(int L, bool padded, int variant) { MSR_CASES(ops_
 
 namespace {
 
+// Low-pass taps of db_p (2p of them, sum sqrt(2), minimum phase) by spectral
+// factorisation: with y = sin^2(w/2), |H|^2 = 2 cos^{2p}(w/2) Q(y),
+// Q(y) = sum_{k<p} C(p-1+k, k) y^k.  Each root y_j of Q gives the root z_j of
+// z^2 - (2 - 4 y_j) z + 1 inside the unit circle, and
+// H(z) ~ (1 + z^-1)^p prod_j (1 - z_j z^-1).  Q's roots come from
+// Durand-Kerner iterations (degree <= 7) polished by Newton steps.
+// Returns false if the result is not orthonormal to 1e-10.
+bool daubechies_taps(int p, double* h) {
+    using cd = std::complex<double>;
+    std::vector<double> q(p);
+    for (int k = 0; k < p; ++k) {
+        double b = 1.0;  // C(p-1+k, k)
+        for (int i = 1; i <= k; ++i) b = b * (p - 1 + i) / i;
+        q[k] = b;
+    }
+    std::vector<cd> poly{cd(1.0)};
+    auto conv2 = [&](cd a0, cd a1) {
+        std::vector<cd> r(poly.size() + 1, cd(0.0));
+        for (size_t i = 0; i < poly.size(); ++i) {
+            r[i] += poly[i] * a0;
+            r[i + 1] += poly[i] * a1;
+        }
+        poly = r;
+    };
+    for (int i = 0; i < p; ++i) conv2(cd(1.0), cd(1.0));
+    const int d = p - 1;
+    if (d > 0) {
+        auto Q = [&](cd y) {
+            cd v(0.0);
+            for (int k = d; k >= 0; --k) v = v * y + q[k];
+            return v;
+        };
+        auto dQ = [&](cd y) {
+            cd v(0.0);
+            for (int k = d; k >= 1; --k) v = v * y + q[k] * (double)k;
+            return v;
+        };
+        std::vector<cd> r(d);
+        for (int i = 0; i < d; ++i) r[i] = std::pow(cd(0.4, 0.9), i);
+        for (int it = 0; it < 2000; ++it) {
+            double ch = 0.0;
+            for (int i = 0; i < d; ++i) {
+                cd den = q[d];
+                for (int j = 0; j < d; ++j)
+                    if (j != i) den *= (r[i] - r[j]);
+                const cd step = Q(r[i]) / den;
+                r[i] -= step;
+                ch = std::max(ch, std::abs(step));
+            }
+            if (ch < 1e-15) break;
+        }
+        for (int i = 0; i < d; ++i)
+            for (int it = 0; it < 5; ++it) {
+                const cd dq = dQ(r[i]);
+                if (std::abs(dq) == 0.0) break;
+                r[i] -= Q(r[i]) / dq;
+            }
+        for (int i = 0; i < d; ++i) {
+            const cd b = 2.0 - 4.0 * r[i];
+            const cd disc = std::sqrt(b * b - 4.0);
+            const cd z1 = (b + disc) / 2.0, z2 = (b - disc) / 2.0;
+            conv2(cd(1.0), -(std::abs(z1) < 1.0 ? z1 : z2));
+        }
+    }
+    double sum = 0.0;
+    for (int i = 0; i < 2 * p; ++i) sum += poly[i].real();
+    for (int i = 0; i < 2 * p; ++i) h[i] = poly[i].real() * std::sqrt(2.0) / sum;
+    for (int m = 0; m < p; ++m) {
+        double s = 0.0;
+        for (int i = 0; i + 2 * m < 2 * p; ++i) s += h[i] * h[i + 2 * m];
+        if (std::fabs(s - (m == 0 ? 1.0 : 0.0)) > 1e-10) return false;
+    }
+    return true;
+}
+
 constexpr double kThetaMargin = 1.01;  // Rayleigh quotients under-estimate lambda_max
 constexpr size_t kAlign = 256;
 
@@ -82,12 +159,13 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
     size_t tw, stwN, stwP, SA, SB, SC, SL, SG, hh1, hh2, d1, d2, b0, b1, t0, t1, mc0, mc1, mc2, mc3, partials, scal,
-        colmax, total;
+        colmax, cb0, cb1, ca, cg, wx, taps, total;
 };
 
 struct Shapes {
     int N, P, T, Cfull, Cpad, Tpsf, Cpad_psf;
     bool padded;
+    bool dict;           // wavelet dictionary: 8 coefficient arrays of N x N per state
     int prec;            // 32 or 64
     size_t rs, cs;       // bytes of a real / complex element
     size_t spec_elems;   // N * Cpad complex
@@ -125,6 +203,15 @@ bool make_shapes(const msr_config* c, Shapes& s, std::string* why) {
         if (why) *why = "precision must be 32 or 64";
         return false;
     }
+    if (c->dictionary != 0 && c->dictionary != 1) {
+        if (why) *why = "dictionary must be 0 (identity) or 1 (db1-db8)";
+        return false;
+    }
+    if (c->dictionary == 1 && c->n < (1 << kWaveletLevels)) {
+        if (why) *why = "the wavelet dictionary needs n >= 16";
+        return false;
+    }
+    s.dict = c->dictionary == 1;
     s.N = c->n;
     s.padded = c->pad == 2;
     s.P = c->pad * c->n;
@@ -181,6 +268,16 @@ Layout make_layout(const Shapes& s) {
     l.partials = take(sizeof(double) * s.partial_cnt);
     l.scal = take(sizeof(double) * 64);
     l.colmax = take(sizeof(double) * (size_t)s.Cfull);
+    if (s.dict) {
+        // coefficient states beta_{k-1}, beta_{k-2} (rotating), alpha_k, W^T g; the image W alpha; filters
+        const size_t ce = (size_t)kWaveletBases * s.img_elems * s.rs;
+        l.cb0 = take(ce);
+        l.cb1 = take(ce);
+        l.ca = take(ce);
+        l.cg = take(ce);
+        l.wx = take(s.rs * s.img_elems);
+        l.taps = take(sizeof(Taps<double>) * kWaveletBases);
+    }
     l.total = off;
     return l;
 }
@@ -301,6 +398,13 @@ struct Impl {
     R* dirty(int step) const { return at<R>(step == 1 ? c->lay.d1 : c->lay.d2); }
     R* beta(int k) const { return at<R>((k & 1) ? c->lay.b1 : c->lay.b0); }
     R* tmp(int i) const { return at<R>(i ? c->lay.t1 : c->lay.t0); }
+    bool dict() const { return c->sh.dict; }
+    size_t cn() const { return (size_t)kWaveletBases * c->sh.img_elems; }
+    R* coef(int k) const { return at<R>((k & 1) ? c->lay.cb1 : c->lay.cb0); }
+    R* cA() const { return at<R>(c->lay.ca); }
+    R* cG() const { return at<R>(c->lay.cg); }
+    R* wx() const { return at<R>(c->lay.wx); }
+    Taps<R>* taps(int b) const { return at<Taps<R>>(c->lay.taps) + b; }
     R* mc(int i) const {
         const size_t o[4] = {c->lay.mc0, c->lay.mc1, c->lay.mc2, c->lay.mc3};
         return at<R>(o[i]);
@@ -538,6 +642,9 @@ struct Impl {
             if (prev >= 0 && std::fabs(theta - prev) <= rtol * theta) break;
             prev = theta;
         }
+        // With the dictionary the variable is alpha and the normal operator is
+        // W^T A W; W W^T = M I makes its largest eigenvalue M times that of A.
+        if (dict()) theta *= kWaveletBases;
         if (theta_out) *theta_out = theta;
         if (iters_out) *iters_out = std::min(j, max_iter);
         return MSR_OK;
@@ -552,7 +659,23 @@ struct Impl {
         }
         HIPCHK(c, hipMemcpy(tw(), t.data(), sizeof(C) * Pn, hipMemcpyHostToDevice));
         TRY(stage_tables(N(), stwN()));
-        return stage_tables(Pn, stwP());
+        TRY(stage_tables(Pn, stwP()));
+        if (dict()) {
+            std::vector<Taps<R>> tp(kWaveletBases);
+            for (int b = 0; b < kWaveletBases; ++b) {
+                double h[kMaxTaps];
+                const int p = b + 1;
+                if (!daubechies_taps(p, h)) return fail(c, MSR_ERR_NUMERIC, "db%d filter is not orthonormal", p);
+                tp[b].L = 2 * p;
+                for (int k = 0; k < kMaxTaps; ++k) {
+                    const bool in = k < 2 * p;
+                    tp[b].h[k] = in ? (R)h[k] : (R)0;
+                    tp[b].g[k] = in ? (R)(((k & 1) ? -1.0 : 1.0) * h[2 * p - 1 - k]) : (R)0;
+                }
+            }
+            HIPCHK(c, hipMemcpy(taps(0), tp.data(), sizeof(Taps<R>) * kWaveletBases, hipMemcpyHostToDevice));
+        }
+        return MSR_OK;
     }
     // The FFT stage twiddle rows (w, w^2, w^4, w^8), w = exp(-2 pi i jm / (NS RD)),
     // of every stage of every E for transforms of length L (stage_offset).
@@ -700,8 +823,170 @@ struct Impl {
         return MSR_OK;
     }
 
+    // ---- wavelet dictionary ------------------------------------------------
+    // x = W a (8 coefficient arrays of N x N); scr: 2 N^2 scratch.
+    msr_status synthesize(const R* a, R* x, R* scr, hipStream_t s) {
+        const int n = N();
+        const size_t nn = c->sh.img_elems;
+        HIPCHK(c, hipMemsetAsync(x, 0, c->sh.rs * nn, s));
+        R* U = scr;
+        R* V = scr + nn;
+        for (int b = 0; b < kWaveletBases; ++b) {
+            const R* ab = a + (size_t)b * nn;
+            for (int j = kWaveletLevels - 1; j >= 0; --j) {
+                const int sj = n >> j;
+                const dim3 g((sj + 255) / 256, sj);
+                hipLaunchKernelGGL(idwt_cols<R>, g, dim3(256), 0, s, j == kWaveletLevels - 1 ? nullptr : (const R*)V, n,
+                                   ab, n, U, n, sj, (const Taps<R>*)taps(b));
+                LAUNCHCHK(c);
+                hipLaunchKernelGGL(idwt_rows<R>, g, dim3(256), 0, s, (const R*)U, n, j == 0 ? x : V, n, sj,
+                                   (const Taps<R>*)taps(b), j == 0 ? 1 : 0);
+                LAUNCHCHK(c);
+            }
+        }
+        return MSR_OK;
+    }
+    // a = W^T x; tmp: N^2 scratch.
+    msr_status analyze(const R* x, R* a, R* tmp, hipStream_t s) {
+        const int n = N();
+        const size_t nn = c->sh.img_elems;
+        for (int b = 0; b < kWaveletBases; ++b) {
+            R* ab = a + (size_t)b * nn;
+            for (int j = 0; j < kWaveletLevels; ++j) {
+                const int sj = n >> j;
+                hipLaunchKernelGGL(dwt_rows<R>, dim3((sj / 2 + 255) / 256, sj), dim3(256), 0, s,
+                                   j == 0 ? x : (const R*)ab, n, tmp, n, sj, (const Taps<R>*)taps(b));
+                LAUNCHCHK(c);
+                hipLaunchKernelGGL(dwt_cols<R>, dim3((sj + 255) / 256, sj / 2), dim3(256), 0, s, (const R*)tmp, n, ab, n,
+                                   sj, (const Taps<R>*)taps(b));
+                LAUNCHCHK(c);
+            }
+        }
+        return MSR_OK;
+    }
+    msr_status coeff_l1(const R* a, double* host, hipStream_t s) {
+        const size_t n = cn();
+        const int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
+        hipLaunchKernelGGL(image_sums<R>, dim3(blocks), dim3(256), 0, s, a, (const R*)nullptr, n, 0, partials());
+        LAUNCHCHK(c);
+        return reduce(blocks, 1, 8, host, s);
+    }
+    // F(beta) = data(W beta) + lambda ||beta||_1; out: F, data, ||beta||_1.
+    msr_status dict_objective(int step, double lambda, const R* beta, double out[3], hipStream_t s) {
+        TRY(synthesize(beta, wx(), cG(), s));
+        TRY(objective_at(step, lambda, wx(), out, s));
+        double l1 = 0.0;
+        TRY(coeff_l1(beta, &l1, s));
+        out[2] = l1;
+        out[0] = out[1] + lambda * l1;
+        return MSR_OK;
+    }
+    // One FISTA iteration on the coefficients (the gradient of Eq. 11 / 12 in
+    // alpha is 2 W^T (image-domain half-gradient at W alpha)).
+    msr_status dict_iterate(int step, int k, double mu, double lambda, hipStream_t s) {
+        TRY(synthesize(cA(), wx(), cG(), s));
+        TRY(fwd_image(step, wx(), (R)1, SA(), KA(step), s));
+        TRY(grad_chain(step, dirty(step), true, s));
+        RowArgs<R> a = step == 1 ? row_args(SB(), Ks(1), nullptr, 0, nullptr, 0)
+                                 : row_args(SB(), Ks(2), SG(), KLs(), nullptr, 0);
+        opr(step)->row_store(a, EpiStore<R>{wx(), N(), (R)1}, s);
+        LAUNCHCHK(c);
+        TRY(analyze(wx(), cG(), cA(), s));
+        const size_t n = cn();
+        const int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
+        hipLaunchKernelGGL(coeff_update<R>, dim3(blocks), dim3(256), 0, s, (const R*)coef(k - 1), coef(k),
+                           (const R*)cG(), cA(), n, (R)(2.0 * mu), (R)(mu * lambda), (R)momentum(k - 1),
+                           (R)momentum(k), partials());
+        LAUNCHCHK(c);
+        return MSR_OK;
+    }
+    msr_status dict_solve(int step, const msr_solve* opt, const R* low_res, const R* x0, R* model_out, R* image_out,
+                          msr_result* res, hipStream_t s) {
+        if (!c->have_theta[step - 1]) {
+            double th = 0.0;
+            TRY(power_iteration(step, 200, 1e-6, &th, nullptr, s));
+            if (!(th > 0)) return fail(c, MSR_ERR_NUMERIC, "zero Lipschitz constant");
+            c->theta[step - 1] = kThetaMargin * th;
+            c->have_theta[step - 1] = true;
+        }
+        const double theta = c->theta[step - 1], mu = 1.0 / theta;
+        const size_t cb = c->sh.rs * cn();
+        if (x0) {  // beta_0 = W^T x0 / M, so that W beta_0 = x0
+            TRY(analyze(x0, coef(0), wx(), s));
+            const size_t n = cn();
+            hipLaunchKernelGGL(scale_copy<R>, dim3(blocks_for(n)), dim3(256), 0, s, (const R*)coef(0), coef(0),
+                               (R)(1.0 / kWaveletBases), n);
+            LAUNCHCHK(c);
+        } else {
+            HIPCHK(c, hipMemsetAsync(coef(0), 0, cb, s));
+        }
+        HIPCHK(c, hipMemcpyAsync(coef(1), coef(0), cb, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(cA(), coef(0), cb, hipMemcpyDeviceToDevice, s));
+        if (step == 2) TRY(set_low_res(low_res, s));
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, hipEventRecord(e0, s));
+        const bool rule = opt->check_every > 0 && opt->f_ref != 0.0 && opt->tol > 0;
+        double F[3] = {0, 0, 0};
+        int k = 0;
+        bool conv = false;
+        double ttt = -1.0;
+        msr_status st = MSR_OK;
+        for (k = 1; k <= opt->max_iters; ++k) {
+            if ((st = dict_iterate(step, k, mu, opt->lambda, s)) != MSR_OK) break;
+            if (opt->check_every > 0 && (k % opt->check_every == 0)) {
+                if ((st = dict_objective(step, opt->lambda, coef(k), F, s)) != MSR_OK) break;
+                if (!std::isfinite(F[0])) {
+                    st = fail(c, MSR_ERR_NUMERIC, "objective is not finite at iteration %d", k);
+                    break;
+                }
+                if (rule && (F[0] - opt->f_ref) / std::fabs(opt->f_ref) <= opt->tol) {
+                    conv = true;
+                    float ms = 0.f;
+                    if (hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+                        ttt = ms;
+                    break;
+                }
+            }
+        }
+        const int done = std::min(k, opt->max_iters);
+        float ms = 0.f;
+        if (st == MSR_OK) {
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                st = fail(c, MSR_ERR_HIP, "event timing failed");
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (res) res->iters = done;
+        if (st != MSR_OK) return st;
+        TRY(dict_objective(step, opt->lambda, coef(done), F, s));
+        if (!std::isfinite(F[0])) return fail(c, MSR_ERR_NUMERIC, "objective is not finite after %d iterations", done);
+        // the image W beta is in wx after dict_objective
+        HIPCHK(c, hipMemcpyAsync(model_out, wx(), c->sh.rs * c->sh.img_elems, hipMemcpyDeviceToDevice, s));
+        if (image_out) {
+            TRY(residual_image(step, dirty(step), wx(), image_out, s));  // i~ - H W beta
+            TRY(axpby(image_out, image_out, wx(), (R)1, (R)1, s));     // + W beta
+        }
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (res) {
+            res->iters = done;
+            res->converged = conv ? 1 : 0;
+            res->objective = F[0];
+            res->data_term = F[1];
+            res->l1_norm = F[2];
+            res->theta = theta;
+            res->elapsed_ms = ms;
+            res->time_to_tol_ms = ttt;
+        }
+        return MSR_OK;
+    }
+
     msr_status solve(int step, const msr_solve* opt, const R* low_res, const R* x0, R* model_out, R* image_out,
                      msr_result* res, hipStream_t s) {
+        if (dict()) return dict_solve(step, opt, low_res, x0, model_out, image_out, res, s);
         double mu = 0.0;
         TRY(prepare(step, low_res, x0, &mu, s));
         const double theta = c->theta[step - 1];
@@ -1016,6 +1301,8 @@ msr_status msr_init(const msr_config* cfg, msr_ctx** out) {
     Shapes s;
     std::string why;
     if (!make_shapes(cfg, s, &why)) return MSR_ERR_INVALID;
+    // The prox of lambda ||alpha||_1 under x = W alpha >= 0 has no closed form.
+    if (s.dict && cfg->positivity) return MSR_ERR_UNSUPPORTED;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return MSR_ERR_INVALID;
     if (hipSetDevice(cfg->device) != hipSuccess) return MSR_ERR_HIP;
@@ -1203,6 +1490,32 @@ msr_status msr_autotune(msr_ctx* c, int reps, int* row_variant, int* col_variant
     return MSR_OK;
 }
 
+msr_status msr_dictionary_synthesis(msr_ctx* c, const void* coeffs, void* image, void* stream) {
+    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!c->sh.dict) return fail(c, MSR_ERR_STATE, "the context has no dictionary");
+    if (!coeffs || !image) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    HIPCHK(c, hipSetDevice(c->cfg.device));
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        TRY(im.synthesize(static_cast<const R*>(coeffs), static_cast<R*>(image), im.cG(), S(stream)));
+        HIPCHK(c, hipStreamSynchronize(S(stream)));
+        return MSR_OK;
+    });
+}
+
+msr_status msr_dictionary_analysis(msr_ctx* c, const void* image, void* coeffs, void* stream) {
+    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!c->sh.dict) return fail(c, MSR_ERR_STATE, "the context has no dictionary");
+    if (!coeffs || !image) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    HIPCHK(c, hipSetDevice(c->cfg.device));
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        TRY(im.analyze(static_cast<const R*>(image), static_cast<R*>(coeffs), im.cA(), S(stream)));
+        HIPCHK(c, hipStreamSynchronize(S(stream)));
+        return MSR_OK;
+    });
+}
+
 msr_status msr_time_pass(msr_ctx* c, int step, int which, int reps, double* ms_out, double* bytes_out,
                          double* flops_out, void* stream) {
     TRY(check_step(c, step, true));
@@ -1290,6 +1603,10 @@ bool plan_batch(int nch, const msr_config* cfgs, std::vector<msr_batch::Group>& 
         if (cfgs[i].pad != cfgs[0].pad || cfgs[i].precision != cfgs[0].precision ||
             cfgs[i].positivity != cfgs[0].positivity || cfgs[i].device != cfgs[0].device) {
             if (why) *why = "all channels need the same pad, precision, positivity and device";
+            return false;
+        }
+        if (cfgs[i].dictionary != 0) {
+            if (why) *why = "batched channels solve in the image domain (dictionary 0)";
             return false;
         }
     }

@@ -79,6 +79,15 @@ def test_init_rejects_bad_config_before_touching_a_device(lib):
     assert not h.value
     lib.msr_destroy(None)
     assert lib.msr_last_error(None) == b"null context"
+    # the wavelet dictionary: n >= 16, no positivity, 0/1 only
+    assert binding.workspace_bytes(8, dictionary=1) == 0
+    assert binding.workspace_bytes(16, dictionary=1) > binding.workspace_bytes(16)
+    assert binding.workspace_bytes(64, dictionary=2) == 0
+    cfg = binding._cfg(64, positivity=True, dictionary=1)
+    assert lib.msr_init(C.byref(cfg), C.byref(h)) == binding.ERR_UNSUPPORTED
+    assert not h.value
+    cfgs = (binding.Config * 2)(binding._cfg(64), binding._cfg(64, dictionary=1))
+    assert lib.msr_batch_workspace_bytes(2, cfgs) == 0  # batches solve in the image domain
 
 
 def test_batch_workspace_bytes_host_only(lib):
