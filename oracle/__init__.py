@@ -24,6 +24,14 @@ It is written to be read against the paper (Wang, Prunet, Mignot, Ferrari,
 * ``helpers``     -- sigma^2 / eta^2 estimators (Sect. 4.3), the lambda
                      schedule (Sect. 5 and App. A.2), the low-resolution
                      image (Sect. 3.2) and PSNR.
+* ``twostep``     -- both steps in sequence and their major cycles with
+                     image-domain residuals (Sect. 3.2, 3.3).
+* ``wavelets``    -- the dictionary W of Daubechies bases db1 .. db8
+                     (Sect. 3, App. A.1).
+* ``unet``        -- the learned warm start: a small U-Net with bfloat16
+                     storage, its forward pass, loss and gradients.
+* ``downsample``  -- the down-sampled low-resolution image: decimation D,
+                     up-sampling U and the small-grid filter term (Sect. 6.1).
 
 Every floating-point computation runs in float64 unless a caller asks for
 float32 (used only to time a float32 CPU variant).
