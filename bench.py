@@ -210,6 +210,41 @@ def psnr_study(torch, cycles=5, iters=100):
             "single_step": single, "two_step": rows}
 
 
+def dictionary_bench(torch, pr, tensors, iters=50):
+    """The paper's dictionary (db1-db8 concatenation, Sect. 3, App. A.1) on the
+    same workload: FISTA on the 8 N^2 wavelet coefficients, positivity off
+    (no closed-form prox with the dictionary).  Loop rates of both steps and
+    the two wavelet passes of an iteration against the HBM roofline."""
+    from paper_2406_18356_amd import Solver
+
+    dL, pL, dH, pH = tensors
+    s = Solver(pr.n, pad=2, positivity=False, prune_tol=1e-6, dictionary=1)
+    s.set_dirty_psf(1, dL, pL)
+    s.set_dirty_psf(2, dH, pH)
+    sig2 = s.estimate_sigma2(dH)
+    s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+    s.autotune(reps=10)
+    s.lipschitz(1)
+    s.lipschitz(2)
+    lam1, lam2 = s.default_lambda(1, 1, 0.05), s.default_lambda(2, 1, 0.05)
+    s.step1(lam1, 2)  # warm
+    b1, iL, r1 = s.step1(lam1, iters, image=True)
+    b2, r2 = s.step2(lam2, iL, iters)
+    passes = {}
+    for which, name in ((4, "synthesis"), (5, "analysis_update")):
+        ms, by, fl = s.time_pass(which, reps=10, step=1)
+        passes[name] = {"ms": ms, "bytes": by, "flops": fl, "gbs": by / (ms * 1e-3) / 1e9,
+                        "hbm_frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    out = {"workload": f"the same {pr.n}x{pr.n} two-step problem, W = db1-db8 (8 x {pr.n}^2 coefficients), "
+                       f"{iters} FISTA iterations per step, positivity off",
+           "step1_loop_iters_per_s": r1.iters / (r1.elapsed_ms * 1e-3),
+           "step2_loop_iters_per_s": r2.iters / (r2.elapsed_ms * 1e-3),
+           "step1_F": r1.objective, "step2_F": r2.objective, "passes": passes}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(pr, budget_s=15.0):
     """FP64 oracle step-1 FISTA iterations on this host (bounded sample)."""
     from oracle import objectives, fista
@@ -246,6 +281,7 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-unet", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
+    ap.add_argument("--no-dict", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=8)
     ap.add_argument("--ttt-ref-iters", type=int, default=20000)
     ap.add_argument("--profile-pass", type=int, nargs=3, action="append", default=None,
@@ -395,6 +431,11 @@ def main(argv=None):
         batch = batch_bench(torch, dev, args.batch_channels, iters)
         log("batch:", json.dumps(batch))
 
+    dictionary = None
+    if not args.no_dict:
+        dictionary = dictionary_bench(torch, pr, tensors)
+        log("dictionary:", json.dumps(dictionary))
+
     psnr = None
     if not args.no_psnr:
         psnr = psnr_study(torch)
@@ -427,6 +468,7 @@ def main(argv=None):
         "learned_warm_start": unet_report,
         "batch": batch,
         "partition_study": psnr,
+        "wavelet_dictionary": dictionary,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

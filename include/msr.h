@@ -185,6 +185,23 @@ msr_status msr_gradient(msr_ctx* ctx, int step, const void* x, const void* low_r
 /* H_s x (N x N in, N x N out): the PSF convolution of step s alone. */
 msr_status msr_apply_psf(msr_ctx* ctx, int step, const void* x, void* out, void* stream);
 
+/* The down-sampled low-resolution image (Sect. 6.1).  Step 1 may run on an
+ * image of N_s = N / d pixels a side (a context of size N_s with the short
+ * baselines' dirty image and PSF on the coarse grid, whose uv cells are those
+ * of the full grid); step 2 then takes out = U small as its low_res, where U
+ * zero-fills the DFT of the N_s x N_s image to N x N (the Nyquist cell split
+ * in halves between +-N_s/2) and transforms back: flux per pixel is
+ * conserved, and a flux-conserving decimation D of the DFT band undoes it
+ * (D U = I).  In circular mode || G_L (U small - x) ||^2 equals
+ * || G_L' (small - D x) ||^2 on the small grid with g_L' = g_L / d whenever
+ * ell + delta < N_s / 2, so step 2 on U small is the paper's step 2 with the
+ * decimation operator and the modified filter; zero padded, the library uses
+ * the same full-grid form.  factor: d, a power of two with N / d >= 2;
+ * small: N_s x N_s device image; out: N x N device image (not aliasing
+ * small).  Computed as K small K^T with the N x N_s interpolation matrix;
+ * uses workspace scratch and synchronises the stream. */
+msr_status msr_upsample(msr_ctx* ctx, int factor, const void* small, void* out, void* stream);
+
 /* The wavelet dictionary (msr_config.dictionary = 1; Sect. 3 and App. A.1):
  * x = W alpha = sum_{b=1..8} Psi_b alpha_b, where Psi_b is the orthonormal
  * 2-D transform of db_b (2b taps, minimum phase, low-pass sum sqrt(2),
@@ -236,9 +253,11 @@ msr_status msr_autotune(msr_ctx* ctx, int reps, int* row_variant, int* col_varia
  * algorithmic bytes and flops one launch moves / performs.  which: 0 = column
  * PSF pass, 1 = residual row pass, 2 = fused update row pass, 3 = step-2
  * low-band filter pass (C_w and C_{g_L^2}, Eq. 12; step 2 only, filters
- * set).  Flops count
- * 5 n log2 n per complex transform of length P.  Any output may be NULL.  For
- * measurement. */
+ * set); with the wavelet dictionary also 4 = W alpha (all levels, 8 N^2 read
+ * and N^2 written) and 5 = W^T of the gradient image with the fused FISTA
+ * coefficient update (all levels; N^2 + 4 x 8 N^2 moved).  Flops count
+ * 5 n log2 n per complex transform of length P and 4 L s^2 per 2-D wavelet
+ * level of size s and L taps.  Any output may be NULL.  For measurement. */
 msr_status msr_time_pass(msr_ctx* ctx, int step, int which, int reps, double* ms, double* bytes, double* flops,
                          void* stream);
 

@@ -93,6 +93,7 @@ SYMBOLS = {
     "msr_gradient": (_ST, [_P, C.c_int, _P, _P, _P, _P]),
     "msr_apply_psf": (_ST, [_P, C.c_int, _P, _P, _P]),
     "msr_dictionary_synthesis": (_ST, [_P, _P, _P, _P]),
+    "msr_upsample": (_ST, [_P, C.c_int, _P, _P, _P]),
     "msr_dictionary_analysis": (_ST, [_P, _P, _P, _P]),
     "msr_get_spectrum": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _P]),
     "msr_estimate_sigma2": (_ST, [_P, _P, C.POINTER(C.c_double), _P]),
@@ -295,6 +296,13 @@ class Solver:
         y = self._img()
         self._check(self._lib.msr_apply_psf(self._h, step, self._p(x), self._p(y), _stream(stream)))
         return y
+
+    def upsample(self, small, factor, stream=None):
+        """U small: an (n/factor)^2 low-resolution image up-sampled to n x n
+        (msr_upsample), the step-2 low_res for a down-sampled step 1."""
+        x = self._img()
+        self._check(self._lib.msr_upsample(self._h, int(factor), self._p(small), self._p(x), _stream(stream)))
+        return x
 
     def synthesis(self, coeffs, stream=None):
         """W alpha: (8, n, n) coefficients -> n x n image (dictionary 1)."""

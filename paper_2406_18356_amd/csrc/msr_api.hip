@@ -32,6 +32,7 @@
 #include "ops.hpp"
 #include "small_kernels.hpp"
 #include "wavelet_kernels.hpp"
+#include "resample_kernels.hpp"
 
 using namespace msr;
 static_assert(kVariants <= MSR_MAX_VARIANTS, "variant table larger than the ABI's timing array");
@@ -269,12 +270,14 @@ Layout make_layout(const Shapes& s) {
     l.scal = take(sizeof(double) * 64);
     l.colmax = take(sizeof(double) * (size_t)s.Cfull);
     if (s.dict) {
-        // coefficient states beta_{k-1}, beta_{k-2} (rotating), alpha_k, W^T g; the image W alpha; filters
+        // coefficient states beta_{k-1}, beta_{k-2} (rotating) and alpha_k; two
+        // regions of 8 (N/2)^2 for the lo-lo images between levels; the image
+        // W alpha; the filters
         const size_t ce = (size_t)kWaveletBases * s.img_elems * s.rs;
         l.cb0 = take(ce);
         l.cb1 = take(ce);
         l.ca = take(ce);
-        l.cg = take(ce);
+        l.cg = take(ce / 2);
         l.wx = take(s.rs * s.img_elems);
         l.taps = take(sizeof(Taps<double>) * kWaveletBases);
     }
@@ -402,7 +405,8 @@ struct Impl {
     size_t cn() const { return (size_t)kWaveletBases * c->sh.img_elems; }
     R* coef(int k) const { return at<R>((k & 1) ? c->lay.cb1 : c->lay.cb0); }
     R* cA() const { return at<R>(c->lay.ca); }
-    R* cG() const { return at<R>(c->lay.cg); }
+    // lo-lo images between levels: region i of 8 x (N/2)^2
+    R* wscr(int i) const { return at<R>(c->lay.cg) + (size_t)i * kWaveletBases * (c->sh.img_elems / 4); }
     R* wx() const { return at<R>(c->lay.wx); }
     Taps<R>* taps(int b) const { return at<Taps<R>>(c->lay.taps) + b; }
     R* mc(int i) const {
@@ -824,45 +828,83 @@ struct Impl {
     }
 
     // ---- wavelet dictionary ------------------------------------------------
-    // x = W a (8 coefficient arrays of N x N); scr: 2 N^2 scratch.
-    msr_status synthesize(const R* a, R* x, R* scr, hipStream_t s) {
+    // x = W a (a: 8 coefficient arrays of N x N), levels coarsest first.
+    msr_status synthesize(const R* a, R* x, hipStream_t s) {
         const int n = N();
-        const size_t nn = c->sh.img_elems;
-        HIPCHK(c, hipMemsetAsync(x, 0, c->sh.rs * nn, s));
-        R* U = scr;
-        R* V = scr + nn;
-        for (int b = 0; b < kWaveletBases; ++b) {
-            const R* ab = a + (size_t)b * nn;
-            for (int j = kWaveletLevels - 1; j >= 0; --j) {
-                const int sj = n >> j;
-                const dim3 g((sj + 255) / 256, sj);
-                hipLaunchKernelGGL(idwt_cols<R>, g, dim3(256), 0, s, j == kWaveletLevels - 1 ? nullptr : (const R*)V, n,
-                                   ab, n, U, n, sj, (const Taps<R>*)taps(b));
-                LAUNCHCHK(c);
-                hipLaunchKernelGGL(idwt_rows<R>, g, dim3(256), 0, s, (const R*)U, n, j == 0 ? x : V, n, sj,
-                                   (const Taps<R>*)taps(b), j == 0 ? 1 : 0);
-                LAUNCHCHK(c);
+        const long long q = (long long)(c->sh.img_elems / 4);
+        const R* ll = nullptr;
+        int ld_ll = 0;
+        for (int j = kWaveletLevels - 1; j >= 0; --j) {
+            const int sj = n >> j;
+            IdwtArgs<R> p{};
+            p.ll = ll;
+            p.ll_bs = q;
+            p.ld_ll = ld_ll;
+            p.coef = a;
+            p.cstride = (long long)c->sh.img_elems;
+            p.ldc = n;
+            p.s = sj;
+            p.taps = taps(0);
+            if (j == 0) {  // all bases summed into x
+                p.out = x;
+                p.ld_out = n;
+                p.bpb = kWaveletBases;
+            } else {
+                R* o = wscr((kWaveletLevels - 1 - j) & 1);
+                p.out = o;
+                p.out_bs = q;
+                p.ld_out = sj;
+                p.bpb = 1;
+                ll = o;
+                ld_ll = sj;
             }
+            const unsigned tiles = (unsigned)((sj + kIdwtT - 1) / kIdwtT);
+            hipLaunchKernelGGL(idwt_level<R>, dim3(tiles * tiles, 1, kWaveletBases / p.bpb), dim3(kWavThreads), 0, s,
+                               p);
+            LAUNCHCHK(c);
         }
         return MSR_OK;
     }
-    // a = W^T x; tmp: N^2 scratch.
-    msr_status analyze(const R* x, R* a, R* tmp, hipStream_t s) {
+    // W^T x, every coefficient through `epi` (a store, or the fused FISTA step).
+    msr_status analyze(const R* x, const WavEpi<R>& epi, hipStream_t s) {
         const int n = N();
-        const size_t nn = c->sh.img_elems;
-        for (int b = 0; b < kWaveletBases; ++b) {
-            R* ab = a + (size_t)b * nn;
-            for (int j = 0; j < kWaveletLevels; ++j) {
-                const int sj = n >> j;
-                hipLaunchKernelGGL(dwt_rows<R>, dim3((sj / 2 + 255) / 256, sj), dim3(256), 0, s,
-                                   j == 0 ? x : (const R*)ab, n, tmp, n, sj, (const Taps<R>*)taps(b));
-                LAUNCHCHK(c);
-                hipLaunchKernelGGL(dwt_cols<R>, dim3((sj + 255) / 256, sj / 2), dim3(256), 0, s, (const R*)tmp, n, ab, n,
-                                   sj, (const Taps<R>*)taps(b));
-                LAUNCHCHK(c);
+        const long long q = (long long)(c->sh.img_elems / 4);
+        const R* in = x;
+        long long in_bs = 0;
+        int ld_in = n;
+        for (int j = 0; j < kWaveletLevels; ++j) {
+            const int sj = n >> j;
+            DwtArgs<R> p{};
+            p.in = in;
+            p.in_bs = in_bs;
+            p.ld_in = ld_in;
+            p.s = sj;
+            p.bpb = j == 0 ? kWaveletBases : 1;  // level 0: the image is every basis's input
+            p.taps = taps(0);
+            p.epi = epi;
+            if (j < kWaveletLevels - 1) {
+                R* o = wscr(j & 1);
+                p.ll = o;
+                p.ll_bs = q;
+                p.ld_ll = sj / 2;
+                in = o;
+                in_bs = q;
+                ld_in = sj / 2;
             }
+            const unsigned tiles = (unsigned)((sj / 2 + kDwtT - 1) / kDwtT);
+            hipLaunchKernelGGL(dwt_level<R>, dim3(tiles * tiles, 1, kWaveletBases / p.bpb), dim3(kWavThreads), 0, s, p);
+            LAUNCHCHK(c);
         }
         return MSR_OK;
+    }
+    WavEpi<R> store_epi(R* out, R scale) const {
+        WavEpi<R> e{};
+        e.cstride = (long long)c->sh.img_elems;
+        e.ldc = N();
+        e.mode = 0;
+        e.out = out;
+        e.scale = scale;
+        return e;
     }
     msr_status coeff_l1(const R* a, double* host, hipStream_t s) {
         const size_t n = cn();
@@ -873,7 +915,7 @@ struct Impl {
     }
     // F(beta) = data(W beta) + lambda ||beta||_1; out: F, data, ||beta||_1.
     msr_status dict_objective(int step, double lambda, const R* beta, double out[3], hipStream_t s) {
-        TRY(synthesize(beta, wx(), cG(), s));
+        TRY(synthesize(beta, wx(), s));
         TRY(objective_at(step, lambda, wx(), out, s));
         double l1 = 0.0;
         TRY(coeff_l1(beta, &l1, s));
@@ -884,21 +926,23 @@ struct Impl {
     // One FISTA iteration on the coefficients (the gradient of Eq. 11 / 12 in
     // alpha is 2 W^T (image-domain half-gradient at W alpha)).
     msr_status dict_iterate(int step, int k, double mu, double lambda, hipStream_t s) {
-        TRY(synthesize(cA(), wx(), cG(), s));
+        TRY(synthesize(cA(), wx(), s));
         TRY(fwd_image(step, wx(), (R)1, SA(), KA(step), s));
         TRY(grad_chain(step, dirty(step), true, s));
         RowArgs<R> a = step == 1 ? row_args(SB(), Ks(1), nullptr, 0, nullptr, 0)
                                  : row_args(SB(), Ks(2), SG(), KLs(), nullptr, 0);
         opr(step)->row_store(a, EpiStore<R>{wx(), N(), (R)1}, s);
         LAUNCHCHK(c);
-        TRY(analyze(wx(), cG(), cA(), s));
-        const size_t n = cn();
-        const int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
-        hipLaunchKernelGGL(coeff_update<R>, dim3(blocks), dim3(256), 0, s, (const R*)coef(k - 1), coef(k),
-                           (const R*)cG(), cA(), n, (R)(2.0 * mu), (R)(mu * lambda), (R)momentum(k - 1),
-                           (R)momentum(k), partials());
-        LAUNCHCHK(c);
-        return MSR_OK;
+        WavEpi<R> e = store_epi(nullptr, (R)1);
+        e.mode = 1;
+        e.b1 = coef(k - 1);
+        e.b2 = coef(k);
+        e.a = cA();
+        e.two_mu = (R)(2.0 * mu);
+        e.thr = (R)(mu * lambda);
+        e.t_prev = (R)momentum(k - 1);
+        e.t_cur = (R)momentum(k);
+        return analyze(wx(), e, s);
     }
     msr_status dict_solve(int step, const msr_solve* opt, const R* low_res, const R* x0, R* model_out, R* image_out,
                           msr_result* res, hipStream_t s) {
@@ -912,11 +956,7 @@ struct Impl {
         const double theta = c->theta[step - 1], mu = 1.0 / theta;
         const size_t cb = c->sh.rs * cn();
         if (x0) {  // beta_0 = W^T x0 / M, so that W beta_0 = x0
-            TRY(analyze(x0, coef(0), wx(), s));
-            const size_t n = cn();
-            hipLaunchKernelGGL(scale_copy<R>, dim3(blocks_for(n)), dim3(256), 0, s, (const R*)coef(0), coef(0),
-                               (R)(1.0 / kWaveletBases), n);
-            LAUNCHCHK(c);
+            TRY(analyze(x0, store_epi(coef(0), (R)(1.0 / kWaveletBases)), s));
         } else {
             HIPCHK(c, hipMemsetAsync(coef(0), 0, cb, s));
         }
@@ -1042,6 +1082,34 @@ struct Impl {
             res->elapsed_ms = ms;
             res->time_to_tol_ms = ttt;
         }
+        return MSR_OK;
+    }
+
+    // out = U small (Sect. 6.1, the down-sampled low-resolution image):
+    // K small K^T with K[n][j] = k((n - d j) mod N), where
+    //   k(t) = (1/N) [1 + 2 sum_{q=1}^{m/2-1} cos(2 pi q t / N) + cos(pi m t / N)],  m = N / d
+    // (the DFT of small zero-filled to N x N, the Nyquist cell split in
+    // halves), evaluated through the Dirichlet closed form
+    //   1 + 2 sum_{q=1}^{M} cos(q th) = sin((M + 1/2) th) / sin(th / 2).
+    msr_status upsample(int d, const R* small, R* out, hipStream_t s) {
+        const int n = N(), m = n / d;
+        std::vector<R> tab(n);
+        for (int t = 0; t < n; ++t) {
+            const double th = 2.0 * M_PI * t / n;
+            const double dir = t == 0 ? (double)(m - 1) : std::sin((m / 2 - 0.5) * th) / std::sin(0.5 * th);
+            tab[t] = (R)((dir + std::cos(0.5 * m * th)) / n);
+        }
+        R* dtab = tmp(0);
+        R* T = tmp(1);  // small K^T: m x n
+        HIPCHK(c, hipMemcpyAsync(dtab, tab.data(), sizeof(R) * n, hipMemcpyHostToDevice, s));
+        const unsigned bn = (unsigned)((n + kRsT - 1) / kRsT), bm = (unsigned)((m + kRsT - 1) / kRsT);
+        hipLaunchKernelGGL((resample_product<R, DenseOperand<R>, KernelCols<R>>), dim3(bn, bm), dim3(kRsThreads), 0, s,
+                           DenseOperand<R>{small, m}, KernelCols<R>{dtab, n - 1, d}, T, n, m, n, m);
+        LAUNCHCHK(c);
+        hipLaunchKernelGGL((resample_product<R, KernelRows<R>, DenseOperand<R>>), dim3(bn, bn), dim3(kRsThreads), 0, s,
+                           KernelRows<R>{dtab, n - 1, d}, DenseOperand<R>{T, n}, out, n, n, n, m);
+        LAUNCHCHK(c);
+        HIPCHK(c, hipStreamSynchronize(s));  // also keeps `tab` alive until its copy is done
         return MSR_OK;
     }
 
@@ -1203,7 +1271,14 @@ struct Impl {
         const double es = (double)c->sh.cs, rs = (double)c->sh.rs;
         const double img = (double)Nn * Nn * rs;
         const double fft_p = 5.0 * Pn * std::log2((double)Pn);
+        WavEpi<R> upd = store_epi(nullptr, (R)1);  // which 5: the fused coefficient update
+        upd.mode = 1;
+        upd.b1 = coef(0);
+        upd.b2 = coef(1);
+        upd.a = cA();
         auto launch = [&]() -> msr_status {
+            if (which == 4) return synthesize(cA(), wx(), s);
+            if (which == 5) return analyze(wx(), upd, s);
             if (which == 0) return col_psf(step, SA(), SB(), s);
             if (which == 3) return col_filt_wl(SL(), s);
             if (which == 1) {
@@ -1222,7 +1297,23 @@ struct Impl {
             return MSR_OK;
         };
         double bytes, flops;
-        if (which == 0) {
+        // a 2-D level of a basis with L taps costs 4 L s^2 flops either way
+        const double lev = (double)Nn * Nn * (1.0 + 1.0 / 4 + 1.0 / 16 + 1.0 / 64);
+        const double wav_flops = 4.0 * lev * (double)(kWaveletBases * (kWaveletBases + 1));  // sum of L = 2 + .. + 16
+        if (which >= 4) {
+            const size_t cb = c->sh.rs * cn();
+            HIPCHK(c, hipMemsetAsync(coef(0), 0, cb, s));
+            HIPCHK(c, hipMemsetAsync(coef(1), 0, cb, s));
+            HIPCHK(c, hipMemsetAsync(cA(), 0, cb, s));
+            HIPCHK(c, hipMemsetAsync(wx(), 0, c->sh.rs * c->sh.img_elems, s));
+        }
+        if (which == 4) {  // read alpha (M N^2), write x (N^2)
+            bytes = (kWaveletBases + 1.0) * img;
+            flops = wav_flops;
+        } else if (which == 5) {  // read the gradient image, beta_{k-1}, beta_{k-2}; write beta_k, alpha_k
+            bytes = (1.0 + 4.0 * kWaveletBases) * img;
+            flops = wav_flops;
+        } else if (which == 0) {
             bytes = 2.0 * Nn * K * es + (double)Pn * K * rs;
             flops = 2.0 * K * fft_p;
         } else if (which == 3) {
@@ -1490,6 +1581,18 @@ msr_status msr_autotune(msr_ctx* c, int reps, int* row_variant, int* col_variant
     return MSR_OK;
 }
 
+msr_status msr_upsample(msr_ctx* c, int factor, const void* small, void* out, void* stream) {
+    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (factor < 2 || (factor & (factor - 1)) || c->sh.N / factor < 2)
+        return fail(c, MSR_ERR_INVALID, "factor must be a power of two with N / factor >= 2");
+    if (!small || !out || small == out) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    HIPCHK(c, hipSetDevice(c->cfg.device));
+    return with_impl(c, [&](auto& im) {
+        using R = std::remove_pointer_t<decltype(im.dirty(1))>;
+        return im.upsample(factor, static_cast<const R*>(small), static_cast<R*>(out), S(stream));
+    });
+}
+
 msr_status msr_dictionary_synthesis(msr_ctx* c, const void* coeffs, void* image, void* stream) {
     if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
     if (!c->sh.dict) return fail(c, MSR_ERR_STATE, "the context has no dictionary");
@@ -1497,7 +1600,7 @@ msr_status msr_dictionary_synthesis(msr_ctx* c, const void* coeffs, void* image,
     HIPCHK(c, hipSetDevice(c->cfg.device));
     return with_impl(c, [&](auto& im) {
         using R = std::remove_pointer_t<decltype(im.dirty(1))>;
-        TRY(im.synthesize(static_cast<const R*>(coeffs), static_cast<R*>(image), im.cG(), S(stream)));
+        TRY(im.synthesize(static_cast<const R*>(coeffs), static_cast<R*>(image), S(stream)));
         HIPCHK(c, hipStreamSynchronize(S(stream)));
         return MSR_OK;
     });
@@ -1510,7 +1613,7 @@ msr_status msr_dictionary_analysis(msr_ctx* c, const void* image, void* coeffs, 
     HIPCHK(c, hipSetDevice(c->cfg.device));
     return with_impl(c, [&](auto& im) {
         using R = std::remove_pointer_t<decltype(im.dirty(1))>;
-        TRY(im.analyze(static_cast<const R*>(image), static_cast<R*>(coeffs), im.cA(), S(stream)));
+        TRY(im.analyze(static_cast<const R*>(image), im.store_epi(static_cast<R*>(coeffs), (R)1), S(stream)));
         HIPCHK(c, hipStreamSynchronize(S(stream)));
         return MSR_OK;
     });
@@ -1519,7 +1622,8 @@ msr_status msr_dictionary_analysis(msr_ctx* c, const void* image, void* coeffs, 
 msr_status msr_time_pass(msr_ctx* c, int step, int which, int reps, double* ms_out, double* bytes_out,
                          double* flops_out, void* stream) {
     TRY(check_step(c, step, true));
-    if (reps <= 0 || which < 0 || which > 3) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    if (reps <= 0 || which < 0 || which > 5) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    if (which >= 4 && !c->sh.dict) return fail(c, MSR_ERR_STATE, "passes 4 and 5 need the wavelet dictionary");
     if (which == 3 && (step != 2 || !c->have_filters))
         return fail(c, MSR_ERR_STATE, "the filter pass needs step 2 with filters set");
     return with_impl(c, [&](auto& im) {

@@ -7,8 +7,25 @@
 //   analysis   lo[i] = sum_k h[k] x[(2i + k) mod s],  hi[i] = sum_k g[k] x[(2i + k) mod s]
 //   synthesis  x[n]  = sum_{k = n mod 2, k < L} lo[m] h[k] + hi[m] g[k],  m = ((n - k) / 2) mod s/2
 // (the synthesis is the transpose of the analysis, which is orthonormal).
-// Arrays are row-major with row stride ld; a level works on the top-left
-// s x s block.  Analysis: rows then columns; synthesis: columns then rows.
+// A 2-D level filters the rows, then the columns, of the top-left s x s
+// block; its output quadrants are (rows: column filter, columns: row filter)
+//   [0, s/2) x [0, s/2): lo-lo (the next level's input)   [0, s/2) x [s/2, s): lo rows of the row-hi half
+//   [s/2, s) x [0, s/2): hi rows of the row-lo half        [s/2, s) x [s/2, s): hi-hi
+//
+// Offsets are 32-bit: 8 N^2 < 2^31 for N <= 8192.
+//
+// Each kernel does one whole 2-D level (both axes) for a tile, through LDS:
+//   dwt_level   reads a (2T + 14)^2 input tile once and writes the four T x T
+//               output quadrants of every basis the block handles;
+//   idwt_level  reads four (T' / 2 + 7)^2 quadrant tiles and writes a T' x T'
+//               output tile (level 0: the sum over all 8 bases, so x is
+//               written once).
+// Level 0 of the analysis shares its input (the image) between the bases, so
+// one block loops over all 8 and reads the tile once; level 0 of the synthesis
+// sums the bases in registers.  The other levels run one basis per block
+// (grid z).  Coefficients that leave the transform (the detail quadrants, and
+// the coarsest lo-lo quadrant) go through an epilogue: a plain store, or the
+// FISTA step on the coefficients fused in (so W^T g is never stored).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -25,117 +42,354 @@ struct Taps {
     int L;
 };
 
-// Rows: out[r][i] = lo, out[r][s/2 + i] = hi, r < s, i < s/2.
+constexpr int kDwtT = 32;                        // analysis: output quadrant tile side
+constexpr int kDwtIn = 2 * kDwtT + kMaxTaps - 2;  // input tile side (78)
+constexpr int kDwtY = 2 * kDwtT + 4;             // row-pass row length: rows 8 apart fall 32 banks apart
+constexpr int kIdwtT = 64;                       // synthesis: output tile side
+constexpr int kIdwtHalo = kMaxTaps / 2 - 1;      // 7 quadrant rows before the tile
+constexpr int kIdwtQ = kIdwtT / 2 + kIdwtHalo;   // quadrant tile side (39)
+constexpr int kWavThreads = 256;
+// Waves per SIMD the LDS footprint allows (about 45 KB per block in FP32, 90 KB
+// in FP64, of 160 KB): the register budget is capped to match.
 template <typename R>
-__global__ void dwt_rows(const R* __restrict__ in, int ld_in, R* __restrict__ out, int ld_out, int s,
-                         const Taps<R>* __restrict__ taps) {
-    const int r = blockIdx.y;
-    const int half = s / 2;
-    const Taps<R> t = *taps;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < half; i += gridDim.x * blockDim.x) {
-        R lo = 0, hi = 0;
-        for (int k = 0; k < t.L; ++k) {
-            const R x = in[(size_t)r * ld_in + ((2 * i + k) & (s - 1))];
-            lo += t.h[k] * x;
-            hi += t.g[k] * x;
-        }
-        out[(size_t)r * ld_out + i] = lo;
-        out[(size_t)r * ld_out + half + i] = hi;
-    }
+constexpr int kWavWaves = sizeof(R) == 4 ? 3 : 1;
+
+// Where coefficients that leave the transform go.  Basis b's coefficients
+// are at offset b * cstride, row stride ldc.
+//   mode 0: out = scale * w
+//   mode 1: one FISTA step with the gradient coefficient w = W^T of the
+//           half-gradient image: alpha_{k-1} = b1 + t_prev (b1 - b2),
+//           beta_k = soft(alpha_{k-1} - 2 mu w, mu lambda) -> b2,
+//           alpha_k = beta_k + t_cur (beta_k - b1) -> a.
+// threadIdx.x behind an empty asm: index arithmetic derived from it stays
+// where it is written instead of being hoisted out of the basis loop and the
+// tap-count switch, which would keep hundreds of addresses live (spills).
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
 }
 
-// Columns: out[i][c] = lo, out[s/2 + i][c] = hi, c < s, i < s/2.
-template <typename R>
-__global__ void dwt_cols(const R* __restrict__ in, int ld_in, R* __restrict__ out, int ld_out, int s,
-                         const Taps<R>* __restrict__ taps) {
-    const int i = blockIdx.y;
-    const int half = s / 2;
-    const Taps<R> t = *taps;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < s; c += gridDim.x * blockDim.x) {
-        R lo = 0, hi = 0;
-        for (int k = 0; k < t.L; ++k) {
-            const R x = in[(size_t)((2 * i + k) & (s - 1)) * ld_in + c];
-            lo += t.h[k] * x;
-            hi += t.g[k] * x;
-        }
-        out[(size_t)i * ld_out + c] = lo;
-        out[(size_t)(half + i) * ld_out + c] = hi;
-    }
+// The tile of this block in a g x g tile grid launched as gridDim.x = g^2.
+// Consecutive blocks go to different XCDs (8 of them), so when g^2 is a
+// multiple of 8 each XCD is given one contiguous row-major range of tiles:
+// neighbouring tiles, whose input halos overlap, then share that XCD's L2.
+__device__ __forceinline__ void xcd_tile(int g, int& tx, int& ty) {
+    const int n = g * g;
+    int id = blockIdx.x;
+    if ((n & 7) == 0) id = (id & 7) * (n >> 3) + (id >> 3);
+    tx = id % g;
+    ty = id / g;
 }
 
-// Synthesis along columns of the s x s block: rows [0, s/2) are lo, [s/2, s)
-// hi.  The top-left s/2 x s/2 quadrant comes from `ll` (row stride ld_ll)
-// when given, everything else from `det` (row stride ld_det).
 template <typename R>
-__global__ void idwt_cols(const R* __restrict__ ll, int ld_ll, const R* __restrict__ det, int ld_det,
-                          R* __restrict__ out, int ld_out, int s, const Taps<R>* __restrict__ taps) {
-    const int n = blockIdx.y;
-    const int half = s / 2;
-    const Taps<R> t = *taps;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < s; c += gridDim.x * blockDim.x) {
-        R acc = 0;
-        for (int k = n & 1; k < t.L; k += 2) {
-            const int m = ((n - k) / 2 + half) & (half - 1);  // (n - k) is even here
-            const R lo = (ll && c < half) ? ll[(size_t)m * ld_ll + c] : det[(size_t)m * ld_det + c];
-            const R hi = det[(size_t)(half + m) * ld_det + c];
-            acc += t.h[k] * lo + t.g[k] * hi;
-        }
-        out[(size_t)n * ld_out + c] = acc;
+struct WavEpi {
+    unsigned cstride;
+    int ldc;
+    int mode;
+    R* out;
+    R scale;
+    const R* b1;
+    R* b2;
+    R* a;
+    R two_mu, thr, t_prev, t_cur;
+};
+
+// The update's operands are loaded before the column sums (wav_fetch) so
+// that their latency overlaps the arithmetic; wav_emit finishes.
+template <typename R>
+__device__ __forceinline__ void wav_fetch(const WavEpi<R>& e, int b, int row, int col, R& p1, R& p2) {
+    const unsigned p = (unsigned)b * e.cstride + (unsigned)row * e.ldc + col;
+    p1 = e.b1[p];
+    p2 = e.b2[p];
+}
+template <typename R>
+__device__ __forceinline__ void wav_emit(const WavEpi<R>& e, int b, int row, int col, R w, R p1, R p2) {
+    const unsigned p = (unsigned)b * e.cstride + (unsigned)row * e.ldc + col;
+    if (e.mode == 0) {
+        e.out[p] = e.scale * w;
+        return;
     }
+    const R al = p1 + e.t_prev * (p1 - p2);
+    const R z = al - e.two_mu * w;
+    const R zero = 0;
+    const R beta = copysign(fmax(fabs(z) - e.thr, zero), z);
+    e.b2[p] = beta;
+    e.a[p] = beta + e.t_cur * (beta - p1);
 }
 
-// Synthesis along rows: columns [0, s/2) lo, [s/2, s) hi; out += result when
-// accumulate (the final level adds one basis's image into the sum).
 template <typename R>
-__global__ void idwt_rows(const R* __restrict__ in, int ld_in, R* __restrict__ out, int ld_out, int s,
-                          const Taps<R>* __restrict__ taps, int accumulate) {
-    const int r = blockIdx.y;
-    const int half = s / 2;
-    const Taps<R> t = *taps;
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < s; n += gridDim.x * blockDim.x) {
-        R acc = 0;
-        for (int k = n & 1; k < t.L; k += 2) {
-            const int m = ((n - k) / 2 + half) & (half - 1);
-            acc += t.h[k] * in[(size_t)r * ld_in + m] + t.g[k] * in[(size_t)r * ld_in + half + m];
-        }
-        const size_t o = (size_t)r * ld_out + n;
-        out[o] = accumulate ? out[o] + acc : acc;
-    }
-}
+struct DwtArgs {
+    const R* in;       // level input: top-left s x s block, row stride ld_in
+    unsigned in_bs;    // basis stride of the input (0: one input shared by all bases)
+    int ld_in;
+    R* ll;             // lo-lo output (s/2 x s/2, row stride ld_ll, basis stride ll_bs); null: to the epilogue
+    unsigned ll_bs;
+    int ld_ll;
+    int s;
+    int bpb;           // bases per block (blockIdx.z * bpb is the first)
+    const Taps<R>* taps;
+    WavEpi<R> epi;
+};
 
-// FISTA update on coefficients (no positivity: the dictionary's prox is soft
-// thresholding), with gc = W^T of the half-gradient image:
-//   alpha_{k-1} = b1 + t_prev (b1 - b2);  beta_k = soft(alpha_{k-1} - 2 mu gc, mu lambda)
-//   alpha_k = beta_k + t_cur (beta_k - b1);  beta_k -> b2, alpha_k -> a;  partial sums of |beta_k|.
-template <typename R>
-__global__ void __launch_bounds__(256) coeff_update(const R* __restrict__ b1, R* __restrict__ b2,
-                                                    const R* __restrict__ gc, R* __restrict__ a, size_t n,
-                                                    R two_mu, R thr, R t_prev, R t_cur,
-                                                    double* __restrict__ partials) {
-    __shared__ double red[4];
-    double s = 0.0;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        const R p1 = b1[i], p2 = b2[i];
-        const R al = p1 + t_prev * (p1 - p2);
-        const R z = al - two_mu * gc[i];
-        const R zero = 0;
-        const R beta = copysign(fmax(fabs(z) - thr, zero), z);
-        b2[i] = beta;
-        a[i] = beta + t_cur * (beta - p1);
-        s += fabs((double)beta);
-    }
+template <typename R, int L>
+__device__ __forceinline__ void dwt_tile(const DwtArgs<R>& p, int b, R (*X)[kDwtIn + 1], R (*Y)[kDwtY],
+                                         int i0, int c0) {
+    const Taps<R>& t = p.taps[b];
+    const int half = p.s >> 1;
+    const int tid = opaque_tid();
+    const int c = tid % kDwtT;
+    const int q = tid / kDwtT;  // 0 .. 7
+    const int col = c0 + c;
+    // the update's operands of this thread's 16 outputs (band order ll, lh,
+    // hl, hh), loaded first so that they arrive during both passes
+    R o1[4][4], o2[4][4];
+    const bool fetch = p.epi.mode == 1 && col < half;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    for (int j = 0; j < 4; ++j) {
+        const int row = i0 + 4 * q + j;
+        if (fetch && row < half) {
+            if (!p.ll) wav_fetch(p.epi, b, row, col, o1[j][0], o2[j][0]);
+            wav_fetch(p.epi, b, row, half + col, o1[j][1], o2[j][1]);
+            wav_fetch(p.epi, b, half + row, col, o1[j][2], o2[j][2]);
+            wav_fetch(p.epi, b, half + row, half + col, o1[j][3], o2[j][3]);
+        }
+    }
+    // rows: Y[r][c] = lo, Y[r][T + c] = hi of input row r, output column c
+    constexpr int nrows = 2 * kDwtT + L - 2;
+#pragma unroll 2
+    for (int e = tid; e < nrows * kDwtT; e += kWavThreads) {
+        const int r = e / kDwtT, c = e % kDwtT;
+        R lo = 0, hi = 0;
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const R x = X[r][2 * c + k];
+            lo += t.h[k] * x;
+            hi += t.g[k] * x;
+        }
+        Y[r][c] = lo;
+        Y[r][kDwtT + c] = hi;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    // columns (below): each thread 4 consecutive output rows of one column
+    R ll[4] = {0, 0, 0, 0}, lh[4] = {0, 0, 0, 0}, hl[4] = {0, 0, 0, 0}, hh[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < L + 6; ++u) {
+        const R ylo = Y[8 * q + u][c], yhi = Y[8 * q + u][kDwtT + c];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = u - 2 * j;
+            if (k >= 0 && k < L) {
+                ll[j] += t.h[k] * ylo;
+                lh[j] += t.h[k] * yhi;
+                hl[j] += t.g[k] * ylo;
+                hh[j] += t.g[k] * yhi;
+            }
+        }
+    }
+    if (col < half) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = i0 + 4 * q + j;
+            if (row < half) {
+                if (p.ll)
+                    p.ll[(unsigned)b * p.ll_bs + (unsigned)row * p.ld_ll + col] = ll[j];
+                else
+                    wav_emit(p.epi, b, row, col, ll[j], o1[j][0], o2[j][0]);
+                wav_emit(p.epi, b, row, half + col, lh[j], o1[j][1], o2[j][1]);
+                wav_emit(p.epi, b, half + row, col, hl[j], o1[j][2], o2[j][2]);
+                wav_emit(p.epi, b, half + row, half + col, hh[j], o1[j][3], o2[j][3]);
+            }
+        }
+    }
 }
 
-// dst[i] = a * src[i]
+// Grid: (g^2, 1, kWaveletBases / bpb) with g = ceil(s/2 / T), 256 threads.
 template <typename R>
-__global__ void scale_copy(const R* __restrict__ src, R* __restrict__ dst, R a, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = a * src[i];
+__global__ void __launch_bounds__(kWavThreads) __attribute__((amdgpu_waves_per_eu(kWavWaves<R>)))
+dwt_level(DwtArgs<R> p) {
+    __shared__ R X[kDwtIn][kDwtIn + 1];
+    __shared__ R Y[kDwtIn][kDwtY];
+    const int mask = p.s - 1;
+    int tx, ty;
+    xcd_tile(((p.s >> 1) + kDwtT - 1) / kDwtT, tx, ty);
+    const int i0 = ty * kDwtT, c0 = tx * kDwtT;
+    for (int bi = 0; bi < p.bpb; ++bi) {
+        const int b = blockIdx.z * p.bpb + bi;
+        if (bi > 0) __syncthreads();  // the previous basis is done with X and Y
+        if (bi == 0 || p.in_bs != 0) {
+            // all of a thread's loads are issued before the first LDS store
+            constexpr int NL = (kDwtIn * kDwtIn + kWavThreads - 1) / kWavThreads;
+            const int tid = opaque_tid();
+            const R* src = p.in + (unsigned)b * p.in_bs;
+            R v[NL];
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int e = tid + i * kWavThreads;
+                const int r = e / kDwtIn, c = e % kDwtIn;
+                if (e < kDwtIn * kDwtIn) v[i] = src[(unsigned)((2 * i0 + r) & mask) * p.ld_in + ((2 * c0 + c) & mask)];
+            }
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int e = tid + i * kWavThreads;
+                if (e < kDwtIn * kDwtIn) X[e / kDwtIn][e % kDwtIn] = v[i];
+            }
+            __syncthreads();
+        }
+        switch (p.taps[b].L) {
+            case 2: dwt_tile<R, 2>(p, b, X, Y, i0, c0); break;
+            case 4: dwt_tile<R, 4>(p, b, X, Y, i0, c0); break;
+            case 6: dwt_tile<R, 6>(p, b, X, Y, i0, c0); break;
+            case 8: dwt_tile<R, 8>(p, b, X, Y, i0, c0); break;
+            case 10: dwt_tile<R, 10>(p, b, X, Y, i0, c0); break;
+            case 12: dwt_tile<R, 12>(p, b, X, Y, i0, c0); break;
+            case 14: dwt_tile<R, 14>(p, b, X, Y, i0, c0); break;
+            default: dwt_tile<R, 16>(p, b, X, Y, i0, c0); break;
+        }
+    }
+}
+
+template <typename R>
+struct IdwtArgs {
+    const R* ll;       // lo-lo input (s/2 x s/2, row stride ld_ll, basis stride ll_bs); null: from the coefficients
+    unsigned ll_bs;
+    int ld_ll;
+    const R* coef;     // coefficients: basis b at b * cstride, row stride ldc
+    unsigned cstride;
+    int ldc;
+    R* out;            // s x s output, row stride ld_out, basis stride out_bs (bpb = 8: the sum, one image)
+    unsigned out_bs;
+    int ld_out;
+    int s;
+    int bpb;
+    const Taps<R>* taps;
+};
+
+template <typename R, int L>
+__device__ __forceinline__ void idwt_tile(const IdwtArgs<R>& p, int b, R (*Q)[kIdwtQ][kIdwtQ + 1],
+                                          R (*U)[2 * kIdwtQ + 1], R (*acc)[2]) {
+    const Taps<R>& t = p.taps[b];
+    const int tid = opaque_tid();
+    // columns: U[n][c] (c < Q: the row-lo half, c >= Q: the row-hi half) for
+    // the output row pair (2 np, 2 np + 1); both rows read quadrant rows
+    // np - kk + halo, the even one with taps 2 kk, the odd one with 2 kk + 1.
+#pragma unroll 2
+    for (int e = tid; e < (kIdwtT / 2) * (2 * kIdwtQ); e += kWavThreads) {
+        const int np = e / (2 * kIdwtQ), cc = e % (2 * kIdwtQ);
+        const int hiq = cc >= kIdwtQ;
+        const int c = cc - hiq * kIdwtQ;
+        const R (*qa)[kIdwtQ + 1] = Q[hiq];      // lo rows: ll or lh
+        const R (*qb)[kIdwtQ + 1] = Q[2 + hiq];  // hi rows: hl or hh
+        R ev = 0, od = 0;
+#pragma unroll
+        for (int kk = 0; kk < L / 2; ++kk) {
+            const int r = np - kk + kIdwtHalo;
+            const R lo = qa[r][c], hi = qb[r][c];
+            ev += t.h[2 * kk] * lo + t.g[2 * kk] * hi;
+            od += t.h[2 * kk + 1] * lo + t.g[2 * kk + 1] * hi;
+        }
+        U[2 * np][cc] = ev;
+        U[2 * np + 1][cc] = od;
+    }
+    __syncthreads();
+    // rows: output pair (2 mp, 2 mp + 1) of row n
+#pragma unroll
+    for (int j = 0; j < (kIdwtT * kIdwtT / 2) / kWavThreads; ++j) {
+        const int e = tid + j * kWavThreads;
+        const int n = e / (kIdwtT / 2), mp = e % (kIdwtT / 2);
+        R ev = 0, od = 0;
+#pragma unroll
+        for (int kk = 0; kk < L / 2; ++kk) {
+            const int m = mp - kk + kIdwtHalo;
+            const R lo = U[n][m], hi = U[n][kIdwtQ + m];
+            ev += t.h[2 * kk] * lo + t.g[2 * kk] * hi;
+            od += t.h[2 * kk + 1] * lo + t.g[2 * kk + 1] * hi;
+        }
+        acc[j][0] += ev;
+        acc[j][1] += od;
+    }
+}
+
+// Grid: (g^2, 1, kWaveletBases / bpb) with g = ceil(s / T'), 256 threads.
+template <typename R>
+__global__ void __launch_bounds__(kWavThreads) __attribute__((amdgpu_waves_per_eu(kWavWaves<R>)))
+idwt_level(IdwtArgs<R> p) {
+    __shared__ R Q[4][kIdwtQ][kIdwtQ + 1];  // lo-lo, lo rows of row-hi, hi rows of row-lo, hi-hi
+    __shared__ R U[kIdwtT][2 * kIdwtQ + 1];
+    constexpr int J = (kIdwtT * kIdwtT / 2) / kWavThreads;
+    const int half = p.s >> 1, hm = half - 1;
+    int tx, ty;
+    xcd_tile((p.s + kIdwtT - 1) / kIdwtT, tx, ty);
+    const int n0 = ty * kIdwtT, m0 = tx * kIdwtT;
+    const int qr = n0 / 2 - kIdwtHalo, qc = m0 / 2 - kIdwtHalo;  // quadrant rows/cols of Q[.][0][0]
+    R acc[J][2];
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j][0] = acc[j][1] = 0;
+    // The quadrant tiles of the next basis are loaded into registers while
+    // the current one is computed; all of a thread's loads are issued before
+    // any of them is waited for.
+    constexpr int NL = (kIdwtQ * kIdwtQ + kWavThreads - 1) / kWavThreads;
+    R v[4][NL];
+    auto fetch = [&](int b) {
+        const R* cf = p.coef + (unsigned)b * p.cstride;
+        const R* llb = p.ll ? p.ll + (unsigned)b * p.ll_bs : nullptr;
+        const int tid = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + i * kWavThreads;
+            if (e < kIdwtQ * kIdwtQ) {
+                const int row = (qr + e / kIdwtQ) & hm, col = (qc + e % kIdwtQ) & hm;
+                v[0][i] = llb ? llb[(unsigned)row * p.ld_ll + col] : cf[(unsigned)row * p.ldc + col];
+                v[1][i] = cf[(unsigned)row * p.ldc + half + col];
+                v[2][i] = cf[(unsigned)(half + row) * p.ldc + col];
+                v[3][i] = cf[(unsigned)(half + row) * p.ldc + half + col];
+            }
+        }
+    };
+    fetch(blockIdx.z * p.bpb);
+    for (int bi = 0; bi < p.bpb; ++bi) {
+        const int b = blockIdx.z * p.bpb + bi;
+        {
+            // Q is free: every thread has passed the barrier that ends the
+            // previous basis's column pass
+            const int tid = opaque_tid();
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int e = tid + i * kWavThreads;
+                if (e < kIdwtQ * kIdwtQ) {
+                    const int r = e / kIdwtQ, c = e % kIdwtQ;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) Q[g][r][c] = v[g][i];
+                }
+            }
+        }
+        __syncthreads();  // Q is written; the previous row pass is done with U
+        if (bi + 1 < p.bpb) fetch(b + 1);
+        switch (p.taps[b].L) {
+            case 2: idwt_tile<R, 2>(p, b, Q, U, acc); break;
+            case 4: idwt_tile<R, 4>(p, b, Q, U, acc); break;
+            case 6: idwt_tile<R, 6>(p, b, Q, U, acc); break;
+            case 8: idwt_tile<R, 8>(p, b, Q, U, acc); break;
+            case 10: idwt_tile<R, 10>(p, b, Q, U, acc); break;
+            case 12: idwt_tile<R, 12>(p, b, Q, U, acc); break;
+            case 14: idwt_tile<R, 14>(p, b, Q, U, acc); break;
+            default: idwt_tile<R, 16>(p, b, Q, U, acc); break;
+        }
+        if (p.bpb == 1 || bi == p.bpb - 1) {
+            R* o = p.out + (unsigned)b * p.out_bs * (p.bpb == 1);
+            const int tid = opaque_tid();
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int e = tid + j * kWavThreads;
+                const int n = n0 + e / (kIdwtT / 2), m = m0 + 2 * (e % (kIdwtT / 2));
+                if (n < p.s && m < p.s) {
+                    o[(unsigned)n * p.ld_out + m] = acc[j][0];
+                    o[(unsigned)n * p.ld_out + m + 1] = acc[j][1];
+                }
+                acc[j][0] = acc[j][1] = 0;
+            }
+        }
+    }
 }
 
 }  // namespace msr

@@ -28,6 +28,7 @@ from .generator import (
     tiny,
     channel_set,
     sky_set,
+    coarse_low,
 )
 
 __all__ = [
@@ -46,4 +47,5 @@ __all__ = [
     "tiny",
     "channel_set",
     "sky_set",
+    "coarse_low",
 ]

@@ -295,6 +295,29 @@ def make_problem(cfg: ProblemConfig, with_full: bool = True) -> Problem:
     )
 
 
+def coarse_low(pr: Problem, d: int, seed: int = 0):
+    """The short-baseline split imaged on a grid of N/d pixels over the same
+    field of view: pixels d times larger, the same uv cells (the coarse P/d
+    grid keeps the cells |k| < P/(2d) of each axis, which must hold every
+    short-baseline cell).  The coarse sky holds the flux of each d x d block
+    of fine pixels.  Returns (sky_s, dirty_L_s, psf_L_s)."""
+    n, P = pr.n, pr.P
+    if d < 2 or (d & (d - 1)) or n // d < 2:
+        raise ValueError("d must be a power of two with n / d >= 2")
+    m, Ps = n // d, P // d
+    k = np.fft.fftfreq(P) * P
+    keep = np.abs(k) < Ps / 2
+    w = pr.w_L
+    if np.any(w[~keep, :]) or np.any(w[:, ~keep]):
+        raise ValueError("short baselines reach beyond the coarse grid's band")
+    ks = (k[keep] % Ps).astype(np.int64)
+    w_s = np.zeros((Ps, Ps))
+    w_s[np.ix_(ks, ks)] = w[np.ix_(keep, keep)]
+    sky_s = pr.sky.reshape(m, d, m, d).sum(axis=(1, 3))
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([pr.cfg.seed, 77, d, seed])))
+    return sky_s, _dirty_from_weights(sky_s, w_s, pr.cfg.noise_rel, rng), _psf_from_weights(w_s)
+
+
 def sky_set(base: Problem, count: int, seed: int) -> list:
     """`count` problems observed with `base`'s uv coverage (same PSFs and
     partition) but new skies and noise, drawn from its sky configuration: many
