@@ -198,15 +198,22 @@ def psnr_study(torch, cycles=5, iters=100):
                           pr.sky), "ms": rep1["ms"], "dirty_psnr": psnr(pr.dirty_full, pr.sky)}
             row = {"ell": ell, "delta": delta, "V_L": int(pr.counts["V_L"]), "V_H": int(pr.counts["V_H"]),
                    "V_LH": int(pr.counts["V_LH"])}
-            for tag, ratio in (("", 1e-3), ("_eta2_eq_sigma2", 1.0)):
-                img, _, rep = multistep.two_step(pr, cycles, iters, eta_ratio=ratio)
+            for tag, ratio, coarse in (("", 1e-3, None), ("_eta2_eq_sigma2", 1.0, None),
+                                       ("_eta2_eq_sigma2_low_res_n2", 1.0, 2)):
+                lo = None
+                if coarse:
+                    _, dirty_s, psf_s = synth.coarse_low(pr, coarse)
+                    lo = (coarse, dirty_s, psf_s)
+                img, _, rep = multistep.two_step(pr, cycles, iters, eta_ratio=ratio, coarse=lo)
                 row["psnr" + tag] = psnr(img.cpu().numpy(), pr.sky)
                 row["psnr_model" + tag] = psnr(rep["model"].cpu().numpy(), pr.sky)
                 row["ms" + tag] = rep["step1_ms"] + rep["step2_ms"]
             rows.append(row)
     return {"workload": "paper-shaped 512^2 sky, 64 antennas 4 h at 120 s, natural weighting, "
                         f"{cycles} major cycles x {iters} FISTA iterations per step, positivity on; "
-                        "two-step with eta2 = 1e-3 sigma2_hat (the paper's estimate) and with eta2 = sigma2_hat",
+                        "two-step with eta2 = 1e-3 sigma2_hat (the paper's estimate) and with eta2 = sigma2_hat; "
+                        "_low_res_n2: step 1 on the 256^2 grid (the down-sampled low-resolution image of Sect. 6.1, "
+                        "a quarter of the secondary data product) and step 2 on its up-sampling",
             "single_step": single, "two_step": rows}
 
 
@@ -242,6 +249,27 @@ def dictionary_bench(torch, pr, tensors, iters=50):
            "step1_F": r1.objective, "step2_F": r2.objective, "passes": passes}
     del s
     torch.cuda.empty_cache()
+    return out
+
+
+def upsample_bench(torch, s, n, factors=(2, 4), reps=5):
+    """msr_upsample (the down-sampled low-resolution image, Sect. 6.1) at the
+    workload size: wall time per call (the call synchronises) and its FMA
+    rate against the FP32 vector peak (2 N m^2 + 2 N^2 m flops, m = N / d)."""
+    out = {}
+    dev = torch.device("cuda:0")
+    for d in factors:
+        m = n // d
+        small = torch.randn((m, m), generator=torch.Generator().manual_seed(d), dtype=torch.float32).to(dev)
+        s.upsample(small, d)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            s.upsample(small, d)
+        ms = (time.perf_counter() - t) / reps * 1e3
+        fl = 2.0 * n * m * m + 2.0 * n * n * m
+        out[f"d{d}"] = {"ms": ms, "tflops": fl / (ms * 1e-3) / 1e12,
+                        "alu_frac": fl / (ms * 1e-3) / 1e12 / FP32_VECTOR_TFLOPS}
     return out
 
 
@@ -291,6 +319,9 @@ def main(argv=None):
                          "then exit")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="K",
                     help="profiling aid: set up the workload, autotune, run K iterations of each step and exit")
+    ap.add_argument("--dictionary-kernels", type=int, default=0, metavar="K",
+                    help="profiling aid: set up the workload with the wavelet dictionary, run K iterations of "
+                         "each step and exit")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the solver runs on one GPU; --gpus must be 1 (a multi-GPU split of the "
@@ -315,6 +346,10 @@ def main(argv=None):
     s.set_dirty_psf(2, tensors[2], tensors[3])
     sig2 = s.estimate_sigma2(tensors[2])
     s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)  # so that the low-band filter pass is tuned too
+    if args.dictionary_kernels:
+        rep = dictionary_bench(torch, pr, tensors, iters=args.dictionary_kernels)
+        log("dictionary kernels:", json.dumps(rep))
+        return 0
     tuned = s.autotune(reps=20)
     log("autotune (row variant, column variant, {variant: (col ms, row ms)}):", tuned)
     torch.cuda.synchronize()
@@ -435,6 +470,8 @@ def main(argv=None):
     if not args.no_dict:
         dictionary = dictionary_bench(torch, pr, tensors)
         log("dictionary:", json.dumps(dictionary))
+    upsampling = upsample_bench(torch, s, pr.n)
+    log("upsampling:", json.dumps(upsampling))
 
     psnr = None
     if not args.no_psnr:
@@ -469,6 +506,7 @@ def main(argv=None):
         "batch": batch,
         "partition_study": psnr,
         "wavelet_dictionary": dictionary,
+        "low_res_upsampling": upsampling,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -133,10 +133,12 @@ msr_status msr_set_dirty_psf(msr_ctx* ctx, int step, const void* dirty, const vo
  * eta2 > 0.  Invalidates step 2's theta. */
 msr_status msr_set_filters(msr_ctx* ctx, double ell, double delta, double sigma2, double eta2);
 
-/* theta_s = 2 lambda_max of the step's normal operator by power iteration
- * (Sect. 3.4), started from v0[n] = splitmix64_mix(seed + n) * 2^-64 - 1/2,
- * stopped when |theta_j - theta_{j-1}| <= rtol * theta_j or after max_iter
- * applications.  Writes the estimate to *theta and the number of operator
+/* theta_s = 2 lambda_max of the step's normal operator (Sect. 3.4) by the
+ * Lanczos iteration (theta_j = 2 x the largest eigenvalue of the j x j
+ * tridiagonal projection; no reorthogonalisation), started from
+ * v0[n] = splitmix64_mix(seed + n) * 2^-64 - 1/2, stopped when
+ * |theta_j - theta_{j-1}| <= rtol * theta_j, when the Krylov space is
+ * invariant, or after max_iter applications.  Writes the estimate to *theta and the number of operator
  * applications to *iters (either may be NULL).  The solver then uses
  * margin * estimate as its Lipschitz constant (margin 1.01, see
  * msr_set_lipschitz to override). */

@@ -339,6 +339,38 @@ msr_status fail(msr_ctx* c, msr_status s, const char* fmt, ...) {
     } while (0)
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal a and
+// off-diagonal b (|b| = |a| - 1) by bisection on the Sturm count: the number
+// of eigenvalues below x is the number of negative pivots of T - x I.
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+    const size_t m = a.size();
+    double lo = a[0], hi = a[0];
+    for (size_t i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto below = [&](double x) {
+        size_t cnt = 0;
+        double d = 1.0;
+        for (size_t i = 0; i < m; ++i) {
+            d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0) ++cnt;
+        }
+        return cnt;
+    };
+    const double scale = std::max(std::fabs(lo), std::fabs(hi));
+    for (int it = 0; it < 200 && hi - lo > 4e-16 * scale; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) == m)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
 inline unsigned blocks_for(size_t n, unsigned b = 256) { return (unsigned)((n + b - 1) / b); }
 
 // All typed work of one context, in precision R.
@@ -611,40 +643,64 @@ struct Impl {
 
     msr_status set_low_res(const R* low_res, hipStream_t s) { return fwd_image(2, low_res, (R)1, SL(), c->KL, s); }
 
+    // theta = 2 lambda_max of the step's normal operator by the Lanczos
+    // iteration (Sect. 3.4 defines theta; the Krylov method is this library's
+    // choice): q_1 = v0 / ||v0|| (SplitMix64 start vector), then per step
+    //   w = A q_j (the gradient chain without data), alpha_j = <q_j, w>,
+    //   r = w - alpha_j q_j - beta_{j-1} q_{j-1}, beta_j = ||r||, q_{j+1} = r / beta_j,
+    // theta_j = 2 lambda_max(T_j) of the tridiagonal (alpha, beta) matrix; stop
+    // when |theta_j - theta_{j-1}| <= rtol theta_j, beta_j = 0 or after max_iter
+    // applications.  Vectors are stored unnormalised with their scale (the
+    // image load applies it); FP64 reductions; one host round trip a step.
     msr_status power_iteration(int step, int max_iter, double rtol, double* theta_out, int* iters_out, hipStream_t s) {
         const size_t n = c->sh.img_elems;
-        R* v = tmp(0);
-        R* w = tmp(1);
-        hipLaunchKernelGGL(start_vector<R>, dim3(blocks_for(n)), dim3(256), 0, s, v, (unsigned long long)c->cfg.seed, n);
+        R* buf[3] = {tmp(0), tmp(1), beta(0)};  // beta(0) is free until a solve sets its start
+        int cur = 0, prv = 1, wb = 2;
+        hipLaunchKernelGGL(start_vector<R>, dim3(blocks_for(n)), dim3(256), 0, s, buf[cur],
+                           (unsigned long long)c->cfg.seed, n);
         LAUNCHCHK(c);
         double nv2 = 0.0;
-        TRY(image_reduce(v, nullptr, 1, &nv2, s));
+        TRY(image_reduce(buf[cur], nullptr, 1, &nv2, s));
         if (!(nv2 > 0)) return fail(c, MSR_ERR_NUMERIC, "zero start vector");
-        double scale = 1.0 / std::sqrt(nv2);
+        double s_cur = 1.0 / std::sqrt(nv2), s_prv = 0.0, beta_prev = 0.0;
+        std::vector<double> al, be;
+        const int sblocks = (int)std::min<size_t>(1024, (n + 255) / 256);
         double theta = 0.0, prev = -1.0;
         int j = 0;
         for (j = 1; j <= max_iter; ++j) {
-            TRY(fwd_image(step, v, (R)scale, SA(), KA(step), s));
+            TRY(fwd_image(step, buf[cur], (R)s_cur, SA(), KA(step), s));
             TRY(grad_chain(step, nullptr, false, s));
-            EpiPower<R> ep{v, w, N(), (R)scale};
+            EpiPower<R> ep{buf[cur], buf[wb], N(), (R)s_cur};
             RowArgs<R> a = step == 1 ? row_args(SB(), c->K[0], nullptr, 0, nullptr, 0, true)
                                      : row_args(SB(), c->K[1], SG(), c->KL, nullptr, 0, true);
             opr(step)->row_power(a, ep, s);
             LAUNCHCHK(c);
-            double sums[2];
-            TRY(reduce(row_grid(step), 2, 0, sums, s));
-            // v has unit norm: theta = 2 <v, A v>
-            theta = 2.0 * sums[1];
-            if (sums[0] == 0.0) {
-                theta = 0.0;
-                break;
-            }
-            if (!std::isfinite(theta) || !std::isfinite(sums[0]))
-                return fail(c, MSR_ERR_NUMERIC, "power iteration diverged at %d", j);
-            scale = 1.0 / std::sqrt(sums[0]);
-            std::swap(v, w);
+            TRY(reduce(row_grid(step), 2, 0, nullptr, s));  // scal[0] = ||w||^2, scal[1] = alpha_j
+            hipLaunchKernelGGL(lanczos_step<R>, dim3(sblocks), dim3(256), 0, s, buf[wb], (const R*)buf[cur],
+                               beta_prev > 0 ? (const R*)buf[prv] : nullptr, (const double*)(scal() + 1), (R)s_cur,
+                               (R)(beta_prev * s_prv), n, partials());
+            LAUNCHCHK(c);
+            hipLaunchKernelGGL(finalize_sums, dim3(1), dim3(256), 0, s, partials(), sblocks, 1, scal() + 2);
+            LAUNCHCHK(c);
+            double h[3];
+            HIPCHK(c, hipMemcpyAsync(h, scal(), sizeof h, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2]))
+                return fail(c, MSR_ERR_NUMERIC, "Lanczos iteration diverged at %d", j);
+            al.push_back(h[1]);
+            theta = 2.0 * tridiag_max_eig(al, be);
             if (prev >= 0 && std::fabs(theta - prev) <= rtol * theta) break;
             prev = theta;
+            if (!(h[2] > 0)) break;  // the Krylov space is invariant: theta is exact
+            const double b = std::sqrt(h[2]);
+            be.push_back(b);
+            s_prv = s_cur;
+            s_cur = 1.0 / b;
+            beta_prev = b;
+            const int old = prv;
+            prv = cur;
+            cur = wb;
+            wb = old;
         }
         // With the dictionary the variable is alpha and the normal operator is
         // W^T A W; W W^T = M I makes its largest eigenvalue M times that of A.

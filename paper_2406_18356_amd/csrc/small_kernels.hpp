@@ -20,6 +20,29 @@ __global__ void __launch_bounds__(256) finalize_sums(const double* __restrict__ 
     }
 }
 
+// One Lanczos step, in place: w <- w - alpha s_j u_j - cp u_p (q_j = s_j u_j,
+// cp = beta_{j-1} s_{j-1}; u_p may be null for j = 1), with alpha read from
+// device memory (the <q_j, A q_j> the preceding row pass reduced), and the
+// per-block FP64 partial sums of ||w||^2.
+template <typename R>
+__global__ void __launch_bounds__(256) lanczos_step(R* __restrict__ w, const R* __restrict__ uj,
+                                                    const R* __restrict__ up, const double* __restrict__ alpha,
+                                                    R s_j, R cp, size_t n, double* __restrict__ partials) {
+    __shared__ double red[4];
+    const R a = (R)(alpha[0] * (double)s_j);
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        R r = w[i] - a * uj[i];
+        if (up) r -= cp * up[i];
+        w[i] = r;
+        acc += (double)r * (double)r;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // PSF spectrum extraction: reads the complex forward spectrum (tiled with width
 // TS, P rows), writes Re/P^2 tiled with width T (P rows), the per-column max
 // |Re| and per-block partials (max |Re|, max |Im|).  One block per column.

@@ -164,8 +164,8 @@ __device__ __forceinline__ void dwt_tile(const DwtArgs<R>& p, int b, R (*X)[kDwt
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             const R x = X[r][2 * c + k];
-            lo += t.h[k] * x;
-            hi += t.g[k] * x;
+            lo = fma(t.h[k], x, lo);
+            hi = fma(t.g[k], x, hi);
         }
         Y[r][c] = lo;
         Y[r][kDwtT + c] = hi;
@@ -180,10 +180,10 @@ __device__ __forceinline__ void dwt_tile(const DwtArgs<R>& p, int b, R (*X)[kDwt
         for (int j = 0; j < 4; ++j) {
             const int k = u - 2 * j;
             if (k >= 0 && k < L) {
-                ll[j] += t.h[k] * ylo;
-                lh[j] += t.h[k] * yhi;
-                hl[j] += t.g[k] * ylo;
-                hh[j] += t.g[k] * yhi;
+                ll[j] = fma(t.h[k], ylo, ll[j]);
+                lh[j] = fma(t.h[k], yhi, lh[j]);
+                hl[j] = fma(t.g[k], ylo, hl[j]);
+                hh[j] = fma(t.g[k], yhi, hh[j]);
             }
         }
     }
@@ -285,8 +285,8 @@ __device__ __forceinline__ void idwt_tile(const IdwtArgs<R>& p, int b, R (*Q)[kI
         for (int kk = 0; kk < L / 2; ++kk) {
             const int r = np - kk + kIdwtHalo;
             const R lo = qa[r][c], hi = qb[r][c];
-            ev += t.h[2 * kk] * lo + t.g[2 * kk] * hi;
-            od += t.h[2 * kk + 1] * lo + t.g[2 * kk + 1] * hi;
+            ev = fma(t.g[2 * kk], hi, fma(t.h[2 * kk], lo, ev));
+            od = fma(t.g[2 * kk + 1], hi, fma(t.h[2 * kk + 1], lo, od));
         }
         U[2 * np][cc] = ev;
         U[2 * np + 1][cc] = od;
@@ -302,8 +302,8 @@ __device__ __forceinline__ void idwt_tile(const IdwtArgs<R>& p, int b, R (*Q)[kI
         for (int kk = 0; kk < L / 2; ++kk) {
             const int m = mp - kk + kIdwtHalo;
             const R lo = U[n][m], hi = U[n][kIdwtQ + m];
-            ev += t.h[2 * kk] * lo + t.g[2 * kk] * hi;
-            od += t.h[2 * kk + 1] * lo + t.g[2 * kk + 1] * hi;
+            ev = fma(t.g[2 * kk], hi, fma(t.h[2 * kk], lo, ev));
+            od = fma(t.g[2 * kk + 1], hi, fma(t.h[2 * kk + 1], lo, od));
         }
         acc[j][0] += ev;
         acc[j][1] += od;

@@ -148,7 +148,8 @@ def test_lipschitz(torch_dev, n, pad):
     s2 = objectives.Step2(pr.dirty_H, pr.psf_H, np.zeros((n, n)), pr.ell, pr.delta, 0.8, 0.3)
     for step, prob in ((1, s1), (2, s2)):
         th, it = s.lipschitz(step, max_iter=500, rtol=1e-9)
-        tho, ito, _ = lipschitz.power_iteration(prob.normal, n, seed=9, max_iter=500, rtol=1e-9)
+        tho, ito, _ = lipschitz.lanczos(prob.normal, n, seed=9, max_iter=500, rtol=1e-9)
+        print(f"lipschitz n={n} pad={pad} step={step}: {th:.12g} ({it} its) oracle {tho:.12g} ({ito})", flush=True)
         assert th == pytest.approx(tho, rel=1e-5)
         if pad == 1:  # circular: the paper's closed form (M = 1) is the exact value
             cf = (lipschitz.closed_form_step1(prob.H.h) if step == 1

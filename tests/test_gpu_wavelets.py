@@ -133,7 +133,7 @@ def test_lipschitz_in_coefficients(torch_dev, pad):
     s = _solver(torch_dev, pr, 64, seed=9)
     prob = objectives.Step1(pr.dirty_L, pr.psf_L)
     th, _ = s.lipschitz(1, max_iter=500, rtol=1e-9)
-    tho, _, _ = lipschitz.power_iteration(prob.normal, n, seed=9, max_iter=500, rtol=1e-9)
+    tho, _, _ = lipschitz.lanczos(prob.normal, n, seed=9, max_iter=500, rtol=1e-9)
     assert th == pytest.approx(8 * tho, rel=1e-6)
     if pad == 1:  # Sect. 3.4: 2 M max |h_hat|^2 with M = 8 bases
         assert th == pytest.approx(8 * lipschitz.closed_form_step1(prob.H.h), rel=1e-4)
