@@ -50,7 +50,7 @@ def two_step(dirty_L, psf_L, dirty_H, psf_H, ell, delta, iters1, iters2, positiv
 
 
 def major_cycles(step, dirty, psf, cycles, iters, c=0.05, theta=None, positivity=False, low_res=None,
-                 ell=None, delta=None, sigma2=None, eta2=None, seed=0, margin=1.01):
+                 ell=None, delta=None, sigma2=None, eta2=None, seed=0, margin=1.01, dictionary=False):
     """Several major cycles of one step (Sect. 3.2 for step 1, Sect. 3.3 for
     step 2), the residual image of each cycle formed in the image domain.
 
@@ -60,7 +60,12 @@ def major_cycles(step, dirty, psf, cycles, iters, c=0.05, theta=None, positivity
     stands in for degridding and gridding), with lambda_n = c ||i~_n||_2 2^(n-1)
     and, in step 2, the constraint l_n = l - sum_{j<n} i_j; FISTA starts from
     zero and its result is the cycle's image i_n.  The step's image is
-    i~_{N+1} + sum_n i_n.  Returns (image, sum of the i_n, per-cycle records)."""
+    i~_{N+1} + sum_n i_n.  Returns (image, sum of the i_n, per-cycle records).
+
+    With ``dictionary`` each cycle runs FISTA on the coefficients of the
+    db1-db8 dictionary (Sect. 3, App. A.1; ``theta`` is then the constant of
+    the problem in alpha, by default M = 8 times the image operator's) and
+    i_n = W alpha_K."""
     dirty = np.asarray(dirty, np.float64)
     if step == 1:
         make = lambda y, l: Step1(y, psf)  # noqa: E731
@@ -75,8 +80,19 @@ def major_cycles(step, dirty, psf, cycles, iters, c=0.05, theta=None, positivity
             resid = dirty - make(dirty, low_res).H.apply(msum)
         lam = default_lambda(resid, c, cycle=n)
         prob = make(resid, None if step == 1 else low_res - msum)
-        beta, _, theta = solve_step(prob, lam, iters, theta, positivity=positivity, seed=seed, margin=margin)
-        recs.append({"lambda": lam, "F": prob.objective(beta, lam)[0], "theta": theta})
+        if dictionary:
+            from .wavelets import InDictionary, M, synthesis
+
+            if theta is None:
+                theta = M * margin * power_iteration(prob.normal, prob.n, seed=seed)[0]
+            dic = InDictionary(prob)
+            alpha, _ = fista(dic.grad, np.zeros((M, prob.n, prob.n)), 1.0 / theta, lam, iters)
+            beta = synthesis(alpha)
+            F = dic.objective(alpha, lam)[0]
+        else:
+            beta, _, theta = solve_step(prob, lam, iters, theta, positivity=positivity, seed=seed, margin=margin)
+            F = prob.objective(beta, lam)[0]
+        recs.append({"lambda": lam, "F": F, "theta": theta})
         msum = msum + beta
     final_resid = dirty - make(dirty, low_res).H.apply(msum)
     return final_resid + msum, msum, recs

@@ -94,3 +94,30 @@ def test_major_cycles_pins():
                                           delta=pr.delta, sigma2=1.0, eta2=1e-3)
     b2, _, _ = twostep.solve_step(s2, helpers.default_lambda(pr.dirty_H, 0.05), 25, th2)
     np.testing.assert_allclose(msum2, b2, atol=1e-14)
+
+
+def test_major_cycles_with_dictionary_pins():
+    """In the dictionary: a delta PSF leaves the bookkeeping exact; a single
+    cycle equals one dictionary FISTA run mapped through W; and with lambda
+    = 0 and H = I a cycle's model converges to the dirty image itself (W W^T
+    = 8 I, so W alpha can reach any image; theta = 2 x 8 for W^T W)."""
+    from oracle import fista, wavelets
+
+    pr = synth.make_problem(tiny(16, seed=3))
+    P = pr.P
+    dpsf = np.zeros((P, P))
+    dpsf[P // 2, P // 2] = 1.0
+    img, msum, recs = twostep.major_cycles(1, pr.dirty_L, dpsf, 2, 10, theta=16.0, dictionary=True)
+    np.testing.assert_allclose(img, pr.dirty_L, atol=1e-12)
+    assert np.abs(msum).max() > 0
+    s1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    th = 8 * 2.0 * float(np.max(np.abs(s1.H.h))) ** 2
+    _, msum1, recs1 = twostep.major_cycles(1, pr.dirty_L, pr.psf_L, 1, 15, theta=th, dictionary=True)
+    lam = helpers.default_lambda(pr.dirty_L, 0.05)
+    dic = wavelets.InDictionary(s1)
+    a, _ = fista.fista(dic.grad, np.zeros((8, 16, 16)), 1.0 / th, lam, 15)
+    np.testing.assert_allclose(msum1, wavelets.synthesis(a), atol=1e-14)
+    assert recs1[0]["F"] == pytest.approx(dic.objective(a, lam)[0], rel=1e-14)
+    # lambda -> 0, H = I: FISTA on ||y - W alpha||^2 drives W alpha to y
+    _, m0, _ = twostep.major_cycles(1, pr.dirty_L, dpsf, 1, 400, c=0.0, theta=16.0 * 1.01, dictionary=True)
+    np.testing.assert_allclose(m0, pr.dirty_L, atol=1e-8 * np.abs(pr.dirty_L).max())
