@@ -914,9 +914,8 @@ struct Impl {
                 ll = o;
                 ld_ll = sj;
             }
-            const unsigned tiles = (unsigned)((sj + kIdwtT - 1) / kIdwtT);
-            hipLaunchKernelGGL(idwt_level<R>, dim3(tiles * tiles, 1, kWaveletBases / p.bpb), dim3(kWavThreads), 0, s,
-                               p);
+            const unsigned tiles = (unsigned)(((sj + kIdwtTC - 1) / kIdwtTC) * ((sj + kIdwtTR - 1) / kIdwtTR));
+            hipLaunchKernelGGL(idwt_level<R>, dim3(tiles, 1, kWaveletBases / p.bpb), dim3(kWavThreads), 0, s, p);
             LAUNCHCHK(c);
         }
         return MSR_OK;

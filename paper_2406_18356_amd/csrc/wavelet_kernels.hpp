@@ -17,9 +17,10 @@
 // Each kernel does one whole 2-D level (both axes) for a tile, through LDS:
 //   dwt_level   reads a (2T + 14)^2 input tile once and writes the four T x T
 //               output quadrants of every basis the block handles;
-//   idwt_level  reads four (T' / 2 + 7)^2 quadrant tiles and writes a T' x T'
-//               output tile (level 0: the sum over all 8 bases, so x is
-//               written once).
+//   idwt_level  reads four (R / 2 + 7) x (C / 2 + 7) quadrant tiles and writes
+//               an R x C output tile, C = 4 R wide so that loads and stores
+//               cover whole cache lines (level 0: the sum over all 8 bases,
+//               so x is written once).
 // Level 0 of the analysis shares its input (the image) between the bases, so
 // one block loops over all 8 and reads the tile once; level 0 of the synthesis
 // sums the bases in registers.  The other levels run one basis per block
@@ -45,10 +46,13 @@ struct Taps {
 constexpr int kDwtT = 32;                        // analysis: output quadrant tile side
 constexpr int kDwtIn = 2 * kDwtT + kMaxTaps - 2;  // input tile side (78)
 constexpr int kDwtY = 2 * kDwtT + 4;             // row-pass row length: rows 8 apart fall 32 banks apart
-constexpr int kIdwtT = 64;                       // synthesis: output tile side
-constexpr int kIdwtHalo = kMaxTaps / 2 - 1;      // 7 quadrant rows before the tile
-constexpr int kIdwtQ = kIdwtT / 2 + kIdwtHalo;   // quadrant tile side (39)
+constexpr int kIdwtTR = 32;                      // synthesis: output tile rows
+constexpr int kIdwtTC = 128;                     // synthesis: output tile columns (wide: whole cache lines)
+constexpr int kIdwtHalo = kMaxTaps / 2 - 1;      // 7 quadrant rows / columns before the tile
+constexpr int kIdwtQR = kIdwtTR / 2 + kIdwtHalo;  // quadrant tile rows (23)
+constexpr int kIdwtQC = kIdwtTC / 2 + kIdwtHalo;  // quadrant tile columns (71)
 constexpr int kWavThreads = 256;
+constexpr int kIdwtRowTasks = (kIdwtTR * kIdwtTC / 8) / kWavThreads;  // row-pass tasks (4 output pairs) a thread
 // Waves per SIMD the LDS footprint allows (about 45 KB per block in FP32, 90 KB
 // in FP64, of 160 KB): the register budget is capped to match.
 template <typename R>
@@ -70,16 +74,16 @@ __device__ __forceinline__ int opaque_tid() {
     return t;
 }
 
-// The tile of this block in a g x g tile grid launched as gridDim.x = g^2.
+// The tile of this block in a gx x gy tile grid launched as gridDim.x = gx gy.
 // Consecutive blocks go to different XCDs (8 of them), so when g^2 is a
 // multiple of 8 each XCD is given one contiguous row-major range of tiles:
 // neighbouring tiles, whose input halos overlap, then share that XCD's L2.
-__device__ __forceinline__ void xcd_tile(int g, int& tx, int& ty) {
-    const int n = g * g;
+__device__ __forceinline__ void xcd_tile(int gx, int gy, int& tx, int& ty) {
+    const int n = gx * gy;
     int id = blockIdx.x;
     if ((n & 7) == 0) id = (id & 7) * (n >> 3) + (id >> 3);
-    tx = id % g;
-    ty = id / g;
+    tx = id % gx;
+    ty = id / gx;
 }
 
 template <typename R>
@@ -155,20 +159,30 @@ __device__ __forceinline__ void dwt_tile(const DwtArgs<R>& p, int b, R (*X)[kDwt
             wav_fetch(p.epi, b, half + row, half + col, o1[j][3], o2[j][3]);
         }
     }
-    // rows: Y[r][c] = lo, Y[r][T + c] = hi of input row r, output column c
+    // rows: Y[r][c] = lo, Y[r][T + c] = hi of input row r, output column c.
+    // A task is 4 adjacent output columns c = 4 g + i, which read the window
+    // X[r][8 g + k'], k' < L + 6 (column c takes k' = 2 i + k).
     constexpr int nrows = 2 * kDwtT + L - 2;
-#pragma unroll 2
-    for (int e = tid; e < nrows * kDwtT; e += kWavThreads) {
-        const int r = e / kDwtT, c = e % kDwtT;
-        R lo = 0, hi = 0;
+    for (int e = tid; e < nrows * (kDwtT / 4); e += kWavThreads) {
+        const int r = e / (kDwtT / 4), g = e % (kDwtT / 4);
+        R lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const R x = X[r][2 * c + k];
-            lo = fma(t.h[k], x, lo);
-            hi = fma(t.g[k], x, hi);
+        for (int k2 = 0; k2 < L + 6; ++k2) {
+            const R x = X[r][8 * g + k2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k2 - 2 * i;
+                if (k >= 0 && k < L) {
+                    lo[i] = fma(t.h[k], x, lo[i]);
+                    hi[i] = fma(t.g[k], x, hi[i]);
+                }
+            }
         }
-        Y[r][c] = lo;
-        Y[r][kDwtT + c] = hi;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            Y[r][4 * g + i] = lo[i];
+            Y[r][kDwtT + 4 * g + i] = hi[i];
+        }
     }
     __syncthreads();
     // columns (below): each thread 4 consecutive output rows of one column
@@ -212,7 +226,8 @@ dwt_level(DwtArgs<R> p) {
     __shared__ R Y[kDwtIn][kDwtY];
     const int mask = p.s - 1;
     int tx, ty;
-    xcd_tile(((p.s >> 1) + kDwtT - 1) / kDwtT, tx, ty);
+    const int gd = ((p.s >> 1) + kDwtT - 1) / kDwtT;
+    xcd_tile(gd, gd, tx, ty);
     const int i0 = ty * kDwtT, c0 = tx * kDwtT;
     for (int bi = 0; bi < p.bpb; ++bi) {
         const int b = blockIdx.z * p.bpb + bi;
@@ -266,61 +281,82 @@ struct IdwtArgs {
 };
 
 template <typename R, int L>
-__device__ __forceinline__ void idwt_tile(const IdwtArgs<R>& p, int b, R (*Q)[kIdwtQ][kIdwtQ + 1],
-                                          R (*U)[2 * kIdwtQ + 1], R (*acc)[2]) {
+__device__ __forceinline__ void idwt_tile(const IdwtArgs<R>& p, int b, R (*Q)[kIdwtQR][kIdwtQC + 1],
+                                          R (*U)[2 * kIdwtQC + 1], R (*acc)[2]) {
     const Taps<R>& t = p.taps[b];
     const int tid = opaque_tid();
-    // columns: U[n][c] (c < Q: the row-lo half, c >= Q: the row-hi half) for
-    // the output row pair (2 np, 2 np + 1); both rows read quadrant rows
-    // np - kk + halo, the even one with taps 2 kk, the odd one with 2 kk + 1.
-#pragma unroll 2
-    for (int e = tid; e < (kIdwtT / 2) * (2 * kIdwtQ); e += kWavThreads) {
-        const int np = e / (2 * kIdwtQ), cc = e % (2 * kIdwtQ);
-        const int hiq = cc >= kIdwtQ;
-        const int c = cc - hiq * kIdwtQ;
-        const R (*qa)[kIdwtQ + 1] = Q[hiq];      // lo rows: ll or lh
-        const R (*qb)[kIdwtQ + 1] = Q[2 + hiq];  // hi rows: hl or hh
-        R ev = 0, od = 0;
+    constexpr int H = L / 2;
+    // columns: U[n][c] (c < Q: the row-lo half, c >= Q: the row-hi half).  The
+    // output rows 2 np, 2 np + 1 both read quadrant rows np - kk + halo
+    // (kk < L/2; the even row with taps 2 kk, the odd one with 2 kk + 1); a
+    // task is 4 adjacent pairs np = 4 g + i of one column, which share a
+    // window of L/2 + 3 quadrant rows.
+    for (int e = tid; e < (kIdwtTR / 8) * (2 * kIdwtQC); e += kWavThreads) {
+        const int g = e / (2 * kIdwtQC), cc = e % (2 * kIdwtQC);
+        const int hiq = cc >= kIdwtQC;
+        const int c = cc - hiq * kIdwtQC;
+        const R (*qa)[kIdwtQC + 1] = Q[hiq];      // lo rows: ll or lh
+        const R (*qb)[kIdwtQC + 1] = Q[2 + hiq];  // hi rows: hl or hh
+        const int r0 = 4 * g + kIdwtHalo - (H - 1);
+        R ev[4] = {0, 0, 0, 0}, od[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < L / 2; ++kk) {
-            const int r = np - kk + kIdwtHalo;
-            const R lo = qa[r][c], hi = qb[r][c];
-            ev = fma(t.g[2 * kk], hi, fma(t.h[2 * kk], lo, ev));
-            od = fma(t.g[2 * kk + 1], hi, fma(t.h[2 * kk + 1], lo, od));
+        for (int u = 0; u < H + 3; ++u) {
+            const R lo = qa[r0 + u][c], hi = qb[r0 + u][c];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kk = i + H - 1 - u;
+                if (kk >= 0 && kk < H) {
+                    ev[i] = fma(t.g[2 * kk], hi, fma(t.h[2 * kk], lo, ev[i]));
+                    od[i] = fma(t.g[2 * kk + 1], hi, fma(t.h[2 * kk + 1], lo, od[i]));
+                }
+            }
         }
-        U[2 * np][cc] = ev;
-        U[2 * np + 1][cc] = od;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            U[2 * (4 * g + i)][cc] = ev[i];
+            U[2 * (4 * g + i) + 1][cc] = od[i];
+        }
     }
     __syncthreads();
-    // rows: output pair (2 mp, 2 mp + 1) of row n
+    // rows: output pairs (2 mp, 2 mp + 1) of row n read U[n][mp - kk + halo];
+    // a task is 4 adjacent pairs mp = 4 g + i (acc[4 j + i]).
 #pragma unroll
-    for (int j = 0; j < (kIdwtT * kIdwtT / 2) / kWavThreads; ++j) {
+    for (int j = 0; j < kIdwtRowTasks; ++j) {
         const int e = tid + j * kWavThreads;
-        const int n = e / (kIdwtT / 2), mp = e % (kIdwtT / 2);
-        R ev = 0, od = 0;
+        const int n = e / (kIdwtTC / 8), g = e % (kIdwtTC / 8);
+        const int m0 = 4 * g + kIdwtHalo - (H - 1);
+        R ev[4] = {0, 0, 0, 0}, od[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < L / 2; ++kk) {
-            const int m = mp - kk + kIdwtHalo;
-            const R lo = U[n][m], hi = U[n][kIdwtQ + m];
-            ev = fma(t.g[2 * kk], hi, fma(t.h[2 * kk], lo, ev));
-            od = fma(t.g[2 * kk + 1], hi, fma(t.h[2 * kk + 1], lo, od));
+        for (int u = 0; u < H + 3; ++u) {
+            const R lo = U[n][m0 + u], hi = U[n][kIdwtQC + m0 + u];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kk = i + H - 1 - u;
+                if (kk >= 0 && kk < H) {
+                    ev[i] = fma(t.g[2 * kk], hi, fma(t.h[2 * kk], lo, ev[i]));
+                    od[i] = fma(t.g[2 * kk + 1], hi, fma(t.h[2 * kk + 1], lo, od[i]));
+                }
+            }
         }
-        acc[j][0] += ev;
-        acc[j][1] += od;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            acc[4 * j + i][0] += ev[i];
+            acc[4 * j + i][1] += od[i];
+        }
     }
 }
 
-// Grid: (g^2, 1, kWaveletBases / bpb) with g = ceil(s / T'), 256 threads.
+// Grid: (gx gy, 1, kWaveletBases / bpb) with gx = ceil(s / C), gy = ceil(s / R), 256 threads.
 template <typename R>
 __global__ void __launch_bounds__(kWavThreads) __attribute__((amdgpu_waves_per_eu(kWavWaves<R>)))
 idwt_level(IdwtArgs<R> p) {
-    __shared__ R Q[4][kIdwtQ][kIdwtQ + 1];  // lo-lo, lo rows of row-hi, hi rows of row-lo, hi-hi
-    __shared__ R U[kIdwtT][2 * kIdwtQ + 1];
-    constexpr int J = (kIdwtT * kIdwtT / 2) / kWavThreads;
+    __shared__ R Q[4][kIdwtQR][kIdwtQC + 1];  // lo-lo, lo rows of row-hi, hi rows of row-lo, hi-hi
+    __shared__ R U[kIdwtTR][2 * kIdwtQC + 1];
+    constexpr int J = (kIdwtTR * kIdwtTC / 2) / kWavThreads;
     const int half = p.s >> 1, hm = half - 1;
     int tx, ty;
-    xcd_tile((p.s + kIdwtT - 1) / kIdwtT, tx, ty);
-    const int n0 = ty * kIdwtT, m0 = tx * kIdwtT;
+    xcd_tile((p.s + kIdwtTC - 1) / kIdwtTC, (p.s + kIdwtTR - 1) / kIdwtTR, tx, ty);
+    const int n0 = ty * kIdwtTR, m0 = tx * kIdwtTC;
     const int qr = n0 / 2 - kIdwtHalo, qc = m0 / 2 - kIdwtHalo;  // quadrant rows/cols of Q[.][0][0]
     R acc[J][2];
 #pragma unroll
@@ -328,7 +364,7 @@ idwt_level(IdwtArgs<R> p) {
     // The quadrant tiles of the next basis are loaded into registers while
     // the current one is computed; all of a thread's loads are issued before
     // any of them is waited for.
-    constexpr int NL = (kIdwtQ * kIdwtQ + kWavThreads - 1) / kWavThreads;
+    constexpr int NL = (kIdwtQR * kIdwtQC + kWavThreads - 1) / kWavThreads;
     R v[4][NL];
     auto fetch = [&](int b) {
         const R* cf = p.coef + (unsigned)b * p.cstride;
@@ -337,8 +373,8 @@ idwt_level(IdwtArgs<R> p) {
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             const int e = tid + i * kWavThreads;
-            if (e < kIdwtQ * kIdwtQ) {
-                const int row = (qr + e / kIdwtQ) & hm, col = (qc + e % kIdwtQ) & hm;
+            if (e < kIdwtQR * kIdwtQC) {
+                const int row = (qr + e / kIdwtQC) & hm, col = (qc + e % kIdwtQC) & hm;
                 v[0][i] = llb ? llb[(unsigned)row * p.ld_ll + col] : cf[(unsigned)row * p.ldc + col];
                 v[1][i] = cf[(unsigned)row * p.ldc + half + col];
                 v[2][i] = cf[(unsigned)(half + row) * p.ldc + col];
@@ -356,8 +392,8 @@ idwt_level(IdwtArgs<R> p) {
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
                 const int e = tid + i * kWavThreads;
-                if (e < kIdwtQ * kIdwtQ) {
-                    const int r = e / kIdwtQ, c = e % kIdwtQ;
+                if (e < kIdwtQR * kIdwtQC) {
+                    const int r = e / kIdwtQC, c = e % kIdwtQC;
 #pragma unroll
                     for (int g = 0; g < 4; ++g) Q[g][r][c] = v[g][i];
                 }
@@ -380,8 +416,8 @@ idwt_level(IdwtArgs<R> p) {
             const int tid = opaque_tid();
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                const int e = tid + j * kWavThreads;
-                const int n = n0 + e / (kIdwtT / 2), m = m0 + 2 * (e % (kIdwtT / 2));
+                const int e = tid + (j / 4) * kWavThreads;  // acc[4 jt + i]: task jt, pair 4 g + i
+                const int n = n0 + e / (kIdwtTC / 8), m = m0 + 2 * (4 * (e % (kIdwtTC / 8)) + j % 4);
                 if (n < p.s && m < p.s) {
                     o[(unsigned)n * p.ld_out + m] = acc[j][0];
                     o[(unsigned)n * p.ld_out + m + 1] = acc[j][1];

@@ -198,6 +198,38 @@ def test_dictionary_warm_start(torch_dev):
     assert rel(b, xo) <= TOL64
 
 
+@pytest.mark.parametrize("step", [1, 2])
+def test_dictionary_major_cycles_f64(torch_dev, step):
+    """Major cycles (Sect. 3.2, 3.3) with every cycle solved in the
+    dictionary: the library's image, model and per-cycle objectives against
+    the oracle's, with the same theta."""
+    from oracle import lipschitz, objectives, twostep
+
+    n, cycles, K = 32, 2, 20
+    pr = _problem(n, 2, seed=7)
+    s = _solver(torch_dev, pr, 64)
+    if step == 1:
+        prob = objectives.Step1(pr.dirty_L, pr.psf_L)
+        low = kw = None
+        dirty, psf = pr.dirty_L, pr.psf_L
+    else:
+        low = np.asarray(pr.dirty_L) * 0.5
+        sig2 = float(np.var(pr.dirty_H))
+        s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        prob = objectives.Step2(pr.dirty_H, pr.psf_H, low, pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        kw = dict(ell=pr.ell, delta=pr.delta, sigma2=sig2, eta2=1e-3 * sig2)
+        dirty, psf = pr.dirty_H, pr.psf_H
+    theta = 8 * 1.01 * lipschitz.lanczos(prob.normal, n)[0]
+    s.set_lipschitz(step, theta)
+    img, model, res = s.major_cycles(step, cycles, K, c=0.05, low_res=None if low is None else _t(torch_dev, low, 64))
+    ref_img, ref_model, recs = twostep.major_cycles(step, dirty, psf, cycles, K, c=0.05, theta=theta,
+                                                    low_res=low, dictionary=True, **(kw or {}))
+    assert rel(model.cpu().numpy(), ref_model) <= TOL64
+    assert rel(img.cpu().numpy(), ref_img) <= TOL64
+    for r, rec in zip(res, recs):
+        assert r.objective == pytest.approx(rec["F"], rel=1e-9)
+
+
 def test_dictionary_errors(torch_dev):
     from paper_2406_18356_amd import Solver
     from paper_2406_18356_amd.binding import MsrError
