@@ -175,6 +175,27 @@ msr_status msr_step2_full_res(msr_ctx* ctx, const msr_solve* opt, const void* lo
 msr_status msr_major_cycles(msr_ctx* ctx, int step, int cycles, double c, int iters, const void* low_res,
                             void* model_out, void* image_out, msr_result* res, void* stream);
 
+/* Checkpoint and resume of a solve (the FISTA state of Algorithm 1).
+ * msr_get_state copies the last two iterates beta_K, beta_{K-1} of the latest
+ * solve of step s on this context (N x N images; with the wavelet dictionary
+ * the coefficient arrays, 8 x N x N each) to beta_k / beta_km1 (device,
+ * caller-owned) and writes K to *k (may be NULL).  The iterates stay
+ * available until the next solve, msr_major_cycles, msr_time_pass or
+ * msr_set_workspace on the context, else MSR_ERR_STATE.
+ * msr_set_state loads such a state: the next msr_step1_low_res /
+ * msr_step2_full_res of step s continues from iteration K + 1 (its x0 is
+ * ignored; the momentum goes on with (k-1)/(k+2), alpha_K is formed from the
+ * two iterates) and msr_result.iters counts the iterations of that call, so
+ * that a solve of K1 iterations, get, set and a solve of K2 iterations reach
+ * the iterate of one solve of K1 + K2 iterations (with the same theta: set
+ * it with msr_set_lipschitz on a new context).  A loaded state is dropped by
+ * msr_time_pass and msr_set_workspace and by loading one for the other step
+ * (the steps share the buffers); msr_major_cycles and batched solves refuse
+ * to run while one waits (MSR_ERR_STATE / MSR_ERR_UNSUPPORTED).  Both calls
+ * synchronise the stream. */
+msr_status msr_get_state(msr_ctx* ctx, int step, void* beta_k, void* beta_km1, int* k, void* stream);
+msr_status msr_set_state(msr_ctx* ctx, int step, const void* beta_k, const void* beta_km1, int k, void* stream);
+
 /* Exact objective of step s at x: out[0] = F(x), out[1] = data term(s),
  * out[2] = ||x||_1 (FP64 accumulation).  low_res is required for step 2. */
 msr_status msr_objective(msr_ctx* ctx, int step, double lambda, const void* x, const void* low_res,

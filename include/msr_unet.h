@@ -81,6 +81,18 @@ msr_status msr_unet_set_params(msr_unet* net, const float* params, void* stream)
 /* Copies the float32 master parameters out (device). */
 msr_status msr_unet_get_params(msr_unet* net, float* params_out, void* stream);
 
+/* Training checkpoints.  msr_unet_save writes the configuration, the FP32
+ * master parameters, Adam's two moment arrays and its step count to the file
+ * `path` (8-byte magic "MSRUNET1", int32 in_channels, base_width, levels, 0,
+ * int64 parameter count, int64 step, then the three float32 arrays, host byte
+ * order); msr_unet_load reads one into a network of the same configuration
+ * (MSR_ERR_INVALID for another configuration or a damaged file) and rebuilds
+ * the bfloat16 weights, so that training continues as if uninterrupted.
+ * save needs parameters (msr_unet_set_params or a load); both need the
+ * workspace and synchronise the stream. */
+msr_status msr_unet_save(msr_unet* net, const char* path, void* stream);
+msr_status msr_unet_load(msr_unet* net, const char* path, void* stream);
+
 /* Warm starts x0 (batch x H x W) from the long-baseline dirty images and the
  * low-resolution images. */
 msr_status msr_unet_forward(msr_unet* net, const float* dirty_h, const float* low_res, float* x0_out, int batch,

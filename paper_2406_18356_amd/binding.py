@@ -94,6 +94,8 @@ SYMBOLS = {
     "msr_apply_psf": (_ST, [_P, C.c_int, _P, _P, _P]),
     "msr_dictionary_synthesis": (_ST, [_P, _P, _P, _P]),
     "msr_upsample": (_ST, [_P, C.c_int, _P, _P, _P]),
+    "msr_get_state": (_ST, [_P, C.c_int, _P, _P, C.POINTER(C.c_int), _P]),
+    "msr_set_state": (_ST, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "msr_dictionary_analysis": (_ST, [_P, _P, _P, _P]),
     "msr_get_spectrum": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _P]),
     "msr_estimate_sigma2": (_ST, [_P, _P, C.POINTER(C.c_double), _P]),
@@ -119,6 +121,8 @@ SYMBOLS = {
     "msr_unet_set_workspace": (_ST, [_P, _P, C.c_size_t, C.c_int, C.c_int, C.c_int]),
     "msr_unet_set_params": (_ST, [_P, _P, _P]),
     "msr_unet_get_params": (_ST, [_P, _P, _P]),
+    "msr_unet_save": (_ST, [_P, C.c_char_p, _P]),
+    "msr_unet_load": (_ST, [_P, C.c_char_p, _P]),
     "msr_unet_forward": (_ST, [_P, _P, _P, _P, C.c_int, _P]),
     "msr_unet_loss_grad": (_ST, [_P, _P, _P, _P, C.c_int, C.POINTER(C.c_double), _P, _P]),
     "msr_unet_train_step": (_ST, [_P, _P, _P, _P, C.c_int, C.POINTER(Adam), C.POINTER(C.c_double), _P]),
@@ -296,6 +300,25 @@ class Solver:
         y = self._img()
         self._check(self._lib.msr_apply_psf(self._h, step, self._p(x), self._p(y), _stream(stream)))
         return y
+
+    def _state_shape(self):
+        return (8, self.n, self.n) if getattr(self, "dictionary", 0) else (self.n, self.n)
+
+    def get_state(self, step, stream=None):
+        """(beta_K, beta_{K-1}, K) of the latest solve of `step` (msr_get_state)."""
+        import torch
+
+        bk = torch.empty(self._state_shape(), dtype=self.dtype, device=self.device)
+        bp = torch.empty_like(bk)
+        k = C.c_int()
+        self._check(self._lib.msr_get_state(self._h, int(step), self._p(bk), self._p(bp), C.byref(k),
+                                            _stream(stream)))
+        return bk, bp, k.value
+
+    def set_state(self, step, beta_k, beta_km1, k, stream=None):
+        """Loads a state: the next solve of `step` continues from iteration k + 1."""
+        self._check(self._lib.msr_set_state(self._h, int(step), self._p(beta_k), self._p(beta_km1), int(k),
+                                            _stream(stream)))
 
     def upsample(self, small, factor, stream=None):
         """U small: an (n/factor)^2 low-resolution image up-sampled to n x n
@@ -521,6 +544,14 @@ class UNet:
         out = torch.empty(self.nparam, dtype=torch.float32, device=self.device)
         self._check(self._lib.msr_unet_get_params(self._h, self._p(out), _stream(stream)))
         return out
+
+    def save(self, path, stream=None):
+        """Writes a training checkpoint (msr_unet_save)."""
+        self._check(self._lib.msr_unet_save(self._h, str(path).encode(), _stream(stream)))
+
+    def load(self, path, stream=None):
+        """Reads a training checkpoint of the same configuration (msr_unet_load)."""
+        self._check(self._lib.msr_unet_load(self._h, str(path).encode(), _stream(stream)))
 
     def forward(self, dirty_h, low_res, out=None, stream=None):
         import torch

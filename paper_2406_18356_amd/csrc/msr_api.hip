@@ -301,6 +301,11 @@ struct msr_ctx {
     double theta[2] = {0, 0};
     double ell = 0, delta = 0, sigma2 = 0, eta2 = 0;
     int KL = 0;  // columns with g_L != 0
+    // FISTA state: the step whose last solve's iterates are still in the
+    // workspace (0: none) and its iteration count; a state loaded by
+    // msr_set_state that the next solve of a step continues from (-1: none)
+    int state_step = 0, state_k = 0;
+    int resume_k[2] = {-1, -1};
     int var_row[2] = {0, 0}, var_col[2] = {0, 0};  // kernel variants per step (autotuned)
     int var_filt = -1;  // variant of the step-2 low-band filter pass (-1: that of the step-2 column pass)
     std::string err;
@@ -654,7 +659,7 @@ struct Impl {
     // image load applies it); FP64 reductions; one host round trip a step.
     msr_status power_iteration(int step, int max_iter, double rtol, double* theta_out, int* iters_out, hipStream_t s) {
         const size_t n = c->sh.img_elems;
-        R* buf[3] = {tmp(0), tmp(1), beta(0)};  // beta(0) is free until a solve sets its start
+        R* buf[3] = {tmp(0), tmp(1), mc(3)};  // mc(3) holds nothing between calls (a solve's output slot)
         int cur = 0, prv = 1, wb = 2;
         hipLaunchKernelGGL(start_vector<R>, dim3(blocks_for(n)), dim3(256), 0, s, buf[cur],
                            (unsigned long long)c->cfg.seed, n);
@@ -1000,24 +1005,30 @@ struct Impl {
         return analyze(wx(), e, s);
     }
     msr_status dict_solve(int step, const msr_solve* opt, const R* low_res, const R* x0, R* model_out, R* image_out,
-                          msr_result* res, hipStream_t s) {
-        if (!c->have_theta[step - 1]) {
-            double th = 0.0;
-            TRY(power_iteration(step, 200, 1e-6, &th, nullptr, s));
-            if (!(th > 0)) return fail(c, MSR_ERR_NUMERIC, "zero Lipschitz constant");
-            c->theta[step - 1] = kThetaMargin * th;
-            c->have_theta[step - 1] = true;
-        }
-        const double theta = c->theta[step - 1], mu = 1.0 / theta;
-        const size_t cb = c->sh.rs * cn();
-        if (x0) {  // beta_0 = W^T x0 / M, so that W beta_0 = x0
-            TRY(analyze(x0, store_epi(coef(0), (R)(1.0 / kWaveletBases)), s));
+                          msr_result* res, hipStream_t s, int K0 = 0, bool resuming = false) {
+        double mu = 0.0;
+        if (resuming) {
+            TRY(resume(step, K0, low_res, &mu, s));
         } else {
-            HIPCHK(c, hipMemsetAsync(coef(0), 0, cb, s));
+            if (!c->have_theta[step - 1]) {
+                double th = 0.0;
+                TRY(power_iteration(step, 200, 1e-6, &th, nullptr, s));
+                if (!(th > 0)) return fail(c, MSR_ERR_NUMERIC, "zero Lipschitz constant");
+                c->theta[step - 1] = kThetaMargin * th;
+                c->have_theta[step - 1] = true;
+            }
+            mu = 1.0 / c->theta[step - 1];
+            const size_t cb = c->sh.rs * cn();
+            if (x0) {  // beta_0 = W^T x0 / M, so that W beta_0 = x0
+                TRY(analyze(x0, store_epi(coef(0), (R)(1.0 / kWaveletBases)), s));
+            } else {
+                HIPCHK(c, hipMemsetAsync(coef(0), 0, cb, s));
+            }
+            HIPCHK(c, hipMemcpyAsync(coef(1), coef(0), cb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(cA(), coef(0), cb, hipMemcpyDeviceToDevice, s));
+            if (step == 2) TRY(set_low_res(low_res, s));
         }
-        HIPCHK(c, hipMemcpyAsync(coef(1), coef(0), cb, hipMemcpyDeviceToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(cA(), coef(0), cb, hipMemcpyDeviceToDevice, s));
-        if (step == 2) TRY(set_low_res(low_res, s));
+        const double theta = c->theta[step - 1];
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
@@ -1028,7 +1039,8 @@ struct Impl {
         bool conv = false;
         double ttt = -1.0;
         msr_status st = MSR_OK;
-        for (k = 1; k <= opt->max_iters; ++k) {
+        const int kend = K0 + opt->max_iters;
+        for (k = K0 + 1; k <= kend; ++k) {
             if ((st = dict_iterate(step, k, mu, opt->lambda, s)) != MSR_OK) break;
             if (opt->check_every > 0 && (k % opt->check_every == 0)) {
                 if ((st = dict_objective(step, opt->lambda, coef(k), F, s)) != MSR_OK) break;
@@ -1046,7 +1058,7 @@ struct Impl {
                 }
             }
         }
-        const int done = std::min(k, opt->max_iters);
+        const int done = std::min(k, kend);
         float ms = 0.f;
         if (st == MSR_OK) {
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1055,7 +1067,7 @@ struct Impl {
         }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
-        if (res) res->iters = done;
+        if (res) res->iters = done - K0;
         if (st != MSR_OK) return st;
         TRY(dict_objective(step, opt->lambda, coef(done), F, s));
         if (!std::isfinite(F[0])) return fail(c, MSR_ERR_NUMERIC, "objective is not finite after %d iterations", done);
@@ -1066,8 +1078,10 @@ struct Impl {
             TRY(axpby(image_out, image_out, wx(), (R)1, (R)1, s));     // + W beta
         }
         HIPCHK(c, hipStreamSynchronize(s));
+        c->state_step = step;
+        c->state_k = done;
         if (res) {
-            res->iters = done;
+            res->iters = done - K0;
             res->converged = conv ? 1 : 0;
             res->objective = F[0];
             res->data_term = F[1];
@@ -1079,11 +1093,42 @@ struct Impl {
         return MSR_OK;
     }
 
+    // Continuing from a loaded state (beta_K, beta_{K-1}): theta, the
+    // constraint, and alpha_K = beta_K + t_K (beta_K - beta_{K-1}) formed as
+    // the update epilogue forms it (into the spectrum SA, or the coefficient
+    // array alpha with the dictionary).
+    msr_status resume(int step, int K, const R* low_res, double* mu, hipStream_t s) {
+        if (!c->have_theta[step - 1]) {
+            double th = 0.0;
+            TRY(power_iteration(step, 200, 1e-6, &th, nullptr, s));
+            if (!(th > 0)) return fail(c, MSR_ERR_NUMERIC, "zero Lipschitz constant");
+            c->theta[step - 1] = kThetaMargin * th;
+            c->have_theta[step - 1] = true;
+        }
+        *mu = 1.0 / c->theta[step - 1];
+        if (step == 2) TRY(set_low_res(low_res, s));
+        const size_t n = dict() ? cn() : c->sh.img_elems;
+        R* a = dict() ? cA() : tmp(0);
+        const R* bk = dict() ? coef(K) : beta(K);
+        const R* bp = dict() ? coef(K - 1) : beta(K - 1);
+        hipLaunchKernelGGL(momentum_point<R>, dim3(blocks_for(n)), dim3(256), 0, s, a, bk, bp, (R)momentum(K), n);
+        LAUNCHCHK(c);
+        if (!dict()) TRY(fwd_image(step, a, (R)1, SA(), KA(step), s));
+        return MSR_OK;
+    }
+
     msr_status solve(int step, const msr_solve* opt, const R* low_res, const R* x0, R* model_out, R* image_out,
                      msr_result* res, hipStream_t s) {
-        if (dict()) return dict_solve(step, opt, low_res, x0, model_out, image_out, res, s);
+        const int K0 = std::max(c->resume_k[step - 1], 0);
+        const bool resuming = c->resume_k[step - 1] >= 0;
+        c->resume_k[step - 1] = -1;
+        c->state_step = 0;
+        if (dict()) return dict_solve(step, opt, low_res, x0, model_out, image_out, res, s, K0, resuming);
         double mu = 0.0;
-        TRY(prepare(step, low_res, x0, &mu, s));
+        if (resuming)
+            TRY(resume(step, K0, low_res, &mu, s));
+        else
+            TRY(prepare(step, low_res, x0, &mu, s));
         const double theta = c->theta[step - 1];
 
         hipEvent_t e0, e1;
@@ -1096,7 +1141,8 @@ struct Impl {
         bool conv = false;
         double ttt = -1.0;
         msr_status st = MSR_OK;
-        for (k = 1; k <= opt->max_iters; ++k) {
+        const int kend = K0 + opt->max_iters;
+        for (k = K0 + 1; k <= kend; ++k) {
             if ((st = iterate(step, k, mu, opt->lambda, s)) != MSR_OK) break;
             if (opt->check_every > 0 && (k % opt->check_every == 0)) {
                 if ((st = objective_at(step, opt->lambda, beta(k), F, s)) != MSR_OK) break;
@@ -1114,7 +1160,7 @@ struct Impl {
                 }
             }
         }
-        const int done = std::min(k, opt->max_iters);
+        const int done = std::min(k, kend);
         float ms = 0.f;
         if (st == MSR_OK) {
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1123,12 +1169,14 @@ struct Impl {
         }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
-        if (res) res->iters = done;
+        if (res) res->iters = done - K0;
         if (st != MSR_OK) return st;
         TRY(finish(step, opt->lambda, done, model_out, image_out, F, s));
         HIPCHK(c, hipStreamSynchronize(s));
+        c->state_step = step;
+        c->state_k = done;
         if (res) {
-            res->iters = done;
+            res->iters = done - K0;
             res->converged = conv ? 1 : 0;
             res->objective = F[0];
             res->data_term = F[1];
@@ -1191,6 +1239,9 @@ struct Impl {
     // dirty image is restored before returning.
     msr_status multi_cycle(int step, int cycles, double cl, int iters, const R* low_res, R* model_out, R* image_out,
                            msr_result* res, hipStream_t s) {
+        if (c->resume_k[step - 1] >= 0)
+            return fail(c, MSR_ERR_STATE, "a loaded FISTA state is waiting for a solve of step %d", step);
+        c->state_step = 0;
         const size_t nb = c->sh.rs * c->sh.img_elems;
         R* d = dirty(step);
         R *d0 = mc(0), *msum = mc(1), *lcur = mc(2), *cyc = mc(3);
@@ -1326,6 +1377,8 @@ struct Impl {
         const double es = (double)c->sh.cs, rs = (double)c->sh.rs;
         const double img = (double)Nn * Nn * rs;
         const double fft_p = 5.0 * Pn * std::log2((double)Pn);
+        c->state_step = 0;                          // the passes below overwrite the iterates
+        c->resume_k[0] = c->resume_k[1] = -1;
         WavEpi<R> upd = store_epi(nullptr, (R)1);  // which 5: the fused coefficient update
         upd.mode = 1;
         upd.b1 = coef(0);
@@ -1475,6 +1528,8 @@ msr_status msr_set_workspace(msr_ctx* c, void* dev, size_t bytes) {
     c->have_psf[0] = c->have_psf[1] = false;
     c->have_theta[0] = c->have_theta[1] = false;
     c->have_filters = false;
+    c->state_step = 0;
+    c->resume_k[0] = c->resume_k[1] = -1;
     return with_impl(c, [](auto& im) { return im.set_workspace(); });
 }
 
@@ -1634,6 +1689,44 @@ msr_status msr_autotune(msr_ctx* c, int reps, int* row_variant, int* col_variant
     if (row_variant) *row_variant = c->var_row[0];
     if (col_variant) *col_variant = c->var_col[0];
     return MSR_OK;
+}
+
+msr_status msr_get_state(msr_ctx* c, int step, void* beta_k, void* beta_km1, int* k, void* stream) {
+    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
+    if (!beta_k || !beta_km1) return fail(c, MSR_ERR_INVALID, "null argument");
+    if (c->state_step != step) return fail(c, MSR_ERR_STATE, "no iterates of step %d in the workspace", step);
+    HIPCHK(c, hipSetDevice(c->cfg.device));
+    const int K = c->state_k;
+    return with_impl(c, [&](auto& im) {
+        const bool d = im.dict();
+        const size_t bytes = c->sh.rs * (d ? im.cn() : c->sh.img_elems);
+        HIPCHK(c, hipMemcpyAsync(beta_k, d ? im.coef(K) : im.beta(K), bytes, hipMemcpyDeviceToDevice, S(stream)));
+        HIPCHK(c, hipMemcpyAsync(beta_km1, d ? im.coef(K - 1) : im.beta(K - 1), bytes, hipMemcpyDeviceToDevice,
+                                 S(stream)));
+        HIPCHK(c, hipStreamSynchronize(S(stream)));
+        if (k) *k = K;
+        return MSR_OK;
+    });
+}
+
+msr_status msr_set_state(msr_ctx* c, int step, const void* beta_k, const void* beta_km1, int k, void* stream) {
+    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
+    if (!beta_k || !beta_km1 || k < 0) return fail(c, MSR_ERR_INVALID, "bad arguments");
+    HIPCHK(c, hipSetDevice(c->cfg.device));
+    return with_impl(c, [&](auto& im) {
+        const bool d = im.dict();
+        const size_t bytes = c->sh.rs * (d ? im.cn() : c->sh.img_elems);
+        HIPCHK(c, hipMemcpyAsync(d ? im.coef(k - 1) : im.beta(k - 1), beta_km1, bytes, hipMemcpyDeviceToDevice,
+                                 S(stream)));
+        HIPCHK(c, hipMemcpyAsync(d ? im.coef(k) : im.beta(k), beta_k, bytes, hipMemcpyDeviceToDevice, S(stream)));
+        HIPCHK(c, hipStreamSynchronize(S(stream)));
+        c->state_step = 0;
+        c->resume_k[step - 1] = k;
+        c->resume_k[2 - step] = -1;  // the other step's loaded state shared these buffers
+        return MSR_OK;
+    });
 }
 
 msr_status msr_upsample(msr_ctx* c, int factor, const void* small, void* out, void* stream) {
@@ -1873,6 +1966,11 @@ struct BatchImpl {
         //    every column its group's launches read: nothing unwritten is read,
         //    not even where a zero factor would cancel it)
         std::vector<double> mu(C);
+        for (int c = 0; c < C; ++c) {
+            if (b->ch[c]->resume_k[step - 1] >= 0)
+                return bfail(b, MSR_ERR_UNSUPPORTED, "channel %d: batched solves start from x0, not a loaded state", c);
+            b->ch[c]->state_step = 0;
+        }
         for (const auto& g : b->groups) {
             const Impl<R> gi = group_impl(g);
             for (int c : g.members) {

@@ -118,6 +118,17 @@ __global__ void image_axpby(R* __restrict__ out, const R* __restrict__ x, const 
     out[i] = v;
 }
 
+// alpha_K = beta_K + t (beta_K - beta_{K-1}), with the update epilogue's
+// operation order (a resumed solve continues from exactly this point).
+template <typename R>
+__global__ void momentum_point(R* __restrict__ out, const R* __restrict__ bk, const R* __restrict__ bp, R t,
+                               size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const R b = bk[i];
+    out[i] = fmaR(t, b - bp[i], b);
+}
+
 // Power-iteration start vector: v[n] = splitmix64_mix(seed + n) * 2^-64 - 1/2,
 // taking the top 53 bits for an exact double, then rounding to R.
 __device__ __forceinline__ unsigned long long splitmix64_mix(unsigned long long c) {

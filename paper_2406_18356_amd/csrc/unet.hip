@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -987,6 +988,70 @@ msr_status msr_unet_get_params(msr_unet* u, float* out, void* stream) {
     UTRY(ready(u, 1));
     Run r{u, u->net, u->plan, 1, S(stream)};
     UHIP(u, hipMemcpyAsync(out, r.params(), 4 * u->net.nparam, hipMemcpyDeviceToDevice, S(stream)));
+    return MSR_OK;
+}
+
+// Checkpoint file: 8-byte magic, int32 in_channels, base_width, levels, 0,
+// int64 parameter count, int64 Adam step, then the FP32 master parameters and
+// Adam's first and second moments (host byte order).
+static const char kUnetMagic[8] = {'M', 'S', 'R', 'U', 'N', 'E', 'T', '1'};
+
+msr_status msr_unet_save(msr_unet* u, const char* path, void* stream) {
+    if (!u || !path) return MSR_ERR_INVALID;
+    UTRY(ready(u, 1));
+    UHIP(u, hipSetDevice(u->cfg.device));
+    const size_t n = u->net.nparam;
+    Run r{u, u->net, u->plan, 1, S(stream)};
+    std::vector<float> buf(3 * n);
+    UHIP(u, hipMemcpyAsync(buf.data(), r.params(), 4 * n, hipMemcpyDeviceToHost, r.s));
+    UHIP(u, hipMemcpyAsync(buf.data() + n, r.at<float>(u->plan.m), 4 * n, hipMemcpyDeviceToHost, r.s));
+    UHIP(u, hipMemcpyAsync(buf.data() + 2 * n, r.at<float>(u->plan.v), 4 * n, hipMemcpyDeviceToHost, r.s));
+    UHIP(u, hipStreamSynchronize(r.s));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return ufail(u, MSR_ERR_INVALID, "cannot open %s for writing", path);
+    const int32_t hdr[4] = {u->cfg.in_channels, u->cfg.base_width, u->cfg.levels, 0};
+    const int64_t cnt[2] = {(int64_t)n, (int64_t)u->step};
+    bool ok = std::fwrite(kUnetMagic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+              std::fwrite(cnt, sizeof cnt, 1, f) == 1 && std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return ufail(u, MSR_ERR_INVALID, "writing %s failed", path);
+    return MSR_OK;
+}
+
+msr_status msr_unet_load(msr_unet* u, const char* path, void* stream) {
+    if (!u || !path) return MSR_ERR_INVALID;
+    if (!u->ws) return ufail(u, MSR_ERR_OOM, "no workspace");
+    UHIP(u, hipSetDevice(u->cfg.device));
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return ufail(u, MSR_ERR_INVALID, "cannot open %s", path);
+    char magic[8];
+    int32_t hdr[4];
+    int64_t cnt[2];
+    const size_t n = u->net.nparam;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kUnetMagic, 8) == 0 &&
+              std::fread(hdr, sizeof hdr, 1, f) == 1 && std::fread(cnt, sizeof cnt, 1, f) == 1;
+    if (!ok) {
+        std::fclose(f);
+        return ufail(u, MSR_ERR_INVALID, "%s is not a network checkpoint", path);
+    }
+    if (hdr[0] != u->cfg.in_channels || hdr[1] != u->cfg.base_width || hdr[2] != u->cfg.levels ||
+        cnt[0] != (int64_t)n || cnt[1] < 0) {
+        std::fclose(f);
+        return ufail(u, MSR_ERR_INVALID, "checkpoint of another configuration (%d, %d, %d)", hdr[0], hdr[1], hdr[2]);
+    }
+    std::vector<float> buf(3 * n);
+    ok = std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return ufail(u, MSR_ERR_INVALID, "%s is truncated", path);
+    hipStream_t s = S(stream);
+    Run r{u, u->net, u->plan, u->plan.B, s};
+    UHIP(u, hipMemcpyAsync(r.params(), buf.data(), 4 * n, hipMemcpyHostToDevice, s));
+    UHIP(u, hipMemcpyAsync(r.at<float>(u->plan.m), buf.data() + n, 4 * n, hipMemcpyHostToDevice, s));
+    UHIP(u, hipMemcpyAsync(r.at<float>(u->plan.v), buf.data() + 2 * n, 4 * n, hipMemcpyHostToDevice, s));
+    UTRY(r.refresh_weights());
+    UHIP(u, hipStreamSynchronize(s));  // the host buffer is released on return
+    u->step = cnt[1];
+    u->have_params = true;
     return MSR_OK;
 }
 

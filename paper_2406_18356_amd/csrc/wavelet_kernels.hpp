@@ -114,12 +114,12 @@ __device__ __forceinline__ void wav_emit(const WavEpi<R>& e, int b, int row, int
         e.out[p] = e.scale * w;
         return;
     }
-    const R al = p1 + e.t_prev * (p1 - p2);
+    const R al = fma(e.t_prev, p1 - p2, p1);
     const R z = al - e.two_mu * w;
     const R zero = 0;
     const R beta = copysign(fmax(fabs(z) - e.thr, zero), z);
     e.b2[p] = beta;
-    e.a[p] = beta + e.t_cur * (beta - p1);
+    e.a[p] = fma(e.t_cur, beta - p1, beta);
 }
 
 template <typename R>

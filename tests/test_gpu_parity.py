@@ -496,3 +496,58 @@ def test_two_step_with_major_cycles_f64(torch_dev):
     ref_img, _, _ = twostep.major_cycles(2, pr.dirty_H, pr.psf_H, 2, 30, theta=th2, positivity=True, low_res=ref_iL,
                                          ell=pr.ell, delta=pr.delta, sigma2=sig2, eta2=1e-3 * sig2)
     assert rel(img.cpu().numpy(), ref_img) <= 1e-8
+
+
+# ------------------------------------------------------------ checkpoints
+@pytest.mark.parametrize("prec,dictionary,step", [(64, 0, 1), (64, 0, 2), (32, 0, 1), (64, 1, 2), (32, 1, 1)])
+def test_checkpoint_resume(torch_dev, prec, dictionary, step):
+    """K1 iterations, msr_get_state, msr_set_state on a new context, K2 more:
+    the same iterate and objective as one solve of K1 + K2 iterations (FP64
+    to rounding, FP32 bit for bit: the same kernels in the same order)."""
+    from oracle import lipschitz, objectives
+    from paper_2406_18356_amd import Solver
+
+    n, K1, K2 = 32, 7, 9
+    pr = _problem(n, 2, seed=8)
+    T = lambda a: _t(torch_dev, a, prec)  # noqa: E731
+
+    def make():
+        s = Solver(n, positivity=not dictionary, precision=prec, dictionary=dictionary)
+        s.set_dirty_psf(1, T(pr.dirty_L), T(pr.psf_L))
+        s.set_dirty_psf(2, T(pr.dirty_H), T(pr.psf_H))
+        s.set_filters(pr.ell, pr.delta, 0.8, 0.3)
+        return s
+
+    prob = (objectives.Step1(pr.dirty_L, pr.psf_L) if step == 1 else
+            objectives.Step2(pr.dirty_H, pr.psf_H, np.zeros((n, n)), pr.ell, pr.delta, 0.8, 0.3))
+    theta = (8 if dictionary else 1) * 1.01 * lipschitz.lanczos(prob.normal, n)[0]
+    lam = 0.03 * float(np.linalg.norm(pr.dirty_L if step == 1 else pr.dirty_H))
+    l = T(0.5 * pr.dirty_L)
+    run = (lambda s, K: s.step1(lam, K)) if step == 1 else (lambda s, K: s.step2(lam, l, K))
+    a = make()
+    a.set_lipschitz(step, theta)
+    full, rf = run(a, K1 + K2)
+    b = make()
+    b.set_lipschitz(step, theta)
+    run(b, K1)
+    bk, bp, k = b.get_state(step)
+    assert k == K1
+    c = make()
+    c.set_lipschitz(step, theta)
+    c.set_state(step, bk, bp, k)
+    part, rp = run(c, K2)
+    assert rp.iters == K2
+    f, p_ = full.cpu().numpy(), part.cpu().numpy()
+    if prec == 32:
+        assert np.array_equal(f, p_)
+    else:
+        assert rel(p_, f) <= 1e-13
+    assert rp.objective == pytest.approx(rf.objective, rel=1e-12 if prec == 64 else 1e-7)
+    # the state is gone after another solve; a loaded state blocks major cycles
+    run(c, 1)
+    c.set_state(step, bk, bp, k)
+    from paper_2406_18356_amd.binding import MsrError
+    with pytest.raises(MsrError):
+        c.major_cycles(step, 1, 2, low_res=None if step == 1 else l)
+    with pytest.raises(MsrError):
+        a.get_state(3 - step)

@@ -141,3 +141,33 @@ def test_smaller_batch_and_errors(torch_dev):
     bare = UNet(1, 32)
     with pytest.raises(MsrError):
         bare.forward(_t(torch_dev, dh[:1]), _t(torch_dev, low[:1]))  # no parameters yet
+
+
+def test_checkpoint_save_load_resumes_training(torch_dev, tmp_path):
+    """Train 3 steps, save, load into a new network, train 2 more on both:
+    the parameters agree bit for bit (the same kernels on the same state)."""
+    from paper_2406_18356_amd import UNet
+    from paper_2406_18356_amd.binding import MsrError
+
+    n, B = 32, 2
+    a, p = _net(torch_dev, B, n, seed=6)
+    dh, low, tgt = [_t(torch_dev, x) for x in _batch(n, B, seed=8)]
+    for _ in range(3):
+        a.train_step(dh, low, tgt, lr=1e-3)
+    path = tmp_path / "net.ckpt"
+    a.save(path)
+    b = UNet(B, n)
+    b.load(path)
+    assert np.array_equal(a.get_params().cpu().numpy(), b.get_params().cpu().numpy())
+    for _ in range(2):
+        la = a.train_step(dh, low, tgt, lr=1e-3)
+        lb = b.train_step(dh, low, tgt, lr=1e-3)
+        assert la == lb
+    assert np.array_equal(a.get_params().cpu().numpy(), b.get_params().cpu().numpy())
+    other = UNet(B, n, base_width=16)
+    with pytest.raises(MsrError):
+        other.load(path)
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"not a checkpoint at all")
+    with pytest.raises(MsrError):
+        b.load(bad)
