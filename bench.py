@@ -461,6 +461,24 @@ def main(argv=None):
             del net
         log("time to tolerance:", json.dumps(ttt))
 
+    # Per-PSF setup (PSF spectra and theta of both steps), which the time to
+    # tolerance excludes, and the sanity ratio lambda_s / ||grad f_s(0)||_inf
+    # (at or above 1 the minimiser is x = 0).
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.set_dirty_psf(1, tensors[0], tensors[1])
+    s.set_dirty_psf(2, tensors[2], tensors[3])
+    s.set_filters(pr.ell, pr.delta, s.estimate_sigma2(tensors[2]), 1e-3 * s.estimate_sigma2(tensors[2]))
+    th1, it1 = s.lipschitz(1)
+    th2, it2 = s.lipschitz(2)
+    torch.cuda.synchronize()
+    setup = {"ms": (time.perf_counter() - t) * 1e3, "lanczos_applications": [it1, it2], "theta": [th1, th2]}
+    zero = torch.zeros_like(tensors[0])
+    g1 = float(s.gradient(1, zero).abs().max())
+    g2 = float(s.gradient(2, zero, iL).abs().max())
+    setup["lambda_over_grad0_inf"] = [s.default_lambda(1, 1, 0.05) / g1, lam2 / g2]
+    log("setup:", json.dumps(setup))
+
     batch = None
     if not args.no_batch:
         batch = batch_bench(torch, dev, args.batch_channels, iters)
@@ -502,6 +520,7 @@ def main(argv=None):
         "step2_loop_iters_per_s": r2.iters / (r2.elapsed_ms * 1e-3),
         "autotune": {"row_variant": tuned[0], "col_variant": tuned[1]},
         "time_to_tol": ttt,
+        "setup": setup,
         "learned_warm_start": unet_report,
         "batch": batch,
         "partition_study": psnr,
