@@ -114,6 +114,40 @@ def batch_bench(torch, dev, count, iters, seed=4):
     }
 
 
+def batch_replicas(torch, pr, tensors, iL, count, iters=20):
+    """`count` copies of the workload's problem as the channels of one batch
+    (the kernels' work does not depend on the data, so this measures the
+    batched path at the full size; the channels are identical, not the
+    frequency-scaled coverages of a real observation): both steps, `iters`
+    iterations each, after a first call that captures the graph."""
+    from paper_2406_18356_amd import Batch
+
+    dL, pL, dH, pH = tensors
+    b = Batch([pr.n] * count, positivity=True)
+    for ch in b.channels:
+        ch.set_dirty_psf(1, dL, pL)
+        ch.set_dirty_psf(2, dH, pH)
+        sig2 = ch.estimate_sigma2(dH)
+        ch.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+    b.autotune(reps=5)
+    ch0 = b.channels[0]
+    lam = {1: [ch0.default_lambda(1, 1, 0.05)] * count, 2: [ch0.default_lambda(2, 1, 0.05)] * count}
+    out = {"channels": count, "image": pr.n, "iters": iters,
+           "workload": f"{count} identical channels of the {pr.n}x{pr.n} problem in one batch, positivity on"}
+    for step in (1, 2):
+        low = None if step == 1 else [iL] * count
+        b.solve(step, lam[step], iters, low_res=low)  # theta and graph capture
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, res = b.solve(step, lam[step], iters, low_res=low)
+        wall = time.perf_counter() - t
+        loop = res[0].elapsed_ms * 1e-3
+        out[f"step{step}"] = {"channel_iters_per_s": count * iters / loop, "loop_ms": loop * 1e3, "wall_s": wall}
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def train_warm_start(torch, n=256, ntrain=256, epochs=20, iters2=3000, neval=4, seed=11):
     """Trains the learned warm start on two-step results of skies observed like
     the benchmark workload (same array and track, sky density and cut) at
@@ -311,6 +345,8 @@ def main(argv=None):
     ap.add_argument("--no-psnr", action="store_true")
     ap.add_argument("--no-dict", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=8)
+    ap.add_argument("--batch-replicas", type=int, default=0, metavar="C",
+                    help="also batch C copies of the workload's problem (about 1.5 GiB of HBM each at 4096^2)")
     ap.add_argument("--ttt-ref-iters", type=int, default=20000)
     ap.add_argument("--profile-pass", type=int, nargs=3, action="append", default=None,
                     metavar=("STEP", "WHICH", "REPS"),
@@ -491,6 +527,11 @@ def main(argv=None):
     upsampling = upsample_bench(torch, s, pr.n)
     log("upsampling:", json.dumps(upsampling))
 
+    replicas = None
+    if args.batch_replicas:
+        replicas = batch_replicas(torch, pr, tensors, iL, args.batch_replicas)
+        log("batch replicas:", json.dumps(replicas))
+
     psnr = None
     if not args.no_psnr:
         psnr = psnr_study(torch)
@@ -523,6 +564,7 @@ def main(argv=None):
         "setup": setup,
         "learned_warm_start": unet_report,
         "batch": batch,
+        "batch_replicas": replicas,
         "partition_study": psnr,
         "wavelet_dictionary": dictionary,
         "low_res_upsampling": upsampling,
