@@ -551,3 +551,58 @@ def test_checkpoint_resume(torch_dev, prec, dictionary, step):
         c.major_cycles(step, 1, 2, low_res=None if step == 1 else l)
     with pytest.raises(MsrError):
         a.get_state(3 - step)
+
+
+def test_maximum_size_8192_sampled(torch_dev):
+    """The largest FP32 image (8192^2 on a 16384^2 grid, every spectral column
+    kept): a symmetric PSF of a few delta taps makes H x and one FISTA step
+    exact short sums, checked at sampled pixels (corners included, where the
+    zero padding cuts the taps)."""
+    from paper_2406_18356_amd import Solver
+
+    torch, dev = torch_dev
+    n, P = 8192, 16384
+    c = P // 2
+    taps = {(0, 0): 1.0, (3, 0): 0.3, (-3, 0): 0.3, (0, 5): -0.2, (0, -5): -0.2, (7, 7): 0.1, (-7, -7): 0.1}
+    psf = torch.zeros((P, P), dtype=torch.float32)
+    for (a, b), v in taps.items():
+        psf[c + a, c + b] = v
+    rng = np.random.default_rng(12)
+    pts_x = np.concatenate([rng.integers(0, n, (200, 2)), [[0, 0], [1, 2], [n - 1, n - 1], [n - 2, n - 3]]])
+    xv = np.abs(rng.normal(size=len(pts_x))).astype(np.float32) + 0.5
+    x = torch.zeros((n, n), dtype=torch.float32)
+    x[pts_x[:, 0], pts_x[:, 1]] = torch.from_numpy(xv)
+    yv = rng.normal(size=len(pts_x)).astype(np.float32) * 0.1
+    y = torch.zeros((n, n), dtype=torch.float32)
+    y[pts_x[:, 0], pts_x[:, 1]] = torch.from_numpy(yv)
+    X = {tuple(p): float(v) for p, v in zip(pts_x, xv)}
+    Y = {tuple(p): float(v) for p, v in zip(pts_x, yv)}
+
+    def H(p):  # (H x)[p] = sum_t psf_t x[p - t]
+        return sum(v * X.get((p[0] - a, p[1] - b), 0.0) for (a, b), v in taps.items())
+
+    def Ht_r(q):  # (H^T (H x - y))[q] = sum_t psf_t r[q + t], r on the image only
+        tot = 0.0
+        for (a, b), v in taps.items():
+            p = (q[0] + a, q[1] + b)
+            if 0 <= p[0] < n and 0 <= p[1] < n:
+                tot += v * (H(p) - Y.get(p, 0.0))
+        return tot
+
+    s = Solver(n, positivity=True, precision=32)
+    s.set_dirty_psf(1, y.to(dev), psf.to(dev))
+    del psf
+    hx = s.apply_psf(1, x.to(dev)).cpu().numpy()
+    check = [tuple(p) for p in pts_x[:60]] + [(0, 0), (n - 1, n - 1), (3, 0), (n - 1, n - 6), (10, 12)]
+    peak = float(np.max(np.abs(hx)))
+    for p in check:
+        assert abs(hx[p] - H(p)) <= OP_TOL * peak, (p, hx[p], H(p))
+    theta = 2.0 * (1.0 + 0.6 + 0.4 + 0.2) ** 2  # >= 2 max |h_hat|^2
+    lam = 0.2
+    s.set_lipschitz(1, theta)
+    b, _ = s.step1(lam, 1, x0=x.to(dev))
+    b = b.cpu().numpy()
+    mu = 1.0 / theta
+    for q in check + [(pts_x[k][0] + 3, pts_x[k][1]) for k in range(20) if pts_x[k][0] + 3 < n]:
+        want = max(X.get(q, 0.0) - mu * 2.0 * Ht_r(q) - mu * lam, 0.0)
+        assert abs(b[q] - want) <= 2e-6 * max(xv.max(), 1.0), (q, b[q], want)
