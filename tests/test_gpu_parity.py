@@ -372,6 +372,18 @@ def test_errors(torch_dev):
     with pytest.raises(MsrError) as e:
         s.step1(0.1, 10, check_every=5)
     assert e.value.status == binding.ERR_NUMERIC
+    assert "iteration 5" in str(e.value)  # the first objective check names where
+    # a workspace smaller than msr_workspace_bytes is refused
+    import ctypes
+
+    lib = binding.lib()
+    h = ctypes.c_void_p()
+    cfg = binding._cfg(16)
+    assert lib.msr_init(ctypes.byref(cfg), ctypes.byref(h)) == binding.OK
+    small = _t(torch_dev, np.zeros(64, np.float32))
+    assert lib.msr_set_workspace(h, ctypes.c_void_p(small.data_ptr()), 256) == binding.ERR_OOM
+    assert b"workspace needs" in lib.msr_last_error(h)
+    lib.msr_destroy(h)
 
 
 # ----------------------------------------------------------------- full size
