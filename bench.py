@@ -488,10 +488,11 @@ def main(argv=None):
         # The best a network trained on 3000-iteration targets can do: its own
         # target as the start (the time to produce it is not counted).
         target, _ = s.step2(lam2, iL, 3000)
-        for name, x0 in (("cold", None), ("low_res_warm", iL), ("step1_model_warm", b1),
-                         ("target_3000_warm", target)):
-            _, rc = s.step2(lam2, iL, args.ttt_ref_iters, x0=x0, check_every=10, tol=1e-6, f_ref=fstar)
-            ttt[name] = {"ms": rc.time_to_tol_ms, "iters": rc.iters, "converged": bool(rc.converged)}
+        from paper_2406_18356_amd import warmstart as ws
+
+        for name, x0, mk in (("cold", None, 0), ("low_res_warm", iL, 0), ("step1_model_warm", b1, 0),
+                             ("target_3000_warm", target, 0), ("target_3000_warm_momentum_3000", target, 3000)):
+            ttt[name] = ws.time_to_tol(s, lam2, iL, fstar, x0=x0, max_iters=args.ttt_ref_iters, momentum_k=mk)
         if unet_params is not None:
             from paper_2406_18356_amd import UNet, warmstart as ws
 
@@ -501,6 +502,8 @@ def main(argv=None):
             ttt["unet_warm"] = ws.time_to_tol(s, lam2, iL, fstar, x0=x0[0].contiguous(), warm_ms=fms,
                                               max_iters=args.ttt_ref_iters)
             ttt["unet_warm"]["trained_at"] = unet_report["train"]["image"]
+            ttt["unet_warm_momentum_3000"] = ws.time_to_tol(s, lam2, iL, fstar, x0=x0[0].contiguous(), warm_ms=fms,
+                                                            max_iters=args.ttt_ref_iters, momentum_k=3000)
             del net
         log("time to tolerance:", json.dumps(ttt))
 

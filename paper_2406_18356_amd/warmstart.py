@@ -77,9 +77,15 @@ def train(net, dh, il, target, epochs=20, batch=8, lr=1e-3, seed=0, log=None):
     return losses
 
 
-def time_to_tol(solver, lam, low_res, f_ref, x0=None, tol=1e-6, max_iters=20000, check_every=10, warm_ms=0.0):
+def time_to_tol(solver, lam, low_res, f_ref, x0=None, tol=1e-6, max_iters=20000, check_every=10, warm_ms=0.0,
+                momentum_k=0):
     """Step-2 time (ms, HIP events; plus `warm_ms` spent producing x0) and
-    iterations to reach (F - f_ref) / |f_ref| <= tol."""
+    iterations to reach (F - f_ref) / |f_ref| <= tol.  With momentum_k > 0
+    the run starts at iteration momentum_k + 1 from beta = x0 with zero
+    velocity (msr_set_state), so that the momentum weight starts near 1
+    instead of at 0 (Algorithm 1 itself restarts at k = 1)."""
+    if momentum_k > 0:
+        solver.set_state(2, x0, x0, momentum_k)
     _, r = solver.step2(lam, low_res, max_iters, x0=x0, check_every=check_every, tol=tol, f_ref=f_ref)
     ms = (r.time_to_tol_ms + warm_ms) if r.converged else -1.0
     return {"ms": ms, "iters": int(r.iters), "converged": bool(r.converged), "warm_start_ms": warm_ms}
