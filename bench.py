@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "FISTA iters/s & time-to-1e-6 rel objective at 4096²; warm-start vs cold"
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector peak
+BF16_MFMA_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
 
 
 def traffic_file(kernel, workload):
@@ -504,6 +505,25 @@ def main(argv=None):
             ttt["unet_warm"]["trained_at"] = unet_report["train"]["image"]
             ttt["unet_warm_momentum_3000"] = ws.time_to_tol(s, lam2, iL, fstar, x0=x0[0].contiguous(), warm_ms=fms,
                                                             max_iters=args.ttt_ref_iters, momentum_k=3000)
+            # the network's forward pass against the dense bf16 MFMA peak: the
+            # MFMA work of every 3x3 convolution (K padded to 32) at its level
+            from paper_2406_18356_amd import unet_layers
+
+            lay = unet_layers(32, 4)
+            lvl = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0]
+            hw = pr.n * pr.n
+            fl = sum(2.0 * (hw >> (2 * j)) * co * kpad for (ci, co, kpad), j in zip(lay, lvl))
+            dh1, il1 = tensors[2][None].contiguous(), iL[None].contiguous()
+            net.forward(dh1, il1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                net.forward(dh1, il1)
+            e1.record()
+            e1.synchronize()
+            fms5 = e0.elapsed_time(e1) / 5
+            ttt["unet_forward"] = {"image": pr.n, "ms": fms5, "mfma_tflops": fl / (fms5 * 1e-3) / 1e12,
+                                   "mfma_frac": fl / (fms5 * 1e-3) / 1e12 / BF16_MFMA_TFLOPS}
             del net
         log("time to tolerance:", json.dumps(ttt))
 
