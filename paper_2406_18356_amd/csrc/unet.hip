@@ -106,8 +106,10 @@ struct ConvOut {
 
 template <typename T, bool BWD>
 __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
-    __shared__ __attribute__((aligned(16))) bf16 As[CBM * CLD];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[CBN * CLD];
+    // two LDS buffers: step i computes from one while step i + 1's operands,
+    // loaded into registers before step i's MFMAs, go into the other
+    __shared__ __attribute__((aligned(16))) bf16 As[2][CBM * CLD];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][CBN * CLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int P = o.B * o.H * o.W;
     const int p0 = blockIdx.x * CBM, n0 = blockIdx.y * CBN;
@@ -127,30 +129,46 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
         px[u] = r - py[u] * o.W;
     }
     const int bco = n0 + tid / 4, bg = (tid % 4) * 8;
-
-    f32x16 acc0 = {}, acc1 = {};
-    for (int k0 = 0; k0 < o.kpad; k0 += CBK) {
+    bf16x8 ra[2], rb;
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int q = tid + u * 256;
-            const bf16x8 a = pv[u] ? im2col8(in, o.H, o.W, pb[u], py[u], px[u], k0 + (q % 4) * 8) : zero8();
-            *reinterpret_cast<bf16x8*>(&As[(q / 4) * CLD + (q % 4) * 8]) = a;
+            ra[u] = pv[u] ? im2col8(in, o.H, o.W, pb[u], py[u], px[u], k0 + (q % 4) * 8) : zero8();
         }
-        {
-            const bf16x8 bv = bco < o.cout ? load8(o.w + (size_t)bco * o.kpad + k0 + bg) : zero8();
-            *reinterpret_cast<bf16x8*>(&Bs[(tid / 4) * CLD + bg]) = bv;
+        rb = bco < o.cout ? load8(o.w + (size_t)bco * o.kpad + k0 + bg) : zero8();
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int q = tid + u * 256;
+            *reinterpret_cast<bf16x8*>(&As[buf][(q / 4) * CLD + (q % 4) * 8]) = ra[u];
         }
-        __syncthreads();
+        *reinterpret_cast<bf16x8*>(&Bs[buf][(tid / 4) * CLD + bg]) = rb;
+    };
+
+    f32x16 acc0 = {}, acc1 = {};
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < o.kpad; k0 += CBK) {
+        const bool more = k0 + CBK < o.kpad;
+        if (more) fetch(k0 + CBK);  // in flight during this step's MFMAs
 #pragma unroll
         for (int kk = 0; kk < CBK; kk += 16) {
             const int ko = kk + (lane >> 5) * 8;
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[(wave * 32 + (lane & 31)) * CLD + ko]);
-            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[(lane & 31) * CLD + ko]);
-            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[(32 + (lane & 31)) * CLD + ko]);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&As[cur][(wave * 32 + (lane & 31)) * CLD + ko]);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[cur][(lane & 31) * CLD + ko]);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[cur][(32 + (lane & 31)) * CLD + ko]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
         }
+        // the other buffer was last read in the previous step, which every
+        // thread finished before the barrier that ended it
+        if (more) stage(cur ^ 1);
         __syncthreads();
+        cur ^= 1;
     }
 
 #pragma unroll
@@ -326,19 +344,39 @@ __global__ void up_back_kernel(const float* __restrict__ dup, const bf16* __rest
     }
 }
 
-// Per image: s = max |l| (1 when l = 0).
-__global__ void scale_kernel(const float* __restrict__ low, int HW, float* __restrict__ scale) {
-    __shared__ float red[256];
-    const float* l = low + (size_t)blockIdx.x * HW;
-    float m = 0.0f;
-    for (int i = threadIdx.x; i < HW; i += 256) m = fmaxf(m, fabsf(l[i]));
+// Input normalisation s = max |l| per image (1 when l = 0), in two passes:
+// scale_partial_kernel's grid (nb, B) gives each image nb blocks that stride
+// over its pixels and leave one maximum each in part[b][nb]; scale_kernel then
+// takes the maximum of those nb values per image. A max is order-free, so the
+// result does not depend on the split.
+constexpr int kScaleBlocks = 256;
+
+__device__ __forceinline__ float block_max256(float m, float* red) {
     red[threadIdx.x] = m;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) scale[blockIdx.x] = red[0] > 0.0f ? red[0] : 1.0f;
+    return red[0];
+}
+
+__global__ void scale_partial_kernel(const float* __restrict__ low, int HW, int nb, float* __restrict__ part) {
+    __shared__ float red[256];
+    const float* l = low + (size_t)blockIdx.y * HW;
+    float m = 0.0f;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < HW; i += nb * 256) m = fmaxf(m, fabsf(l[i]));
+    m = block_max256(m, red);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * nb + blockIdx.x] = m;
+}
+
+__global__ void scale_kernel(const float* __restrict__ part, int nb, float* __restrict__ scale) {
+    __shared__ float red[256];
+    const float* q = part + (size_t)blockIdx.x * nb;
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < nb; i += 256) m = fmaxf(m, q[i]);
+    m = block_max256(m, red);
+    if (threadIdx.x == 0) scale[blockIdx.x] = m > 0.0f ? m : 1.0f;
 }
 
 // NHWC input with 8 channels: (i_H / s, l / s, 0, ...).
@@ -623,6 +661,7 @@ bool make_plan(const Net& n, int B, int H, int W, Plan& p) {
         pf = std::max(pf, (size_t)((P + 1023) / 1024) * l.cout);  // bias partials
     }
     pf = std::max(pf, (size_t)((npix(p, 0) + 1023) / 1024) * (n.width + 1));  // head partials
+    pf = std::max(pf, (size_t)B * kScaleBlocks);                              // input-scale partials
     p.part_floats = pf;
     p.part = take(4 * pf);
     p.dpart = take(8 * 1024);
@@ -899,7 +938,10 @@ struct Run {
 
     msr_status prepare_input(const float* dh, const float* low) {
         const int HW = p.H * p.W;
-        hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(256), 0, s, low, HW, at<float>(p.scale));
+        const int nb = std::min(kScaleBlocks, (HW + 255) / 256);
+        hipLaunchKernelGGL(scale_partial_kernel, dim3(nb, B), dim3(256), 0, s, low, HW, nb, at<float>(p.part));
+        ULAUNCH(u);
+        hipLaunchKernelGGL(scale_kernel, dim3(B), dim3(256), 0, s, at<float>(p.part), nb, at<float>(p.scale));
         ULAUNCH(u);
         hipLaunchKernelGGL(pack_kernel, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, dh, low, at<float>(p.scale), B,
                            HW, at<bf16>(p.in0));
