@@ -118,12 +118,25 @@ constexpr int waves_per_eu() {
 #endif
 
 // Row kernels exchange FFT stages through two LDS arrays (one barrier per
-// stage) when both fit in a CU's LDS next to nothing else (MSR_ROW_PINGPONG = 0
-// turns this off).
+// stage) when the doubled footprint still lets a CU hold blocks for 16 waves
+// (4 per SIMD), or when the launch has no more blocks than the chip has CUs
+// (256), so that no CU would hold a second one anyway.  Otherwise they use one
+// array and two barriers per stage, and the extra resident blocks hide the
+// global loads and stores of their neighbours (MSR_ROW_PINGPONG = 0 turns
+// ping-pong off everywhere).
 #ifndef MSR_ROW_PINGPONG
 #define MSR_ROW_PINGPONG 1
 #endif
+#ifndef MSR_ROW_REFETCH
+#define MSR_ROW_REFETCH 1
+#endif
 constexpr size_t kLdsBytes = 160 * 1024;
+constexpr bool row_pingpong(size_t line_bytes, int threads, int grid_blocks) {
+    const int waves = threads >= 64 ? threads / 64 : 1;
+    const int resident = (16 + waves - 1) / waves;
+    return MSR_ROW_PINGPONG && 2 * line_bytes <= kLdsBytes &&
+           (grid_blocks <= 256 || (size_t)resident * 2 * line_bytes <= kLdsBytes);
+}
 
 template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
 __global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R, EMAX>::TPF))
@@ -135,7 +148,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     constexpr int ZLEN = padded_len(PT);
     constexpr int NT = PAIRS * TPF;
     constexpr int NQ = Epi::NQ;
-    constexpr bool PP = MSR_ROW_PINGPONG && 2 * PAIRS * ZLEN * sizeof(C) <= kLdsBytes;
+    constexpr bool PP = row_pingpong(PAIRS * ZLEN * sizeof(C), NT, L / (2 * PAIRS));
     __shared__ C lds[(PP ? 2 : 1) * PAIRS * ZLEN];
     __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
 
@@ -242,19 +255,33 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     for (int m = 0; m < E; ++m) z[m] = epi.apply(ra, t + m * TPF, z[m], acc);
 
     if constexpr (FWD_OUT) {
+        // The forward transform reads the same twiddles, and computes the same
+        // LDS and global addresses, as the inverse one.  Through opaque copies
+        // of the table pointers and thread indices it loads and computes them
+        // again instead of keeping the inverse's values live in registers
+        // across the epilogue (MSR_ROW_REFETCH = 0: keep them).
+        const C* tw_f = a.tw;
+        const C* tws_f = a.tws;
+        int tf = t, tidf = tid;
+#if MSR_ROW_REFETCH
+        if constexpr (INV_IN) {
+            asm volatile("" : "+s"(tw_f), "+s"(tws_f));
+            asm volatile("" : "+v"(tf), "+v"(tidf));
+        }
+#endif
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             v[0][m] = z[m];
-            if constexpr (PADDED) v[1][m] = cmul(z[m], a.tw[t + m * TPF]);
+            if constexpr (PADDED) v[1][m] = cmul(z[m], tw_f[tf + m * TPF]);
         }
         __syncthreads();
-        if constexpr (PP) fft_pp<L, E, false, Cf::TWS, NH, 1, C>(v, hv, hw, t, a.tws);
-        else fft<L, E, false, Cf::TWS, NH, 1, C>(v, hv, t, a.tws);
+        if constexpr (PP) fft_pp<L, E, false, Cf::TWS, NH, 1, C>(v, hv, hw, tf, tws_f);
+        else fft<L, E, false, Cf::TWS, NH, 1, C>(v, hv, tf, tws_f);
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < E; ++m)
 #pragma unroll
-            for (int h = 0; h < NH; ++h) zv[NH * (t + m * TPF) + h] = v[h][m];
+            for (int h = 0; h < NH; ++h) zv[NH * (tf + m * TPF) + h] = v[h][m];
         __syncthreads();
         // Split the packed spectra and store columns [0, K_out) of both rows
         // (tile tail zero-filled); unrolled over a compile-time item bound.
@@ -265,7 +292,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
         const R half = (R)0.5;
 #pragma unroll
         for (int u = 0; u < OPT; ++u) {
-            const int q = tid + u * NT;
+            const int q = tidf + u * NT;
             if (q < nitems) {
                 const int c = q % T;
                 const int rest = q / T;
