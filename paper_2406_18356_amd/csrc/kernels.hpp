@@ -127,8 +127,8 @@ constexpr int waves_per_eu() {
 #ifndef MSR_ROW_PINGPONG
 #define MSR_ROW_PINGPONG 1
 #endif
-#ifndef MSR_ROW_REFETCH
-#define MSR_ROW_REFETCH 1
+#ifndef MSR_REFETCH
+#define MSR_REFETCH 1
 #endif
 constexpr size_t kLdsBytes = 160 * 1024;
 constexpr bool row_pingpong(size_t line_bytes, int threads, int grid_blocks) {
@@ -259,11 +259,11 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
         // LDS and global addresses, as the inverse one.  Through opaque copies
         // of the table pointers and thread indices it loads and computes them
         // again instead of keeping the inverse's values live in registers
-        // across the epilogue (MSR_ROW_REFETCH = 0: keep them).
+        // across the epilogue (MSR_REFETCH = 0: keep them).
         const C* tw_f = a.tw;
         const C* tws_f = a.tws;
         int tf = t, tidf = tid;
-#if MSR_ROW_REFETCH
+#if MSR_REFETCH
         if constexpr (INV_IN) {
             asm volatile("" : "+s"(tw_f), "+s"(tws_f));
             asm volatile("" : "+v"(tf), "+v"(tidf));
@@ -567,14 +567,25 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
         }
 
     if constexpr (Mode::INVERSE) {
+        // As in the row passes: opaque copies make the inverse transform load
+        // its twiddles and compute its addresses again rather than keep the
+        // forward transform's live across the pointwise step.
+        const C* tw_i = a.tw;
+        const C* tws_i = a.tws;
+        int ti = t;
+        size_t base_i = base;
+#if MSR_REFETCH
+        asm volatile("" : "+s"(tw_i), "+s"(tws_i));
+        asm volatile("" : "+v"(ti), "+v"(base_i));
+#endif
         __syncthreads();
-        fft<L, E, true, Cf::TWS, NH, CB, C>(v, hv, t, a.tws);
+        fft<L, E, true, Cf::TWS, NH, CB, C>(v, hv, ti, tws_i);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            const int i = t + m * TPF;
+            const int i = ti + m * TPF;
             C s = v[0][m];
-            if constexpr (PADDED) s = cadd(s, cmulc(v[1][m], a.tw[i]));
-            a.spec_out[base + (size_t)i * T] = s;
+            if constexpr (PADDED) s = cadd(s, cmulc(v[1][m], tw_i[i]));
+            a.spec_out[base_i + (size_t)i * T] = s;
         }
     } else if constexpr (Mode::STORE_SPECTRUM) {
         // unpadded forward transform only: bin ky = t + m*TPF
