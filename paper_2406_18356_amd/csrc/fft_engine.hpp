@@ -16,9 +16,24 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <type_traits>
 
 namespace msr {
+
+// Element i of the global-memory array p, addressed as p plus a 32-bit byte
+// offset.  The cast to the global address space lets the compiler emit
+// global (not flat) loads and stores even where p was moved by integer
+// arithmetic (a channel of a batched launch): flat accesses would also count
+// against the LDS wait counter and need a full 64-bit address per lane.
+// Every array the kernels index is smaller than 4 GiB, so an access costs one
+// 32-bit add on top of a uniform base.
+template <typename T>
+__device__ __forceinline__ T& el(T* p, uint32_t i) {
+    using B = std::conditional_t<std::is_const_v<T>, const char, char>;
+    auto* g = (__attribute__((address_space(1))) B*)p;
+    return *(T*)(g + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
 
 template <typename R>
 struct cplx_of;
@@ -182,7 +197,7 @@ __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, 
         const int jm = j & (NS - 1);
         C w[RD];
         if constexpr (NS > 1) {
-            const C* row = tws + stage_offset(L, E, NS) + 4 * jm;
+            const C* row = &el(tws, (uint32_t)(stage_offset(L, E, NS) + 4 * jm));
 #pragma unroll
             for (int r = 1; r < RD; ++r) {
                 const int lg = 31 - __builtin_clz(r);

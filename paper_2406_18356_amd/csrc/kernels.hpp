@@ -50,8 +50,8 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
     return (b % NX) * (nblocks / NX) + b / NX;
 }
 
-__device__ __forceinline__ size_t spec_idx(int kx, int row, int NR, int T) {
-    return ((size_t)(kx / T) * NR + row) * T + (kx % T);
+__device__ __forceinline__ uint32_t spec_idx(int kx, int row, int NR, int T) {
+    return ((uint32_t)kx / T * (uint32_t)NR + (uint32_t)row) * (uint32_t)T + (uint32_t)kx % T;
 }
 
 // ===========================================================================
@@ -138,6 +138,37 @@ constexpr bool row_pingpong(size_t line_bytes, int threads, int grid_blocks) {
            (grid_blocks <= 256 || (size_t)resident * 2 * line_bytes <= kLdsBytes);
 }
 
+// The column items of a row block: item u of thread `tid` is q = tid + u NT,
+// i.e. column kx of row pair p (kx % T fastest, then the pair, then the tile).
+// `ia` is the tiled spectrum index of row row0 + 2p at that column; the pair's
+// second row is at ia + T.  When NT is a multiple of T * PAIRS, p does not
+// depend on u and kx and ia advance by uniform steps.
+template <int T, int PAIRS, int NT>
+struct RowItems {
+    static constexpr bool REG = NT % (T * PAIRS) == 0;
+    int tid, row0, NR, p0, kx0;
+    uint32_t i0, istep;
+    __device__ __forceinline__ RowItems(int tid_, int row0_, int NR_) : tid(tid_), row0(row0_), NR(NR_) {
+        p0 = (tid / T) % PAIRS;
+        kx0 = (tid / T / PAIRS) * T + tid % T;
+        i0 = spec_idx(kx0, row0 + 2 * p0, NR, T);
+        istep = (uint32_t)(NT / PAIRS) * (uint32_t)NR;
+    }
+    __device__ __forceinline__ void get(int u, int& q, int& p, int& kx, uint32_t& ia) const {
+        q = tid + u * NT;
+        if constexpr (REG) {
+            p = p0;
+            kx = kx0 + u * (NT / PAIRS);
+            ia = i0 + (uint32_t)u * istep;
+        } else {
+            const int rest = q / T;
+            p = rest % PAIRS;
+            kx = (rest / PAIRS) * T + q % T;
+            ia = spec_idx(kx, row0 + 2 * p, NR, T);
+        }
+    }
+};
+
 template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
 __global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R, EMAX>::TPF))
 MSR_WAVES_ATTR(EMAX, R)
@@ -186,43 +217,36 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
         constexpr int NITEMS = ((HALF + T) / T) * T * PAIRS;
         constexpr int IPT = (NITEMS + NT - 1) / NT;
         C xa[IPT], xb[IPT];
+        const RowItems<T, PAIRS, NT> items(tid, row0, a.NR);
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
-            const int q = tid + u * NT;
-            const int c = q % T;
-            const int rest = q / T;
-            const int p = rest % PAIRS;
-            const int kx = (rest / PAIRS) * T + c;
-            const int rr = row0 + 2 * p;
+            int q, p, kx;
+            uint32_t ia;
+            items.get(u, q, p, kx, ia);
             xa[u] = mk<C>(zero, zero);
             xb[u] = xa[u];
             if (q < NITEMS && kx < a.K_in) {
-                xa[u] = a.spec_in[spec_idx(kx, rr, a.NR, T)];
-                xb[u] = a.spec_in[spec_idx(kx, rr + 1, a.NR, T)];
+                xa[u] = el(a.spec_in, ia);
+                xb[u] = el(a.spec_in, ia + T);
             }
         }
         if (a.K_in2 > 0) {
 #pragma unroll
             for (int u = 0; u < IPT; ++u) {
-                const int q = tid + u * NT;
-                const int c = q % T;
-                const int rest = q / T;
-                const int p = rest % PAIRS;
-                const int kx = (rest / PAIRS) * T + c;
-                const int rr = row0 + 2 * p;
+                int q, p, kx;
+                uint32_t ia;
+                items.get(u, q, p, kx, ia);
                 if (q < NITEMS && kx < a.K_in2) {
-                    xa[u] = cadd(xa[u], a.spec_in2[spec_idx(kx, rr, a.NR, T)]);
-                    xb[u] = cadd(xb[u], a.spec_in2[spec_idx(kx, rr + 1, a.NR, T)]);
+                    xa[u] = cadd(xa[u], el(a.spec_in2, ia));
+                    xb[u] = cadd(xb[u], el(a.spec_in2, ia + T));
                 }
             }
         }
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
-            const int q = tid + u * NT;
-            const int c = q % T;
-            const int rest = q / T;
-            const int p = rest % PAIRS;
-            const int kx = (rest / PAIRS) * T + c;
+            int q, p, kx;
+            uint32_t ia;
+            items.get(u, q, p, kx, ia);
             if (q < NITEMS && kx <= HALF) {
                 const LdsView<1, C> zp{lds + p * ZLEN, 0};
                 zp[kx] = mk<C>(xa[u].x - xb[u].y, xa[u].y + xb[u].x);  // Xa + i Xb
@@ -240,7 +264,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             C s = v[0][m];
-            if constexpr (PADDED) s = cadd(s, cmulc(v[1][m], a.tw[t + m * TPF]));
+            if constexpr (PADDED) s = cadd(s, cmulc(v[1][m], el(a.tw, t + m * TPF)));
             z[m] = s;
         }
     } else {
@@ -272,7 +296,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             v[0][m] = z[m];
-            if constexpr (PADDED) v[1][m] = cmul(z[m], tw_f[tf + m * TPF]);
+            if constexpr (PADDED) v[1][m] = cmul(z[m], el(tw_f, tf + m * TPF));
         }
         __syncthreads();
         if constexpr (PP) fft_pp<L, E, false, Cf::TWS, NH, 1, C>(v, hv, hw, tf, tws_f);
@@ -290,15 +314,13 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
         constexpr int OMAX = ((HALF + T) / T) * T * PAIRS;
         constexpr int OPT = (OMAX + NT - 1) / NT;
         const R half = (R)0.5;
+        const RowItems<T, PAIRS, NT> oitems(tidf, row0, a.NR);
 #pragma unroll
         for (int u = 0; u < OPT; ++u) {
-            const int q = tidf + u * NT;
+            int q, p, kx;
+            uint32_t ia;
+            oitems.get(u, q, p, kx, ia);
             if (q < nitems) {
-                const int c = q % T;
-                const int rest = q / T;
-                const int p = rest % PAIRS;
-                const int kx = (rest / PAIRS) * T + c;
-                const int rr = row0 + 2 * p;
                 C xa = mk<C>(zero, zero), xb = xa;
                 if (kx < a.K_out) {
                     const LdsView<1, C> zp{lds + p * ZLEN, 0};
@@ -307,8 +329,8 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
                     xa = mk<C>(half * (zk.x + zm.x), half * (zk.y - zm.y));
                     xb = mk<C>(half * (zk.y + zm.y), -half * (zk.x - zm.x));
                 }
-                a.spec_out[spec_idx(kx, rr, a.NR, T)] = xa;
-                a.spec_out[spec_idx(kx, rr + 1, a.NR, T)] = xb;
+                el(a.spec_out, ia) = xa;
+                el(a.spec_out, ia + T) = xb;
             }
         }
     }
@@ -319,7 +341,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
             block_sum<NQ, NT>(acc, red, tot);
             if (tid == 0)
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) a.partials[(size_t)blockIdx.x * NQ + q] = tot[q];
+                for (int q = 0; q < NQ; ++q) el(a.partials, blockIdx.x * NQ + q) = tot[q];
         }
     }
 }
@@ -340,7 +362,8 @@ struct EpiLoad {
     __device__ __forceinline__ void to_channel(long long off) { img = shifted(img, off); }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R>, double*) const {
-        return mk<cplx<R>>(scale * img[(size_t)r * ld + i], scale * img[(size_t)(r + 1) * ld + i]);
+        const uint32_t ia = (uint32_t)r * ld + i;
+        return mk<cplx<R>>(scale * el(img, ia), scale * el(img, ia + ld));
     }
 };
 
@@ -355,7 +378,8 @@ struct EpiLoadShift {
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R>, double*) const {
         const int h = P / 2;
         const int c = (i + h) & (P - 1);
-        return mk<cplx<R>>(img[(size_t)((r + h) & (P - 1)) * P + c], img[(size_t)((r + 1 + h) & (P - 1)) * P + c]);
+        return mk<cplx<R>>(el(img, (uint32_t)((r + h) & (P - 1)) * P + c),
+                           el(img, (uint32_t)((r + 1 + h) & (P - 1)) * P + c));
     }
 };
 
@@ -369,8 +393,9 @@ struct EpiStore {
     __device__ __forceinline__ void to_channel(long long off) { out = shifted(out, off); }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double*) const {
-        out[(size_t)r * ld + i] = scale * z.x;
-        out[(size_t)(r + 1) * ld + i] = scale * z.y;
+        const uint32_t ia = (uint32_t)r * ld + i;
+        el(out, ia) = scale * z.x;
+        el(out, ia + ld) = scale * z.y;
         return z;
     }
 };
@@ -388,14 +413,15 @@ struct EpiResid {
     }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc) const {
+        const uint32_t ia = (uint32_t)r * ld + i;
         if (y) {
-            z.x -= y[(size_t)r * ld + i];
-            z.y -= y[(size_t)(r + 1) * ld + i];
+            z.x -= el(y, ia);
+            z.y -= el(y, ia + ld);
         }
         acc[0] += (double)z.x * z.x + (double)z.y * z.y;
         if (r_out) {
-            r_out[(size_t)r * ld + i] = z.x;
-            r_out[(size_t)(r + 1) * ld + i] = z.y;
+            el(r_out, ia) = z.x;
+            el(r_out, ia + ld) = z.y;
         }
         return z;
     }
@@ -435,12 +461,12 @@ struct EpiUpdate {
         return fmaR(t_cur, beta - p1, beta);
     }
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc) const {
-        const size_t ia = (size_t)r * ld + i, ib = ia + ld;
-        R pa = b2[ia], pb = b2[ib];
-        const R qa = upd(z.x, b1[ia], pa);
-        const R qb = upd(z.y, b1[ib], pb);
-        b2[ia] = pa;
-        b2[ib] = pb;
+        const uint32_t ia = (uint32_t)r * ld + i, ib = ia + ld;
+        R pa = el(b2, ia), pb = el(b2, ib);
+        const R qa = upd(z.x, el(b1, ia), pa);
+        const R qb = upd(z.y, el(b1, ib), pb);
+        el(b2, ia) = pa;
+        el(b2, ib) = pb;
         acc[0] += (double)fabs(pa) + (double)fabs(pb);
         return mk<cplx<R>>(qa, qb);
     }
@@ -460,11 +486,11 @@ struct EpiPower {
     }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc) const {
-        const size_t ia = (size_t)r * ld + i, ib = ia + ld;
+        const uint32_t ia = (uint32_t)r * ld + i, ib = ia + ld;
         acc[0] += (double)z.x * z.x + (double)z.y * z.y;
-        acc[1] += (double)z.x * (double)(vscale * vprev[ia]) + (double)z.y * (double)(vscale * vprev[ib]);
-        w_out[ia] = z.x;
-        w_out[ib] = z.y;
+        acc[1] += (double)z.x * (double)(vscale * el(vprev, ia)) + (double)z.y * (double)(vscale * el(vprev, ib));
+        el(w_out, ia) = z.x;
+        el(w_out, ib) = z.y;
         return z;
     }
 };
@@ -540,17 +566,17 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
     for (int h = 0; h < NH; ++h) hv[h] = LdsView<CB, C>{lds + h * CB * HL, cl};
 
     C v[NH][E];
-    const size_t base = (size_t)tile * a.NR * T + c;
+    const uint32_t base = (uint32_t)tile * a.NR * T + c;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int i = t + m * TPF;
         C y = mk<C>(zero, zero);
         if (live) {
-            y = cscale(a.spec_in[base + (size_t)i * T], a.in_scale);
-            if (a.spec_in2) y = csub(y, a.spec_in2[base + (size_t)i * T]);
+            y = cscale(el(a.spec_in, base + (uint32_t)i * T), a.in_scale);
+            if (a.spec_in2) y = csub(y, el(a.spec_in2, base + (uint32_t)i * T));
         }
         v[0][m] = y;
-        if constexpr (PADDED) v[1][m] = cmul(y, a.tw[i]);
+        if constexpr (PADDED) v[1][m] = cmul(y, el(a.tw, i));
     }
     fft<L, E, false, Cf::TWS, NH, CB, C>(v, hv, t, a.tws);
 
@@ -573,7 +599,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
         const C* tw_i = a.tw;
         const C* tws_i = a.tws;
         int ti = t;
-        size_t base_i = base;
+        uint32_t base_i = base;
 #if MSR_REFETCH
         asm volatile("" : "+s"(tw_i), "+s"(tws_i));
         asm volatile("" : "+v"(ti), "+v"(base_i));
@@ -584,13 +610,13 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
         for (int m = 0; m < E; ++m) {
             const int i = ti + m * TPF;
             C s = v[0][m];
-            if constexpr (PADDED) s = cadd(s, cmulc(v[1][m], tw_i[i]));
-            a.spec_out[base_i + (size_t)i * T] = s;
+            if constexpr (PADDED) s = cadd(s, cmulc(v[1][m], el(tw_i, i)));
+            el(a.spec_out, base_i + (uint32_t)i * T) = s;
         }
     } else if constexpr (Mode::STORE_SPECTRUM) {
         // unpadded forward transform only: bin ky = t + m*TPF
 #pragma unroll
-        for (int m = 0; m < E; ++m) a.spec_out[base + (size_t)(t + m * TPF) * T] = v[0][m];
+        for (int m = 0; m < E; ++m) el(a.spec_out, base + (uint32_t)(t + m * TPF) * T) = v[0][m];
     }
 
     if constexpr (NQ > 0) {
@@ -599,7 +625,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
             block_sum<NQ, NT>(acc, red, tot);
             if (tid == 0)
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) a.partials[(size_t)pblock * NQ + q] = tot[q];
+                for (int q = 0; q < NQ; ++q) el(a.partials, (uint32_t)pblock * NQ + q) = tot[q];
         }
     }
 }
@@ -651,7 +677,7 @@ struct ModePsf {
     __device__ __forceinline__ void to_channel(long long off) { hh = shifted(hh, off); }
     __device__ __forceinline__ void use(const FilterCoef<R>&) {}
     __device__ __forceinline__ cplx<R> apply(int tile, int c, int, int ky, bool, cplx<R> y, double*) const {
-        return cscale(y, hh[((size_t)tile * P + ky) * T + c]);
+        return cscale(y, el(hh, ((uint32_t)tile * P + ky) * T + c));
     }
 };
 
