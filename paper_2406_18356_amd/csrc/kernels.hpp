@@ -208,6 +208,16 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     C v[NH][E];
     C z[E];
     const R zero = 0;
+    // Image values the epilogue reads, loaded up front (after the spectrum
+    // columns) so that their latency hides behind the inverse transform.
+    constexpr int NPRE = Epi::NPRE > 0 ? Epi::NPRE : 1;
+    R pre[E][NPRE];
+    auto prefetch = [&]() {
+        if constexpr (Epi::NPRE > 0) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) epi.load(ra, t + m * TPF, pre[m]);
+        }
+    };
 
     if constexpr (INV_IN) {
         // Half-plane columns of both rows -> full Hermitian-combined line Z in
@@ -242,6 +252,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
                 }
             }
         }
+        prefetch();
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
             int q, p, kx;
@@ -268,6 +279,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
             z[m] = s;
         }
     } else {
+        prefetch();
 #pragma unroll
         for (int m = 0; m < E; ++m) z[m] = mk<C>(zero, zero);
     }
@@ -276,7 +288,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 #pragma unroll
     for (int q = 0; q < (NQ > 0 ? NQ : 1); ++q) acc[q] = 0.0;
 #pragma unroll
-    for (int m = 0; m < E; ++m) z[m] = epi.apply(ra, t + m * TPF, z[m], acc);
+    for (int m = 0; m < E; ++m) z[m] = epi.apply(ra, t + m * TPF, z[m], acc, pre[m]);
 
     if constexpr (FWD_OUT) {
         // The forward transform reads the same twiddles, and computes the same
@@ -347,21 +359,24 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 }
 
 // ---------------------------------------------------------------------------
-// Row epilogues.  apply(row, i, z, acc) gets the cropped inverse result of
-// rows (row, row+1) at column i packed as z = (x_row, x_row+1) and returns the
-// pair to transform forward (or anything, when nothing follows).
+// Row epilogues.  apply(row, i, z, acc, pre) gets the cropped inverse result
+// of rows (row, row+1) at column i packed as z = (x_row, x_row+1) and returns
+// the pair to transform forward (or anything, when nothing follows).  `pre`
+// holds the NPRE values load(row, i, pre) fetched for that element at the
+// start of the kernel.
 // ---------------------------------------------------------------------------
 
 // Load an image (times a scale): the forward pass of a plain row transform.
 template <typename R>
 struct EpiLoad {
-    static constexpr int NQ = 0;
+    static constexpr int NQ = 0, NPRE = 0;
     const R* __restrict__ img;
     int ld;
     R scale;
     __device__ __forceinline__ void to_channel(long long off) { img = shifted(img, off); }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
-    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R>, double*) const {
+    __device__ __forceinline__ void load(int, int, R*) const {}
+    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R>, double*, const R*) const {
         const uint32_t ia = (uint32_t)r * ld + i;
         return mk<cplx<R>>(scale * el(img, ia), scale * el(img, ia + ld));
     }
@@ -370,12 +385,13 @@ struct EpiLoad {
 // Load a P x P PSF with ifftshift (row and column rolled by P/2).
 template <typename R>
 struct EpiLoadShift {
-    static constexpr int NQ = 0;
+    static constexpr int NQ = 0, NPRE = 0;
     const R* __restrict__ img;
     int P;
     __device__ __forceinline__ void to_channel(long long off) { img = shifted(img, off); }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
-    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R>, double*) const {
+    __device__ __forceinline__ void load(int, int, R*) const {}
+    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R>, double*, const R*) const {
         const int h = P / 2;
         const int c = (i + h) & (P - 1);
         return mk<cplx<R>>(el(img, (uint32_t)((r + h) & (P - 1)) * P + c),
@@ -386,13 +402,14 @@ struct EpiLoadShift {
 // Store the cropped inverse (times a scale) as an image.
 template <typename R>
 struct EpiStore {
-    static constexpr int NQ = 0;
+    static constexpr int NQ = 0, NPRE = 0;
     R* __restrict__ out;
     int ld;
     R scale;
     __device__ __forceinline__ void to_channel(long long off) { out = shifted(out, off); }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
-    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double*) const {
+    __device__ __forceinline__ void load(int, int, R*) const {}
+    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double*, const R*) const {
         const uint32_t ia = (uint32_t)r * ld + i;
         el(out, ia) = scale * z.x;
         el(out, ia + ld) = scale * z.y;
@@ -403,7 +420,7 @@ struct EpiStore {
 // r = H x - y (y may be null): accumulates ||r||^2, optionally stores r, forwards r.
 template <typename R>
 struct EpiResid {
-    static constexpr int NQ = 1;
+    static constexpr int NQ = 1, NPRE = 2;
     const R* __restrict__ y;
     R* __restrict__ r_out;
     int ld;
@@ -412,11 +429,18 @@ struct EpiResid {
         r_out = shifted(r_out, off);
     }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
-    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc) const {
+    __device__ __forceinline__ void load(int r, int i, R* p) const {
+        if (y) {
+            const uint32_t ia = (uint32_t)r * ld + i;
+            p[0] = el(y, ia);
+            p[1] = el(y, ia + ld);
+        }
+    }
+    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc, const R* p) const {
         const uint32_t ia = (uint32_t)r * ld + i;
         if (y) {
-            z.x -= el(y, ia);
-            z.y -= el(y, ia + ld);
+            z.x -= p[0];
+            z.y -= p[1];
         }
         acc[0] += (double)z.x * z.x + (double)z.y * z.y;
         if (r_out) {
@@ -434,7 +458,7 @@ struct EpiResid {
 // beta_k overwrites b2 (same element, same thread); alpha_k is forwarded.
 template <typename R>
 struct EpiUpdate {
-    static constexpr int NQ = 1;
+    static constexpr int NQ = 1, NPRE = 0;
     const R* __restrict__ b1;
     R* __restrict__ b2;  // in: beta_{k-2}; out: beta_k
     int ld;
@@ -460,7 +484,10 @@ struct EpiUpdate {
         p2 = beta;
         return fmaR(t_cur, beta - p1, beta);
     }
-    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc) const {
+    // no prefetch: the images it reads (beta_{k-1}, beta_{k-2}) would take the
+    // kernel past the register budget of two blocks per CU
+    __device__ __forceinline__ void load(int, int, R*) const {}
+    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc, const R*) const {
         const uint32_t ia = (uint32_t)r * ld + i, ib = ia + ld;
         R pa = el(b2, ia), pb = el(b2, ib);
         const R qa = upd(z.x, el(b1, ia), pa);
@@ -475,7 +502,7 @@ struct EpiUpdate {
 // Power iteration: w = A v.  Accumulates <w, w> and <w, vprev>, stores w.
 template <typename R>
 struct EpiPower {
-    static constexpr int NQ = 2;
+    static constexpr int NQ = 2, NPRE = 0;
     const R* __restrict__ vprev;
     R* __restrict__ w_out;
     int ld;
@@ -485,7 +512,8 @@ struct EpiPower {
         w_out = shifted(w_out, off);
     }
     __device__ __forceinline__ void use(const ChanScalars<R>&) {}
-    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc) const {
+    __device__ __forceinline__ void load(int, int, R*) const {}
+    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc, const R*) const {
         const uint32_t ia = (uint32_t)r * ld + i, ib = ia + ld;
         acc[0] += (double)z.x * z.x + (double)z.y * z.y;
         acc[1] += (double)z.x * (double)(vscale * el(vprev, ia)) + (double)z.y * (double)(vscale * el(vprev, ib));
