@@ -117,6 +117,20 @@ constexpr int waves_per_eu() {
 #define MSR_WAVES_ATTR(EMAX, R)
 #endif
 
+// A row kernel whose epilogue holds prefetched values across the inverse
+// transform (Epi::MIN_WAVES = 4) is compiled for four waves per SIMD when it
+// keeps 8 or fewer complex values per thread, so that its register count stays
+// within what two 512-thread blocks per CU allow.
+template <class Epi, int EMAX, typename R>
+constexpr int row_min_waves() {
+    return (EMAX * (int)sizeof(cplx<R>)) < 128 ? Epi::MIN_WAVES : 1;
+}
+#ifdef MSR_WAVES_PER_EU
+#define MSR_ROW_WAVES_ATTR(EMAX, R, Epi) MSR_WAVES_ATTR(EMAX, R)
+#else
+#define MSR_ROW_WAVES_ATTR(EMAX, R, Epi) __attribute__((amdgpu_waves_per_eu(row_min_waves<Epi, EMAX, R>())))
+#endif
+
 // Row kernels exchange FFT stages through two LDS arrays (one barrier per
 // stage) when the doubled footprint still lets a CU hold blocks for 16 waves
 // (4 per SIMD), or when the launch has no more blocks than the chip has CUs
@@ -171,7 +185,7 @@ struct RowItems {
 
 template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
 __global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R, EMAX>::TPF))
-MSR_WAVES_ATTR(EMAX, R)
+MSR_ROW_WAVES_ATTR(EMAX, R, Epi)
 row_kernel(RowArgs<R> a0, Epi epi0) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     using C = cplx<R>;
@@ -369,7 +383,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 // Load an image (times a scale): the forward pass of a plain row transform.
 template <typename R>
 struct EpiLoad {
-    static constexpr int NQ = 0, NPRE = 0;
+    static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
     const R* __restrict__ img;
     int ld;
     R scale;
@@ -385,7 +399,7 @@ struct EpiLoad {
 // Load a P x P PSF with ifftshift (row and column rolled by P/2).
 template <typename R>
 struct EpiLoadShift {
-    static constexpr int NQ = 0, NPRE = 0;
+    static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
     const R* __restrict__ img;
     int P;
     __device__ __forceinline__ void to_channel(long long off) { img = shifted(img, off); }
@@ -402,7 +416,7 @@ struct EpiLoadShift {
 // Store the cropped inverse (times a scale) as an image.
 template <typename R>
 struct EpiStore {
-    static constexpr int NQ = 0, NPRE = 0;
+    static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
     R* __restrict__ out;
     int ld;
     R scale;
@@ -420,7 +434,7 @@ struct EpiStore {
 // r = H x - y (y may be null): accumulates ||r||^2, optionally stores r, forwards r.
 template <typename R>
 struct EpiResid {
-    static constexpr int NQ = 1, NPRE = 2;
+    static constexpr int NQ = 1, NPRE = 2, MIN_WAVES = 1;
     const R* __restrict__ y;
     R* __restrict__ r_out;
     int ld;
@@ -458,7 +472,7 @@ struct EpiResid {
 // beta_k overwrites b2 (same element, same thread); alpha_k is forwarded.
 template <typename R>
 struct EpiUpdate {
-    static constexpr int NQ = 1, NPRE = 0;
+    static constexpr int NQ = 1, NPRE = 2, MIN_WAVES = 4;
     const R* __restrict__ b1;
     R* __restrict__ b2;  // in: beta_{k-2}; out: beta_k
     int ld;
@@ -484,14 +498,18 @@ struct EpiUpdate {
         p2 = beta;
         return fmaR(t_cur, beta - p1, beta);
     }
-    // no prefetch: the images it reads (beta_{k-1}, beta_{k-2}) would take the
-    // kernel past the register budget of two blocks per CU
-    __device__ __forceinline__ void load(int, int, R*) const {}
-    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc, const R*) const {
+    // beta_{k-1} of both rows is prefetched; beta_{k-2} too would not fit the
+    // register budget
+    __device__ __forceinline__ void load(int r, int i, R* p) const {
+        const uint32_t ia = (uint32_t)r * ld + i;
+        p[0] = el(b1, ia);
+        p[1] = el(b1, ia + ld);
+    }
+    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc, const R* p) const {
         const uint32_t ia = (uint32_t)r * ld + i, ib = ia + ld;
         R pa = el(b2, ia), pb = el(b2, ib);
-        const R qa = upd(z.x, el(b1, ia), pa);
-        const R qb = upd(z.y, el(b1, ib), pb);
+        const R qa = upd(z.x, p[0], pa);
+        const R qb = upd(z.y, p[1], pb);
         el(b2, ia) = pa;
         el(b2, ib) = pb;
         acc[0] += (double)fabs(pa) + (double)fabs(pb);
@@ -502,7 +520,7 @@ struct EpiUpdate {
 // Power iteration: w = A v.  Accumulates <w, w> and <w, vprev>, stores w.
 template <typename R>
 struct EpiPower {
-    static constexpr int NQ = 2, NPRE = 0;
+    static constexpr int NQ = 2, NPRE = 0, MIN_WAVES = 1;
     const R* __restrict__ vprev;
     R* __restrict__ w_out;
     int ld;
