@@ -613,33 +613,50 @@ struct Impl {
     }
 
     // Exact objective of step s at image x (device), FP64 sums.  out: F, data, l1.
-    // Uses SB, SC as scratch (and SL for step 2); SA is preserved.
+    // Uses SB, SC (and SG for step 2) as scratch; SA and SL are preserved.  The
+    // sums land in scal[16..19] and come back to the host in one copy.
     msr_status objective_at(int step, double lambda, const R* x, double out[3], hipStream_t s) {
-        double data = 0.0;
+        constexpr int kSlot = 16;  // data (or ||r||^2), sum w |R|^2, sum g_L^2 |.|^2, ||x||_1
         if (step == 1) {
             TRY(fwd_image(1, x, (R)1, SB(), c->K[0], s));
             TRY(col_psf(1, SB(), SC(), s));
             opr(1)->row_resid(row_args(SC(), c->K[0], nullptr, 0, nullptr, 0, true), EpiResid<R>{dirty(1), nullptr, N()}, s);
             LAUNCHCHK(c);
-            TRY(reduce(row_grid(1), 1, 0, &data, s));
+            TRY(reduce(row_grid(1), 1, kSlot, nullptr, s));
         } else {
             // ||G_H r||^2 = ||r||^2 / sigma^2 - (1/P^2) sum w |R|^2, ||G_L (l - x)||^2 = (1/P^2) sum g_L^2 |.|^2
-            double dr = 0.0, dw = 0.0, dl = 0.0;
             TRY(fwd_image(2, x, (R)1, SB(), KA(2), s));
             TRY(col_psf(2, SB(), SC(), s));
             opr(2)->row_resid_fwd(row_args(SC(), c->K[1], nullptr, 0, SC(), c->KL, true),
                                   EpiResid<R>{dirty(2), nullptr, N()}, s);
             LAUNCHCHK(c);
-            TRY(reduce(row_grid(2), 1, 0, &dr, s));
-            TRY(col_filtw(SC(), SC(), true, s));
-            TRY(reduce(col_grid(2, c->KL), 1, 0, &dw, s));
-            TRY(col_filtl(SB(), SL(), SC(), true, s));
-            TRY(reduce(col_grid(2, c->KL), 1, 0, &dl, s));
-            const double ip2 = 1.0 / ((double)P() * (double)P());
-            data = dr / c->sigma2 + (dl - dw) * ip2;
+            TRY(reduce(row_grid(2), 1, kSlot, nullptr, s));
+            // C_w on SC (in place) and C_{g_L^2} on SB - SL (into SG) in one
+            // launch; the blocks of each pass hold their own partial rows
+            const ModeFilterW<R> mw{filters(), inv_p2()};
+            const ModeFilterL<R> ml{filters(), inv_p2()};
+            opf_->col_filt_wl(col_args(SC(), nullptr, SC(), c->KL, true), mw, col_args(SB(), SL(), SG(), c->KL, true), ml,
+                              s);
+            LAUNCHCHK(c);
+            const int g = (c->KL + opf_->col_cb - 1) / opf_->col_cb;
+            TRY(reduce(g, 1, kSlot + 1, nullptr, s));
+            hipLaunchKernelGGL(finalize_sums, dim3(1), dim3(256), 0, s, partials() + g, g, 1, scal() + kSlot + 2);
+            LAUNCHCHK(c);
         }
-        double l1 = 0.0;
-        TRY(image_reduce(x, nullptr, 0, &l1, s));
+        const size_t n = c->sh.img_elems;
+        const int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
+        hipLaunchKernelGGL(image_sums<R>, dim3(blocks), dim3(256), 0, s, x, (const R*)nullptr, n, 0, partials());
+        LAUNCHCHK(c);
+        TRY(reduce(blocks, 1, kSlot + 3, nullptr, s));
+        double h[4];
+        HIPCHK(c, hipMemcpyAsync(h, scal() + kSlot, sizeof h, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        double data = h[0];
+        if (step == 2) {
+            const double ip2 = 1.0 / ((double)P() * (double)P());
+            data = h[0] / c->sigma2 + (h[2] - h[1]) * ip2;
+        }
+        const double l1 = h[3];
         out[0] = data + lambda * l1;
         out[1] = data;
         out[2] = l1;
