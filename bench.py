@@ -49,6 +49,8 @@ WORKLOADS = {
                       "Gaussians, 197 antennas 8 h at 30 s, cut 20%, 500 FISTA iterations per step, positivity on"),
     4096: ("sky4096", "two-step solve, 4096x4096 image on an 8192x8192 zero-padded grid: 8000 points + 200 "
                       "Gaussians, 197 antennas 8 h at 30 s, cut 15%, 500 FISTA iterations per step, positivity on"),
+    8192: ("sky8192", "two-step solve, 8192x8192 image on a 16384x16384 zero-padded grid: 32000 points + 800 "
+                      "Gaussians, 512 antennas 4 h at 10 s, cut 10%, 500 FISTA iterations per step, positivity on"),
 }
 
 
@@ -380,7 +382,7 @@ def main(argv=None):
     cfg = synth.preset(preset)
     iters = args.iters or cfg.iters
     t = time.perf_counter()
-    pr = synth.make_problem(cfg, with_full=False)
+    pr = synth.make_problem(cfg, with_full=False, progress=lambda msg: log(f"workload {preset}: {msg}"))
     log(f"workload {preset}: generated in {time.perf_counter() - t:.1f} s; counts {pr.counts}")
     dev = torch.device("cuda:0")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731

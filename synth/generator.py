@@ -191,11 +191,12 @@ def _max_radius(xyz, arr):
     return m
 
 
-def grid_weights(xyz, arr: ArrayConfig, P: int, uv_fill: float, ell: float, delta: float):
+def grid_weights(xyz, arr: ArrayConfig, P: int, uv_fill: float, ell: float, delta: float, progress=None):
     """Natural-weight grids of the full set and of the L / H splits.
 
     Returns (w_full, w_L, w_H, counts).  Grids are P x P float64 in FFT order
-    (row = v cell, column = u cell, index k mod P).
+    (row = v cell, column = u cell, index k mod P).  `progress(message)`, if
+    given, is called every 8 chunks of baselines.
     """
     rmax = _max_radius(xyz, arr)
     scale = uv_fill * P / rmax
@@ -203,7 +204,9 @@ def grid_weights(xyz, arr: ArrayConfig, P: int, uv_fill: float, ell: float, delt
     w_L = np.zeros(P * P, dtype=np.float64)
     w_H = np.zeros(P * P, dtype=np.float64)
     n_all = n_L = n_H = n_LH = 0
-    for u, v in uv_tracks(xyz, arr):
+    for chunk, (u, v) in enumerate(uv_tracks(xyz, arr)):
+        if progress is not None and chunk % 8 == 0:
+            progress(f"gridding baseline chunk {chunk}")
         uc, vc = u * scale, v * scale
         r = np.sqrt(uc * uc + vc * vc)
         iu = np.rint(uc).astype(np.int64)
@@ -260,8 +263,11 @@ def _dirty_from_weights(sky: np.ndarray, w: np.ndarray, noise_rel: float, rng) -
     return clean + rng.normal(0.0, sd, clean.shape)
 
 
-def make_problem(cfg: ProblemConfig, with_full: bool = True) -> Problem:
-    """Builds the problem; ``with_full=False`` skips the all-baseline PSF/dirty image."""
+def make_problem(cfg: ProblemConfig, with_full: bool = True, progress=None) -> Problem:
+    """Builds the problem; ``with_full=False`` skips the all-baseline PSF/dirty
+    image.  `progress(message)`, if given, is called as each stage starts (the
+    largest workloads take minutes)."""
+    say = progress if progress is not None else (lambda msg: None)
     n, P = cfg.n, cfg.P
     if n < 4 or (n & (n - 1)):
         raise ValueError("n must be a power of two >= 4")
@@ -275,11 +281,16 @@ def make_problem(cfg: ProblemConfig, with_full: bool = True) -> Problem:
     rmax_cells = cfg.uv_fill * P
     ell = cfg.cut * rmax_cells
     delta = cfg.delta if cfg.delta is not None else float(max(1, round(0.1 * ell)))
-    w_full, w_L, w_H, counts = grid_weights(xyz, cfg.array, P, cfg.uv_fill, ell, delta)
+    say("uv extent and gridding")
+    w_full, w_L, w_H, counts = grid_weights(xyz, cfg.array, P, cfg.uv_fill, ell, delta, progress)
+    say("PSF of the short baselines")
     psf_L = _psf_from_weights(w_L)
+    say("PSF of the long baselines")
     psf_H = _psf_from_weights(w_H)
     gen = lambda s: np.random.Generator(np.random.PCG64(s))  # noqa: E731
+    say("dirty image of the short baselines")
     dirty_L = _dirty_from_weights(sky, w_L, cfg.noise_rel, gen(s_nL))
+    say("dirty image of the long baselines")
     dirty_H = _dirty_from_weights(sky, w_H, cfg.noise_rel, gen(s_nH))
     if with_full:
         psf_full = _psf_from_weights(w_full)
@@ -352,6 +363,11 @@ PRESETS = {
     # 4096^2 image, 8192^2 grid at the same source density, cut 15 %.
     "sky4096": ProblemConfig(
         n=4096, sky=SkyConfig(8000, 200), array=ArrayConfig(197, 8.0, 30.0), cut=0.15, seed=3, iters=500
+    ),
+    # 8192^2 image, 16384^2 grid at the same source density: 512 antennas,
+    # 4 h at 10 s, cut 10 %.
+    "sky8192": ProblemConfig(
+        n=8192, sky=SkyConfig(32000, 800), array=ArrayConfig(512, 4.0, 10.0), cut=0.10, seed=4, iters=500
     ),
     # the paper's data shape: 512^2 image, 64 dishes, 4 h at 120 s.
     "paper512": ProblemConfig(
