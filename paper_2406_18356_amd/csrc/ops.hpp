@@ -13,11 +13,22 @@
 namespace msr {
 
 // Column-tile width of the row-spectrum layout for lines of length L, for an
-// element of `esize` bytes (8: complex64, 16: complex128).  The column pass
-// keeps NH * T lines of L complex values in LDS.
+// element of `esize` bytes (8: complex64, 16: complex128).  A row pass reads
+// and writes T adjacent columns of a row as one contiguous run.
 __host__ __device__ constexpr int tile_width(int L, int esize) {
-    if (esize == 8) return L <= 1024 ? 4 : (L <= 4096 ? 2 : 1);
+    if (esize == 8) return L <= 1024 ? 4 : (L <= 8192 ? 2 : 1);
     return L <= 1024 ? 4 : (L <= 2048 ? 2 : 1);
+}
+
+// Columns per column-pass block: the whole tile (T lines of NH halves in LDS)
+// unless that does not fit a CU's LDS or the variant asks for single columns;
+// then one column (the block reads every T-th value of each row run, and the
+// tile's other columns are read by neighbouring blocks through the L2).
+__host__ __device__ constexpr int col_block(int L, bool padded, int esize, bool onecol) {
+    const int NH = padded ? 2 : 1;
+    const int T = tile_width(L, esize);
+    const int whole = NH * T * (L + L / 16) * esize;
+    return (onecol || whole > 160 * 1024 - 4096) ? 1 : T;
 }
 
 // Largest number of complex elements a thread holds in a transform (the
@@ -38,16 +49,17 @@ __host__ __device__ constexpr int row_pairs(int L, bool padded, int esize, int e
 }
 
 // Whether the passes of a (length, padding, element size, elements per
-// thread) combination fit the 160 KB of LDS and the 1024-thread block limit.
-__host__ __device__ constexpr bool fits_lds(int L, bool padded, int esize, int emax) {
+// thread, single-column) variant fit the 160 KB of LDS and the 1024-thread
+// block limit.
+__host__ __device__ constexpr bool fits_lds(int L, bool padded, int esize, int emax, bool onecol) {
     const int NH = padded ? 2 : 1;
     const int E = L >= emax ? emax : L;
-    const int T = tile_width(L, esize);
-    const int col = NH * T * (L + L / 16) * esize;  // the whole-tile column block is the larger one
+    const int CB = col_block(L, padded, esize, onecol);
+    const int col = NH * CB * (L + L / 16) * esize;
     const int PT = padded ? 2 * L : L;
     const int pairs = row_pairs(L, padded, esize, emax);
     const int row = pairs * (PT + PT / 16) * esize;
-    return col <= 160 * 1024 - 4096 && row <= 160 * 1024 - 4096 && T * (L / E) <= 1024 && pairs * (L / E) <= 1024;
+    return col <= 160 * 1024 - 4096 && row <= 160 * 1024 - 4096 && CB * (L / E) <= 1024 && pairs * (L / E) <= 1024;
 }
 
 // Kernel variants per precision: elements per thread (hence radix schedule

@@ -17,7 +17,7 @@ struct Inst {
     static constexpr int ES = (int)sizeof(cplx<R>);
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     static constexpr int T = tile_width(L, ES);
-    static constexpr int CB = ONECOL ? 1 : T;
+    static constexpr int CB = col_block(L, PADDED, ES, ONECOL);
     static constexpr int PAIRS = row_pairs(L, PADDED, ES, EMAX);
     static constexpr int RT = PAIRS * Cf::TPF;
     static constexpr int CT = CB * Cf::TPF;
@@ -83,7 +83,7 @@ template <typename R, bool PADDED, int V>
 const Ops<R>* table() {
     constexpr int ES = (int)sizeof(cplx<R>);
     constexpr int EMAX = variant_emax(ES, V);
-    if constexpr (!fits_lds(MSR_L, PADDED, ES, EMAX)) {
+    if constexpr (!fits_lds(MSR_L, PADDED, ES, EMAX, variant_single_column(V))) {
         return nullptr;
     } else {
         constexpr bool full = MSR_L <= 8192;
