@@ -10,12 +10,16 @@ step 2 (K iterations, cold start).  The reported value is FISTA iterations
 Also reported: the per-step loop rates, time to a 1e-6 relative objective in
 step 2 from a cold start and from warm starts (the low-resolution image, the
 step-1 model, the learned warm start, and the network's own training target
-as the best it could do), the dominant kernel against the HBM roofline (timed
-live with HIP events), the per-PSF setup, the wavelet dictionary, the
+as the best it could do), the dominant pass against its roofline (the FP32
+FMA rate these kernels can reach and HBM; timed live with HIP events), the
+per-PSF setup, the wavelet dictionary, the
 up-sampling of a down-sampled low-resolution image, batched channels, a
 synthetic partition study and the FP64 CPU oracle timed on this host.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--size 4096]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--size 2048|4096|8192]
+
+The default workload is the 4096^2 image; --size 8192 runs the largest one
+(its synthesis takes a minute or more on the host).
 """
 from __future__ import annotations
 
