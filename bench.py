@@ -369,6 +369,9 @@ def main(argv=None):
                          "then exit")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="K",
                     help="profiling aid: set up the workload, autotune, run K iterations of each step and exit")
+    ap.add_argument("--unet-forward", type=int, default=0, metavar="K",
+                    help="only run K forward passes of the warm-start network (random weights) on this workload's "
+                         "image size, for a kernel trace, and exit")
     ap.add_argument("--dictionary-kernels", type=int, default=0, metavar="K",
                     help="profiling aid: set up the workload with the wavelet dictionary, run K iterations of "
                          "each step and exit")
@@ -396,6 +399,23 @@ def main(argv=None):
     s.set_dirty_psf(2, tensors[2], tensors[3])
     sig2 = s.estimate_sigma2(tensors[2])
     s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)  # so that the low-band filter pass is tuned too
+    if args.unet_forward:
+        # weights and inputs only set the values, not the work: random weights,
+        # the long-baseline dirty image and the short-baseline one as the
+        # low-resolution input
+        from paper_2406_18356_amd import UNet, unet_init_params
+
+        net = UNet(1, pr.n)
+        net.set_params(unet_init_params(seed=0))
+        dh1, il1 = tensors[2][None].contiguous(), tensors[0][None].contiguous()
+        net.forward(dh1, il1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.unet_forward):
+            net.forward(dh1, il1)
+        torch.cuda.synchronize()
+        log(f"unet forward {pr.n}^2: {(time.perf_counter() - t) / args.unet_forward * 1e3:.2f} ms")
+        return 0
     if args.dictionary_kernels:
         rep = dictionary_bench(torch, pr, tensors, iters=args.dictionary_kernels)
         log("dictionary kernels:", json.dumps(rep))

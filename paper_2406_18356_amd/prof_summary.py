@@ -43,8 +43,39 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+_MANGLED_ARG = [(r"DF16b", "bf16"), (r"f", "float"), (r"d", "double"), (r"Lb0E", "false"), (r"Lb1E", "true"),
+                (r"Li(\d+)E", r"\1")]
+
+
+def _demangle_local(name: str) -> str:
+    """Names of templates in an anonymous namespace arrive mangled
+    (_ZN12_GLOBAL__N_1<len><name>I<args>E...): keep the name and its simple
+    template arguments (bf16, float, double, bool and int literals)."""
+    m = re.match(r"_ZN12_GLOBAL__N_1(\d+)", name)
+    if not m:
+        return name
+    rest = name[m.end():]
+    k = int(m.group(1))
+    ident, rest = rest[:k], rest[k:]
+    if not rest.startswith("I"):
+        return ident
+    rest, args = rest[1:], []
+    while rest and not rest.startswith("E"):
+        for pat, rep in _MANGLED_ARG:
+            mm = re.match(pat, rest)
+            if mm:
+                args.append(mm.expand(rep))
+                rest = rest[mm.end():]
+                break
+        else:
+            break
+    return f"{ident}<{', '.join(args)}>" if args else ident
+
+
 def _short(name: str) -> str:
-    n = re.sub(r"void msr::", "", name)
+    n = _demangle_local(name)
+    n = n.replace("(anonymous namespace)::", "")
+    n = re.sub(r"void msr::", "", n)
     n = re.sub(r"msr::(RowArgs|ColArgs)<(float|double)>, ", "", n)
     n = re.sub(r"\(.*", "", n)
     return n
