@@ -6,7 +6,7 @@
  * start with a small U-Net from the two images step 2 already has -- the
  * long-baseline dirty image i_H and the low-resolution image l = i_L of step 1
  * (Sect. 3.2) -- and FISTA still runs to the same tolerance from it, so the
- * plain cold start stays both the fallback and the judge.  The network is not
+ * plain cold start stays both the fallback and the reference.  The network is not
  * part of the paper.
  *
  * Network (base width w, L levels; w = 32, L = 4 by default):
