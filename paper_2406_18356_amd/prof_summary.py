@@ -5,6 +5,8 @@
         --kernel SUBSTRING --segment I --bytes ALGORITHMIC_BYTES --command "..."
     python -m paper_2406_18356_amd.prof_summary passes DIR PREFIX OUT.txt --command "..." \
         --pass NAME SUBSTRING I [--pass ...]
+    python -m paper_2406_18356_amd.prof_summary counters DIR PREFIX OUT.txt --command "..." \
+        --pass NAME SUBSTRING I [--pass ...]
 
 ``stats`` condenses ``<PREFIX>_kernel_stats.csv`` (rocprofv3 --kernel-trace
 --stats --output-format csv) into a table.  ``traffic`` reads two --pmc runs
@@ -13,6 +15,10 @@ the largest device-to-device copy in the same run (a copy of B bytes must read
 and write B bytes) and records the scaled per-launch HBM traffic of the kernel
 whose name contains SUBSTRING, with a hash of the kernel sources so that the
 benchmark can tell whether the figure still describes the current code.
+``counters`` reads one --pmc run of SQ_* counters and GRBM_GUI_ACTIVE over the
+same --profile-pass passes and reports, per named pass, instructions per wave
+and the vector-ALU issue share (VALU instructions x 4 cycles over the SIMD
+cycles of the kernel; GRBM_GUI_ACTIVE is summed over the 8 XCDs).
 ``passes`` reads ``<PREFIX>_kernel_trace.csv`` and reports, per named pass, the
 mean duration of the dispatches whose kernel name contains SUBSTRING in
 segment I.  Segments: in a ``bench.py --profile-pass ...`` run every pass is
@@ -154,6 +160,36 @@ def _copy_scale(rows, copy_bytes):
     return copy_bytes / 1024.0 / big, big
 
 
+# MI355X: 256 CUs x 4 SIMDs, 8 XCDs, 2.4 GHz; a wave64 VALU instruction holds a
+# 16-lane SIMD for 4 cycles
+SIMDS, XCDS, CLOCK_GHZ, VALU_CYCLES = 1024, 8, 2.4, 4
+
+
+def counters(d, prefix, out, command, specs):
+    names = ("GRBM_GUI_ACTIVE", "SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+             "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT")
+    per = {n: _per_dispatch(d, prefix, n) for n in names}
+    lines = ["# rocprofv3 SQ counters per pass (mean over the pass's timed dispatches)", f"# command: {command}", "",
+             f"{'pass':18s} {'us':>7s} {'waves':>7s} {'valu/wave':>9s} {'valu_busy':>9s} {'lds/wave':>8s} "
+             f"{'vmem/wave':>9s} {'lds_conflict':>12s}"]
+    for name, sub, seg in specs:
+        v = {}
+        for n in names:
+            ds = _pick(_segments(per[n], "Kernel_Name")[int(seg)], sub, "Kernel_Name")
+            if not ds:
+                raise SystemExit(f"no dispatch matching {sub!r} for {n}")
+            v[n] = sum(r["value"] for r in ds) / len(ds)
+        cyc = v["GRBM_GUI_ACTIVE"] / XCDS
+        waves = max(v["SQ_WAVES"], 1.0)
+        busy = v["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * cyc)
+        conflict = v["SQ_LDS_BANK_CONFLICT"] / max(v["SQ_ACTIVE_INST_LDS"], 1.0)
+        lines.append(f"{name:18s} {cyc / (CLOCK_GHZ * 1e3):7.1f} {waves:7.0f} {v['SQ_INSTS_VALU'] / waves:9.0f} "
+                     f"{busy:9.2f} {v['SQ_INSTS_LDS'] / waves:8.0f} "
+                     f"{(v['SQ_INSTS_VMEM_RD'] + v['SQ_INSTS_VMEM_WR']) / waves:9.1f} {conflict:12.2f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    return out
+
+
 def traffic(d, fprefix, wprefix, out, kernel, alg_bytes, copy_bytes, command, segment):
     fr = _per_dispatch(d, fprefix, "FETCH_SIZE")
     wr = _per_dispatch(d, wprefix, "WRITE_SIZE")
@@ -202,8 +238,17 @@ def main(argv=None):
     q.add_argument("--command", required=True)
     q.add_argument("--pass", dest="specs", nargs=3, action="append", required=True,
                    metavar=("NAME", "SUBSTRING", "SEGMENT"))
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("prefix")
+    c.add_argument("out")
+    c.add_argument("--command", required=True)
+    c.add_argument("--pass", dest="specs", nargs=3, action="append", required=True,
+                   metavar=("NAME", "SUBSTRING", "SEGMENT"))
     a = ap.parse_args(argv)
-    if a.cmd == "stats":
+    if a.cmd == "counters":
+        print(counters(a.dir, a.prefix, a.out, a.command, a.specs))
+    elif a.cmd == "stats":
         print(stats(a.dir, a.prefix, a.out, a.command))
     elif a.cmd == "passes":
         print(passes(a.dir, a.prefix, a.out, a.command, a.specs))
