@@ -121,3 +121,77 @@ def test_major_cycles_with_dictionary_pins():
     # lambda -> 0, H = I: FISTA on ||y - W alpha||^2 drives W alpha to y
     _, m0, _ = twostep.major_cycles(1, pr.dirty_L, dpsf, 1, 400, c=0.0, theta=16.0 * 1.01, dictionary=True)
     np.testing.assert_allclose(m0, pr.dirty_L, atol=1e-8 * np.abs(pr.dirty_L).max())
+
+
+def _soft(z, t):
+    """sign(z) max(|z| - t, 0), written out element by element."""
+    out = np.zeros_like(z)
+    for idx, v in np.ndenumerate(z):
+        out[idx] = (v - t) if v > t else ((v + t) if v < -t else 0.0)
+    return out
+
+
+def _delta_psf(P):
+    d = np.zeros((P, P))
+    d[P // 2, P // 2] = 1.0
+    return d
+
+
+@pytest.mark.parametrize("positivity", [False, True])
+def test_major_cycles_step1_closed_form(positivity):
+    """Cycles n >= 2 of step 1 in closed form (Sect. 3.2, Sect. 5 / App. A.2).
+
+    With a delta PSF, H = I and f(x) = ||i~ - x||^2, so theta = 2 gives
+    mu = 1/2 and the first prox step lands on the minimiser
+    tau_{lambda/2}(i~) (positive part with positivity); the momentum term is
+    then zero for ever, so every cycle's FISTA result is exact after any K.
+    Cycle n therefore gives i_n = tau_{lambda_n/2}(i~_n) with
+    i~_n = i~_1 - sum_{j<n} i_j and lambda_n = c ||i~_n|| 2^(n-1); the
+    recursion below is run independently of the oracle's operators."""
+    pr = synth.make_problem(tiny(16, seed=3))
+    c = 0.02
+    y = pr.dirty_L
+    msum = np.zeros_like(y)
+    lams, parts = [], []
+    for n in range(1, 4):
+        resid = y - msum
+        lam = c * np.sqrt(np.sum(resid * resid)) * 2.0 ** (n - 1)
+        i_n = np.maximum(resid - lam / 2, 0.0) if positivity else _soft(resid, lam / 2)
+        lams.append(lam)
+        parts.append(i_n)
+        msum = msum + i_n
+    # every later cycle does something, else the pin would not see its bookkeeping
+    assert all(np.abs(p).max() > 1e-3 * np.abs(y).max() for p in parts[1:])
+    img, got, recs = twostep.major_cycles(1, y, _delta_psf(pr.P), 3, 3, c=c, theta=2.0, positivity=positivity)
+    np.testing.assert_allclose(got, msum, atol=1e-13 * np.abs(y).max())
+    np.testing.assert_allclose([r["lambda"] for r in recs], lams, rtol=1e-13)
+    np.testing.assert_allclose(img, y, atol=1e-13 * np.abs(y).max())
+
+
+def test_major_cycles_step2_closed_form():
+    """Cycles n >= 2 of step 2 in closed form (Eq. 5's l_{L_n}, Sect. 3.3).
+
+    With a delta PSF, sigma^2 = eta^2 = 1 (so g_H^2 + g_L^2 = 1 everywhere,
+    Eqs. 6-10) and the data image equal to the constraint l, the data
+    residual of cycle n and its constraint l_n = l - sum_{j<n} i_j are the
+    same image, grad f = 2 E^T C_{g_H^2 + g_L^2} E (x - l_n) = 2 (x - l_n), and
+    theta = 2 makes one prox step exact: i_n = tau_{lambda_n/2}(l - sum_{j<n} i_j)
+    with lambda_n = c ||l - sum_{j<n} i_j|| 2^(n-1).  A constraint left at l
+    (not l_n) pulls every later cycle towards l and fails this."""
+    pr = synth.make_problem(tiny(16, seed=5))
+    c = 0.02
+    l = pr.dirty_H.copy()
+    msum = np.zeros_like(l)
+    lams, parts = [], []
+    for n in range(1, 4):
+        resid = l - msum
+        lam = c * np.sqrt(np.sum(resid * resid)) * 2.0 ** (n - 1)
+        i_n = _soft(resid, lam / 2)
+        lams.append(lam)
+        parts.append(i_n)
+        msum = msum + i_n
+    assert all(np.abs(p).max() > 1e-3 * np.abs(l).max() for p in parts[1:])
+    img, got, recs = twostep.major_cycles(2, l, _delta_psf(pr.P), 3, 3, c=c, theta=2.0, low_res=l,
+                                          ell=pr.ell, delta=pr.delta, sigma2=1.0, eta2=1.0)
+    np.testing.assert_allclose(got, msum, atol=1e-12 * np.abs(l).max())
+    np.testing.assert_allclose([r["lambda"] for r in recs], lams, rtol=1e-13)
