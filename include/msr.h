@@ -34,7 +34,9 @@
  *     N <= 8192 circular).
  *   - All device memory the library uses is one workspace the caller
  *     allocates (size from msr_workspace_bytes) and hands over with
- *     msr_set_workspace; the library itself never allocates device memory.
+ *     msr_set_workspace, or the library's static array of
+ *     MSR_STATIC_WORKSPACE_BYTES per device (msr_set_workspace_static, for
+ *     small images); the library itself never allocates device memory.
  *   - Work is ordered on the caller's HIP stream (hipStream_t passed as
  *     void*; NULL is the default stream).  Calls that return scalars
  *     synchronise that stream before returning.
@@ -118,6 +120,32 @@ size_t msr_workspace_bytes(const msr_config* cfg);
  * msr_workspace_bytes bytes, 256-byte aligned, and must outlive the context's
  * use of it.  Invalidates everything computed before. */
 msr_status msr_set_workspace(msr_ctx* ctx, void* dev, size_t bytes);
+
+/* Size of the static workspace of msr_set_workspace_static: 32 MiB, enough
+ * for N <= 512 in single precision and N <= 256 in double precision (zero
+ * padded, W = I; msr_workspace_bytes gives the exact need). */
+#define MSR_STATIC_WORKSPACE_BYTES ((size_t)32 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * msr_set_workspace, with the workspace taken from a static device array of
+ * MSR_STATIC_WORKSPACE_BYTES that the library holds on each device from the
+ * loading of its device code until the process ends.  Allocates nothing (no
+ * hipMalloc, hipFree or allocating library call); the caller still passes
+ * every input and output to the later calls, which run unchanged on that
+ * array.  Returns MSR_ERR_OOM, with the two sizes in msr_last_error, if
+ * msr_workspace_bytes for the context's configuration exceeds
+ * MSR_STATIC_WORKSPACE_BYTES; MSR_ERR_HIP if the array's device address
+ * cannot be looked up.
+ * Sharing: all contexts on one device share its one array.  Binding a
+ * context takes the array from the context bound before it, whose later
+ * calls then fail with MSR_ERR_STATE until it is given a workspace again;
+ * calls of contexts on one device that overlap in time race (do not bind a
+ * second context while work of the first is still queued).  The array keeps
+ * the last call's contents; nothing in it has to start at zero (every buffer
+ * is written before it is read, as in a freshly allocated caller workspace).
+ * Invalidates everything computed before, as msr_set_workspace does. */
+msr_status msr_set_workspace_static(msr_ctx* ctx);
 
 /* Sets the dirty image i_s and the PSF of step s (1 = short baselines, L;
  * 2 = long baselines, H) -- the inputs of Eq. 4 / Eq. 5.  Computes and caches

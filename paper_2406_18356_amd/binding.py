@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libmsr.so"
 
 OK, ERR_INVALID, ERR_OOM, ERR_HIP, ERR_STATE, ERR_NUMERIC, ERR_UNSUPPORTED = range(7)
+# MSR_STATIC_WORKSPACE_BYTES of include/msr.h: the static workspace of msr_set_workspace_static
+STATIC_WORKSPACE_BYTES = 32 << 20
 _STATUS = {0: "OK", 1: "INVALID", 2: "OOM", 3: "HIP", 4: "STATE", 5: "NUMERIC", 6: "UNSUPPORTED"}
 
 
@@ -82,6 +84,7 @@ SYMBOLS = {
     "msr_last_error": (C.c_char_p, [_P]),
     "msr_workspace_bytes": (C.c_size_t, [C.POINTER(Config)]),
     "msr_set_workspace": (_ST, [_P, _P, C.c_size_t]),
+    "msr_set_workspace_static": (_ST, [_P]),
     "msr_set_dirty_psf": (_ST, [_P, C.c_int, _P, _P, _P]),
     "msr_set_filters": (_ST, [_P, C.c_double, C.c_double, C.c_double, C.c_double]),
     "msr_lipschitz": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int), _P]),
@@ -188,10 +191,15 @@ class Solver:
     >>> beta1, i_L, r1 = s.step1(lam1, iters=200, image=True)
     >>> s.set_filters(ell, delta, sigma2, eta2)
     >>> beta2, r2 = s.step2(lam2, i_L, iters=200)
+
+    ``static_workspace=True`` takes the library's static device array
+    (msr_set_workspace_static: no allocation, images up to 512^2 in float32)
+    instead of a torch-allocated workspace.
     """
 
     def __init__(self, n: int, pad: int = 2, positivity: bool = False, device: int = 0, seed: int = 0,
-                 prune_tol: float = 1e-6, precision: int = 32, dictionary: int = 0, _borrowed=None):
+                 prune_tol: float = 1e-6, precision: int = 32, dictionary: int = 0, static_workspace: bool = False,
+                 _borrowed=None):
         import torch
 
         self._lib = lib()
@@ -215,12 +223,17 @@ class Solver:
             raise MsrError(st, "msr_init rejected the configuration")
         self._h = h
         nbytes = int(self._lib.msr_workspace_bytes(C.byref(cfg)))
+        self.workspace_bytes = nbytes
+        if static_workspace:
+            # the library's static array on this device (msr_set_workspace_static)
+            self._ws = None
+            self._check(self._lib.msr_set_workspace_static(self._h))
+            return
         # 256-byte aligned workspace owned by torch
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         aligned = (base + 255) // 256 * 256
         self._check(self._lib.msr_set_workspace(self._h, C.c_void_p(aligned), nbytes))
-        self.workspace_bytes = nbytes
 
     def __del__(self):
         h = getattr(self, "_h", None)

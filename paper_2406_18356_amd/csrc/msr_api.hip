@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,39 @@ const Ops<float>* ops_for_f32(int L, bool padded, int variant) { MSR_CASES(ops_l
 const Ops<double>* ops_for_f64(int L, bool padded, int variant) { MSR_CASES(ops_len_f64_) }
 #undef MSR_CASES
 }  // namespace msr
+
+// The workspace of msr_set_workspace_static: one array per device, held from
+// the loading of this library's device code until the process ends.  Host
+// code never uses the name `scratch` as an address (in host code it stands
+// for a host-side shadow); it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device below.
+static __device__ __align__(256) char scratch[MSR_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct StaticWorkspace {
+    void* ptr = nullptr;          // device address of `scratch` on this device
+    unsigned long long gen = 0;   // bumped whenever a context binds the array
+};
+StaticWorkspace g_static[kMaxDevices];
+std::mutex g_static_mu;
+
+// Looks up the device address of `scratch` on `dev` once; `dev` must be the
+// current device.  Returns hipSuccess and sets *out, or the lookup's error.
+hipError_t static_workspace_ptr(int dev, void** out) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_static[dev].ptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_static[dev].ptr = p;
+    }
+    *out = g_static[dev].ptr;
+    return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -293,6 +327,11 @@ struct msr_ctx {
     Layout lay{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    // bound to the static workspace of its device (msr_set_workspace_static) at
+    // binding number ws_gen; a later binding by another context takes it away
+    bool ws_static = false;
+    unsigned long long ws_gen = 0;
+    bool ws_lost = false;  // the static workspace was bound by another context since
     // state
     int K[2] = {0, 0};  // kept columns per PSF
     bool have_psf[2] = {false, false};
@@ -1485,10 +1524,28 @@ msr_status with_impl(msr_ctx* c, F&& f) {
     return f(im);
 }
 
-bool ready(msr_ctx* c) { return c && c->ws; }
+// True when the context has a workspace it still owns: a caller workspace,
+// or the static workspace of its device not rebound by another context since.
+bool ready(msr_ctx* c) {
+    if (!c || !c->ws) return false;
+    if (!c->ws_static) return true;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static[c->cfg.device].gen == c->ws_gen) return true;
+    c->ws = nullptr;  // another context took the array: this one has none now
+    c->ws_static = false;
+    c->ws_lost = true;
+    return false;
+}
+
+// The error of a call that found no workspace.
+msr_status ws_missing(msr_ctx* c) {
+    if (c && c->ws_lost)
+        return fail(c, MSR_ERR_STATE, "the static workspace of device %d was bound by another context since", c->cfg.device);
+    return fail(c, MSR_ERR_OOM, "no workspace");
+}
 
 msr_status check_step(msr_ctx* c, int step, bool need_filters_for_2) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
     if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
     if (need_filters_for_2 && step == 2 && !c->have_filters) return fail(c, MSR_ERR_STATE, "set_filters first");
@@ -1522,6 +1579,12 @@ msr_status msr_init(const msr_config* cfg, msr_ctx** out) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return MSR_ERR_INVALID;
     if (hipSetDevice(cfg->device) != hipSuccess) return MSR_ERR_HIP;
+    {
+        // the static workspace's device address, once per device (an error is
+        // reported by msr_set_workspace_static, which looks it up again)
+        void* p = nullptr;
+        (void)static_workspace_ptr(cfg->device, &p);
+    }
     msr_ctx* c = new (std::nothrow) msr_ctx();
     if (!c) return MSR_ERR_OOM;
     c->cfg = *cfg;
@@ -1535,13 +1598,17 @@ void msr_destroy(msr_ctx* ctx) { delete ctx; }
 
 const char* msr_last_error(const msr_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-msr_status msr_set_workspace(msr_ctx* c, void* dev, size_t bytes) {
-    if (!c) return MSR_ERR_INVALID;
-    if (!dev || bytes < c->lay.total) return fail(c, MSR_ERR_OOM, "workspace needs %zu bytes", c->lay.total);
-    if (reinterpret_cast<uintptr_t>(dev) % kAlign) return fail(c, MSR_ERR_INVALID, "workspace must be 256-byte aligned");
-    HIPCHK(c, hipSetDevice(c->cfg.device));
+}  // extern "C"
+
+namespace {
+// Binds dev (device memory of `bytes` bytes on the context's device, which is
+// current) as the context's workspace and fills its constant tables.
+msr_status bind_workspace(msr_ctx* c, void* dev, size_t bytes, bool is_static, unsigned long long gen) {
     c->ws = static_cast<char*>(dev);
     c->ws_bytes = bytes;
+    c->ws_static = is_static;
+    c->ws_gen = gen;
+    c->ws_lost = false;
     c->have_psf[0] = c->have_psf[1] = false;
     c->have_theta[0] = c->have_theta[1] = false;
     c->have_filters = false;
@@ -1549,9 +1616,38 @@ msr_status msr_set_workspace(msr_ctx* c, void* dev, size_t bytes) {
     c->resume_k[0] = c->resume_k[1] = -1;
     return with_impl(c, [](auto& im) { return im.set_workspace(); });
 }
+}  // namespace
+
+extern "C" {
+
+msr_status msr_set_workspace(msr_ctx* c, void* dev, size_t bytes) {
+    if (!c) return MSR_ERR_INVALID;
+    if (!dev || bytes < c->lay.total) return fail(c, MSR_ERR_OOM, "workspace needs %zu bytes", c->lay.total);
+    if (reinterpret_cast<uintptr_t>(dev) % kAlign) return fail(c, MSR_ERR_INVALID, "workspace must be 256-byte aligned");
+    HIPCHK(c, hipSetDevice(c->cfg.device));
+    return bind_workspace(c, dev, bytes, false, 0);
+}
+
+msr_status msr_set_workspace_static(msr_ctx* c) {
+    if (!c) return MSR_ERR_INVALID;
+    if (c->lay.total > (size_t)MSR_STATIC_WORKSPACE_BYTES)
+        return fail(c, MSR_ERR_OOM, "this configuration needs %zu bytes of workspace; the static workspace holds %zu",
+                    c->lay.total, (size_t)MSR_STATIC_WORKSPACE_BYTES);
+    if (c->cfg.device >= kMaxDevices) return fail(c, MSR_ERR_INVALID, "device ordinal above %d", kMaxDevices - 1);
+    HIPCHK(c, hipSetDevice(c->cfg.device));
+    void* p = nullptr;
+    const hipError_t e = static_workspace_ptr(c->cfg.device, &p);
+    if (e != hipSuccess) return fail(c, MSR_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    unsigned long long gen;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        gen = ++g_static[c->cfg.device].gen;
+    }
+    return bind_workspace(c, p, (size_t)MSR_STATIC_WORKSPACE_BYTES, true, gen);
+}
 
 msr_status msr_set_dirty_psf(msr_ctx* c, int step, const void* dirty, const void* psf, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
     if (!dirty || !psf) return fail(c, MSR_ERR_INVALID, "null image");
     HIPCHK(c, hipSetDevice(c->cfg.device));
@@ -1603,7 +1699,7 @@ msr_status msr_set_lipschitz(msr_ctx* c, int step, double theta) {
 
 static msr_status solve_entry(msr_ctx* c, int step, const msr_solve* opt, const void* low_res, const void* x0,
                               void* model_out, void* image_out, msr_result* res, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (!opt || !model_out) return fail(c, MSR_ERR_INVALID, "null argument");
     if (!c->have_psf[step - 1]) return fail(c, MSR_ERR_STATE, "set_dirty_psf(%d) first", step);
     if (step == 2 && (!c->have_filters || !low_res)) return fail(c, MSR_ERR_STATE, "step 2 needs filters and low_res");
@@ -1679,7 +1775,7 @@ msr_status msr_get_spectrum(msr_ctx* c, int step, double* host_out, int* kept, v
 }
 
 msr_status msr_estimate_sigma2(msr_ctx* c, const void* dirty, double* sigma2, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (!dirty || !sigma2) return fail(c, MSR_ERR_INVALID, "bad arguments");
     HIPCHK(c, hipSetDevice(c->cfg.device));
     return with_impl(c, [&](auto& im) {
@@ -1709,7 +1805,7 @@ msr_status msr_autotune(msr_ctx* c, int reps, int* row_variant, int* col_variant
 }
 
 msr_status msr_get_state(msr_ctx* c, int step, void* beta_k, void* beta_km1, int* k, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
     if (!beta_k || !beta_km1) return fail(c, MSR_ERR_INVALID, "null argument");
     if (c->state_step != step) return fail(c, MSR_ERR_STATE, "no iterates of step %d in the workspace", step);
@@ -1728,7 +1824,7 @@ msr_status msr_get_state(msr_ctx* c, int step, void* beta_k, void* beta_km1, int
 }
 
 msr_status msr_set_state(msr_ctx* c, int step, const void* beta_k, const void* beta_km1, int k, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
     if (!beta_k || !beta_km1 || k < 0) return fail(c, MSR_ERR_INVALID, "bad arguments");
     HIPCHK(c, hipSetDevice(c->cfg.device));
@@ -1747,7 +1843,7 @@ msr_status msr_set_state(msr_ctx* c, int step, const void* beta_k, const void* b
 }
 
 msr_status msr_upsample(msr_ctx* c, int factor, const void* small, void* out, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (factor < 2 || (factor & (factor - 1)) || c->sh.N / factor < 2)
         return fail(c, MSR_ERR_INVALID, "factor must be a power of two with N / factor >= 2");
     if (!small || !out || small == out) return fail(c, MSR_ERR_INVALID, "bad arguments");
@@ -1759,7 +1855,7 @@ msr_status msr_upsample(msr_ctx* c, int factor, const void* small, void* out, vo
 }
 
 msr_status msr_dictionary_synthesis(msr_ctx* c, const void* coeffs, void* image, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (!c->sh.dict) return fail(c, MSR_ERR_STATE, "the context has no dictionary");
     if (!coeffs || !image) return fail(c, MSR_ERR_INVALID, "bad arguments");
     HIPCHK(c, hipSetDevice(c->cfg.device));
@@ -1772,7 +1868,7 @@ msr_status msr_dictionary_synthesis(msr_ctx* c, const void* coeffs, void* image,
 }
 
 msr_status msr_dictionary_analysis(msr_ctx* c, const void* image, void* coeffs, void* stream) {
-    if (!ready(c)) return fail(c, MSR_ERR_OOM, "no workspace");
+    if (!ready(c)) return ws_missing(c);
     if (!c->sh.dict) return fail(c, MSR_ERR_STATE, "the context has no dictionary");
     if (!coeffs || !image) return fail(c, MSR_ERR_INVALID, "bad arguments");
     HIPCHK(c, hipSetDevice(c->cfg.device));

@@ -134,3 +134,17 @@ def test_unet_sizes_host_only(lib):
     h = C.c_void_p(1)
     assert lib.msr_unet_init(C.byref(binding.UNetConfig(2, 12, 4, 0)), C.byref(h)) == binding.ERR_INVALID
     assert lib.msr_unet_last_error(None) == b"null network"
+
+
+def test_static_workspace_size_host_only(lib):
+    """The Python constant is the header's MSR_STATIC_WORKSPACE_BYTES, and the
+    sizes it covers are the ones the header states (N <= 512 in float32,
+    N <= 256 in float64, zero padded)."""
+    from paper_2406_18356_amd import binding
+
+    txt = open(HEADER).read()
+    m = re.search(r"#define MSR_STATIC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == binding.STATIC_WORKSPACE_BYTES
+    cap = binding.STATIC_WORKSPACE_BYTES
+    assert binding.workspace_bytes(512) <= cap < binding.workspace_bytes(1024)
+    assert binding.workspace_bytes(256, precision=64) <= cap < binding.workspace_bytes(512, precision=64)
