@@ -298,6 +298,20 @@ msr_status msr_default_lambda(msr_ctx* ctx, int step, int cycle, double c, doubl
 msr_status msr_autotune(msr_ctx* ctx, int reps, int* row_variant, int* col_variant, double* times_ms,
                         void* stream);
 
+/* Kernel variants of a step's passes, as msr_autotune chooses them (variant
+ * v: v = 0 large E, whole column tiles; 1 small E, whole tiles; 2 small E,
+ * single columns; 3 large E, single columns; E = complex values per thread of
+ * a transform).  msr_set_variants selects them explicitly: row_variant for
+ * the row passes, col_variant for the column PSF passes and filter_variant
+ * for the step-2 low-band filter pass (-1: the column pass's variant; step 1
+ * takes -1).  Results do not depend on the variant beyond rounding order.
+ * MSR_ERR_UNSUPPORTED if a variant is not built for this image size (its
+ * LDS footprint does not fit), MSR_ERR_INVALID for a bad step or number.
+ * msr_get_variants reports the current choice (filter_variant -1 for
+ * step 1). */
+msr_status msr_set_variants(msr_ctx* ctx, int step, int row_variant, int col_variant, int filter_variant);
+msr_status msr_get_variants(msr_ctx* ctx, int step, int* row_variant, int* col_variant, int* filter_variant);
+
 /* Runs one kernel of an iteration of step s `reps` times back to back on
  * `stream` (on the context's current state, which it overwrites: call it
  * outside a solve) and returns its mean device time in milliseconds, plus the

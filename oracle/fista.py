@@ -55,3 +55,23 @@ def fista(grad, x0, mu, lam, iters, positivity=False, momentum_on=True, callback
         if callback is not None:
             callback(k, beta)
     return beta, alpha
+
+
+def fista_from(grad, beta_k, beta_km1, k, mu, lam, iters, positivity=False, dtype=np.float64):
+    """Algorithm 1 continued from iteration k: given beta_k and beta_{k-1},
+    alpha_k = beta_k + (k-1)/(k+2) (beta_k - beta_{k-1}), then the same prox
+    and momentum steps for k+1 .. k+iters.  Returns (beta_{k+iters},
+    beta_{k+iters-1}, alpha_{k+iters}).  With beta_k = beta_{k-1} = x0 and
+    k = 0 it is ``fista`` from x0."""
+    dt = np.dtype(dtype)
+    beta = np.asarray(beta_k, dtype=dt).copy()
+    beta_prev = np.asarray(beta_km1, dtype=dt).copy()
+    alpha = beta + dt.type(momentum(k) if k >= 1 else 0.0) * (beta - beta_prev)
+    t = dt.type(mu * lam)
+    mu_ = dt.type(mu)
+    for j in range(k + 1, k + iters + 1):
+        z = alpha - mu_ * grad(alpha)
+        new = prox(z, t, positivity).astype(dt)
+        alpha = new + dt.type(momentum(j)) * (new - beta)
+        beta_prev, beta = beta, new
+    return beta, beta_prev, alpha

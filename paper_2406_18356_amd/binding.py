@@ -106,6 +106,8 @@ SYMBOLS = {
     "msr_time_pass": (_ST, [_P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                             C.POINTER(C.c_double), _P]),
     "msr_autotune": (_ST, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double), _P]),
+    "msr_set_variants": (_ST, [_P, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "msr_get_variants": (_ST, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "msr_batch_workspace_bytes": (C.c_size_t, [C.c_int, C.POINTER(Config)]),
     "msr_batch_init": (_ST, [C.c_int, C.POINTER(Config), C.POINTER(_P)]),
     "msr_batch_destroy": (None, [_P]),
@@ -381,6 +383,16 @@ class Solver:
         self._check(self._lib.msr_autotune(self._h, reps, C.byref(vr), C.byref(vc), t, _stream(stream)))
         times = {v: (t[2 * v], t[2 * v + 1]) for v in range(4) if t[2 * v] >= 0}
         return vr.value, vc.value, times
+
+    def set_variants(self, step, row, col, filt=-1):
+        """Selects the kernel variants of a step's passes (msr_set_variants)."""
+        self._check(self._lib.msr_set_variants(self._h, int(step), int(row), int(col), int(filt)))
+
+    def get_variants(self, step):
+        """(row, column, filter) variants of a step's passes (msr_get_variants)."""
+        r, c_, f = C.c_int(), C.c_int(), C.c_int()
+        self._check(self._lib.msr_get_variants(self._h, int(step), C.byref(r), C.byref(c_), C.byref(f)))
+        return r.value, c_.value, f.value
 
     def time_pass(self, which, reps=20, step=1, stream=None):
         """(mean ms, algorithmic bytes, algorithmic flops) of one pass launch."""

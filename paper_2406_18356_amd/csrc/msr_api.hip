@@ -1880,6 +1880,36 @@ msr_status msr_dictionary_analysis(msr_ctx* c, const void* image, void* coeffs, 
     });
 }
 
+msr_status msr_set_variants(msr_ctx* c, int step, int row_variant, int col_variant, int filter_variant) {
+    if (!c) return MSR_ERR_INVALID;
+    if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
+    if (step == 1 && filter_variant != -1) return fail(c, MSR_ERR_INVALID, "step 1 has no filter pass");
+    const int want[3] = {row_variant, col_variant, filter_variant};
+    for (int i = 0; i < 3; ++i) {
+        const int v = want[i];
+        if (i == 2 && v == -1) continue;
+        if (v < 0 || v >= kVariants) return fail(c, MSR_ERR_INVALID, "variant %d out of range", v);
+        const bool built = c->sh.prec == 64 ? (ops_for<double>(c->sh.N, c->sh.padded, v) &&
+                                                ops_for<double>(c->sh.N, c->sh.padded, v)->row_update_fwd)
+                                             : (ops_for<float>(c->sh.N, c->sh.padded, v) &&
+                                                ops_for<float>(c->sh.N, c->sh.padded, v)->row_update_fwd);
+        if (!built) return fail(c, MSR_ERR_UNSUPPORTED, "variant %d is not built for n = %d", v, c->sh.N);
+    }
+    c->var_row[step - 1] = row_variant;
+    c->var_col[step - 1] = col_variant;
+    if (step == 2) c->var_filt = filter_variant;
+    return MSR_OK;
+}
+
+msr_status msr_get_variants(msr_ctx* c, int step, int* row_variant, int* col_variant, int* filter_variant) {
+    if (!c) return MSR_ERR_INVALID;
+    if (step != 1 && step != 2) return fail(c, MSR_ERR_INVALID, "step must be 1 or 2");
+    if (row_variant) *row_variant = c->var_row[step - 1];
+    if (col_variant) *col_variant = c->var_col[step - 1];
+    if (filter_variant) *filter_variant = step == 2 ? c->var_filt : -1;
+    return MSR_OK;
+}
+
 msr_status msr_time_pass(msr_ctx* c, int step, int which, int reps, double* ms_out, double* bytes_out,
                          double* flops_out, void* stream) {
     TRY(check_step(c, step, true));

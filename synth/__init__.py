@@ -29,6 +29,7 @@ from .generator import (
     channel_set,
     sky_set,
     coarse_low,
+    late_state,
 )
 
 __all__ = [
@@ -48,4 +49,5 @@ __all__ = [
     "channel_set",
     "sky_set",
     "coarse_low",
+    "late_state",
 ]

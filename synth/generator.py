@@ -407,6 +407,25 @@ def channel_set(count: int, sizes=(512, 1024, 2048, 4096), seed: int = 4, cut: f
     return out
 
 
+def late_state(n: int, seed: int = 0, scale: float = 1e-2, change: float = 0.02):
+    """Two non-negative N x N images (b_k, b_km1) shaped like late iterates of a
+    sparse reconstruction: b_k holds point sources and Gaussians of the small
+    preset's density times `scale`; b_km1 differs from it by a relative
+    change of up to `change` on every non-zero pixel and by a few isolated
+    pixels present in only one of the two.  Inputs only, no solver arithmetic.
+    """
+    rng = np.random.default_rng(seed)
+    dens = (n / 256.0) ** 2
+    sky = make_sky(n, SkyConfig(max(2, int(20 * dens)), max(1, int(3 * dens))), rng)
+    b_k = scale * sky
+    b_km1 = b_k * (1.0 - change * rng.random((n, n)))
+    m = max(4, n // 16)
+    idx = rng.integers(0, n, (m, 2))
+    b_km1[idx[: m // 2, 0], idx[: m // 2, 1]] += scale * rng.random(m // 2)
+    b_k[idx[m // 2:, 0], idx[m // 2:, 1]] += scale * rng.random(m - m // 2)
+    return b_k, b_km1
+
+
 def tiny(n: int, seed: int = 11, cut: float = 0.25, n_ant: int = 16) -> ProblemConfig:
     """A small problem for tests: density ~ that of the small preset."""
     pts = max(2, (20 * n * n) // (256 * 256))
