@@ -2,6 +2,9 @@
 the host API, one shared library next to this file.
 
     python -m paper_2406_18356_amd.build [--jobs J]
+
+MSR_HIPCC_FLAGS (environment) adds hipcc flags, e.g. kernel switches such
+as -DMSR_TW_PRELOAD_INV=1; MSR_OFFLOAD_ARCH overrides gfx950.
 """
 from __future__ import annotations
 
@@ -26,6 +29,8 @@ CXXFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+# extra hipcc flags for experiments (e.g. -DMSR_ROW_PINGPONG=0), space separated
+CXXFLAGS += os.environ.get("MSR_HIPCC_FLAGS", "").split()
 
 
 def hipcc() -> str:

@@ -134,17 +134,70 @@ __device__ __forceinline__ void dft(C (&x)[RD]) {
     for (int i = 0; i < RD; ++i) x[i] = y[i];
 }
 
-// LDS view of one transform's data: element p lives at base[(p + p/16) * S + c]
-// (one pad slot every 16 elements breaks the power-of-two strides of the
-// Stockham writes; S interleaves several columns).
+// LDS view of one transform's data, S columns interleaved: slot q of column c
+// is base[q * S + c].  Element p of a line goes to slot p + p/16 when the
+// line is staged (operator[]: one pad slot every 16 elements), and to slot
+// p + A (p >> SH) in the exchange after FFT stage NS, with (A, SH) chosen per
+// stage (stage_pad) so that the stage's strided writes and the contiguous
+// reads that follow hit distinct LDS banks.
 template <int S, typename C>
 struct LdsView {
     C* base;
     int c;
     __device__ __forceinline__ C& operator[](int p) const { return base[(p + (p >> 4)) * S + c]; }
+    __device__ __forceinline__ C& slot(int q) const { return base[q * S + c]; }
 };
 
 __host__ __device__ constexpr int padded_len(int L) { return L + L / 16; }
+
+// Padding of the exchange after stage NS (radix RD) of a transform whose LDS
+// view interleaves S columns: element p at slot p + A (p >> SH).  The LDS has
+// 32 banks of 4 bytes, so a 64-lane access of 8-byte elements is served 16
+// lanes at a time, and 16 lanes must hit 16 distinct 8-byte bank pairs.
+// Reads (element t + m TPF, consecutive over lanes) do so under each padding
+// below.  The writes of stage NS put lane j at
+//   (j / NS) NS RD + j % NS + r NS:
+// for NS >= 16 the lanes of a 16-group stay consecutive (no pad needed); for
+// NS = 1 they are RD apart and a stride of one extra slot per 16 (or per 8
+// when two or four columns interleave) separates them; for NS = 8 (RD = 8)
+// the two 8-lane groups are 64 apart and need 2 extra slots per 16; for
+// NS = 4 (RD = 4) four groups 16 apart need 4 per 16.  Every (L, E, S) the
+// library builds was checked against this bank model.
+struct LdsPad {
+    int A, SH;
+};
+__host__ __device__ constexpr LdsPad stage_pad(int NS, int RD, int S) {
+    if (NS >= 16) return LdsPad{0, 4};
+    if (NS == 1) {
+        if (RD >= 16 || S == 1) return LdsPad{1, 4};
+        if (S >= 4 && RD <= 4) return LdsPad{1, 2};
+        return LdsPad{1, 3};
+    }
+    if (NS == 8) return S == 1 ? LdsPad{2, 4} : LdsPad{0, 4};
+    if (NS == 4) return S == 1 ? LdsPad{4, 4} : (S == 2 ? LdsPad{2, 3} : LdsPad{0, 4});
+    return LdsPad{1, 4};
+}
+template <int A, int SH>
+__host__ __device__ constexpr int pad_slot(int p) {
+    return p + A * (p >> SH);
+}
+__host__ __device__ constexpr int pad_slot_rt(int p, LdsPad q) { return p + q.A * (p >> q.SH); }
+
+// Slots one transform's LDS view needs: the largest padded index over the
+// exchanges of a length-L, E-per-thread transform with S interleaved
+// columns, plus one (at least L).
+__host__ __device__ constexpr int fft_lds_len(int L, int E, int S) {
+    int n = L;
+    for (int NS = 1; NS < L;) {
+        const int RD = (L / NS) >= E ? E : (L / NS);
+        if (NS * RD < L) {
+            const int m = pad_slot_rt(L - 1, stage_pad(NS, RD, S)) + 1;
+            if (m > n) n = m;
+        }
+        NS *= RD;
+    }
+    return n;
+}
 
 // Elements per thread for a transform of length L when at most EMAX are wanted.
 __host__ __device__ constexpr int elems_per_thread(int L, int EMAX) { return L >= EMAX ? EMAX : L; }
@@ -175,21 +228,71 @@ __host__ __device__ constexpr int stage_tables_offset(int L, int E) {
 }
 __host__ __device__ constexpr int stage_tables_len(int L) { return stage_tables_offset(L, 32); }
 
+__host__ __device__ constexpr int ilog2(int x) {
+    int r = 0;
+    while ((2 << r) <= x) ++r;
+    return r;
+}
+
+// Twiddle rows a thread needs, in registers.  Stage NS (> 1) reads, for each
+// of its NB = E / RD butterflies, the log2(RD) table entries w^1, w^2, w^4
+// (and w^8); the entries of all stages are loaded at the start of a
+// transform so their global-memory latency overlaps the first stage instead
+// of stalling every stage after its barrier.  pre[] index of stage NS:
+// tw_pre_offset(L, E, NS) + b log2(RD) + lg.
+__host__ __device__ constexpr int tw_pre_offset(int L, int E, int NSq) {
+    int off = 0;
+    for (int NS = 1; NS < L && NS < NSq; NS *= stage_radix(L, E, NS))
+        if (NS > 1) off += (E / stage_radix(L, E, NS)) * ilog2(stage_radix(L, E, NS));
+    return off;
+}
+__host__ __device__ constexpr int tw_pre_count(int L, int E) {
+    const int n = tw_pre_offset(L, E, L);
+    return n > 0 ? n : 1;
+}
+
+template <int L, int E, int NS, typename C>
+__device__ __forceinline__ void tw_preload_from(C* pre, int t, const C* __restrict__ tws) {
+    constexpr int TPF = L / E;
+    constexpr int RD = stage_radix(L, E, NS);
+    if constexpr (NS > 1) {
+        constexpr int NB = E / RD, LG = ilog2(RD), OFF = tw_pre_offset(L, E, NS);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int jm = (t + b * TPF) & (NS - 1);
+            const C* row = &el(tws, (uint32_t)(stage_offset(L, E, NS) + 4 * jm));
+#pragma unroll
+            for (int lg = 0; lg < LG; ++lg) pre[OFF + b * LG + lg] = row[lg];
+        }
+    }
+    if constexpr (NS * RD < L) tw_preload_from<L, E, NS * RD, C>(pre, t, tws);
+}
+
+// Loads the twiddle rows of every stage of a length-L transform (tw: the
+// stage tables of length L, all E).
+template <int L, int E, typename C>
+__device__ __forceinline__ void tw_preload(C (&pre)[tw_pre_count(L, E)], int t, const C* __restrict__ tw) {
+    tw_preload_from<L, E, 1, C>(pre, t, tw + stage_tables_offset(L, E));
+}
+
 // One Stockham stage on NH arrays at once.  Butterfly b of thread t owns the
 // register slots b + r*NB (r < RD), so results go back into the same slots
 // (last stage) or straight to LDS (other stages): no second register copy.
 // With ping-pong buffers (PP) consecutive stages exchange through different
 // LDS arrays, so one barrier per stage suffices (a stage's writes cannot
 // overtake the previous stage's reads of the other array); otherwise one array
-// and two barriers.  Twiddles come from the stage table `tws` of this
-// (L, E): w^r for power-of-two r directly, the others as products of two.
-template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, typename C>
+// and two barriers.  Twiddles come from the preloaded rows `pre` of the stage
+// tables of this (L, E): w^r for power-of-two r directly, the others as
+// products of two.
+template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, bool PRE, typename C>
 __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
-                                          const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tws) {
+                                          const LdsView<S, C> (&lds1)[NH], int t, const C* pre,
+                                          const C* __restrict__ tws) {
     constexpr int TPF = L / E;
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
     constexpr int NB = E / RD;
     constexpr bool LAST = (NS * RD == L);
+    constexpr LdsPad PD = stage_pad(NS, RD, S);
     const LdsView<S, C>(&lds)[NH] = (PP && BUF) ? lds1 : lds0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -197,16 +300,21 @@ __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, 
         const int jm = j & (NS - 1);
         C w[RD];
         if constexpr (NS > 1) {
+            constexpr int LG = ilog2(RD), OFF = tw_pre_offset(L, E, NS);
             const C* row = &el(tws, (uint32_t)(stage_offset(L, E, NS) + 4 * jm));
 #pragma unroll
             for (int r = 1; r < RD; ++r) {
                 const int lg = 31 - __builtin_clz(r);
                 const int hb = 1 << lg;  // highest power of two in r
-                if (hb == r) w[r] = row[lg];
+                if (hb == r) w[r] = PRE ? pre[OFF + b * LG + lg] : row[lg];
                 else w[r] = cmul(w[hb], w[r - hb]);
             }
         }
         const int idxD = (j - jm) * RD + jm;
+        // idxD and r NS occupy disjoint bits (j/NS scaled by NS RD, j % NS,
+        // r NS), so the padded slot splits into a per-thread part and a
+        // compile-time part that folds into the LDS instruction's offset.
+        const int q0 = pad_slot<PD.A, PD.SH>(idxD);
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
             C x[RD];
@@ -222,43 +330,57 @@ __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, 
                 for (int r = 0; r < RD; ++r) v[h][b + r * NB] = x[r];
             } else {
 #pragma unroll
-                for (int r = 0; r < RD; ++r) lds[h][idxD + r * NS] = x[r];
+                for (int r = 0; r < RD; ++r) lds[h].slot(q0 + pad_slot<PD.A, PD.SH>(r * NS)) = x[r];
             }
         }
     }
     if constexpr (!LAST) {
         __syncthreads();
+        // t < TPF and m TPF occupy disjoint bits: the same split as above
+        const int t0 = pad_slot<PD.A, PD.SH>(t);
 #pragma unroll
         for (int h = 0; h < NH; ++h)
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[h][m] = lds[h][t + m * TPF];
+            for (int m = 0; m < E; ++m) v[h][m] = lds[h].slot(t0 + pad_slot<PD.A, PD.SH>(m * TPF));
         if constexpr (!PP) __syncthreads();
     }
 }
 
-template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, typename C>
+template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, bool PRE, typename C>
 __device__ __forceinline__ void fft_from(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
-                                         const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw) {
+                                         const LdsView<S, C> (&lds1)[NH], int t, const C* pre,
+                                         const C* __restrict__ tws) {
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
-    fft_stage<L, E, NS, INV, TWS, NH, S, BUF, PP, C>(v, lds0, lds1, t, tw);
-    if constexpr (NS * RD < L) fft_from<L, E, NS * RD, INV, TWS, NH, S, 1 - BUF, PP, C>(v, lds0, lds1, t, tw);
+    fft_stage<L, E, NS, INV, TWS, NH, S, BUF, PP, PRE, C>(v, lds0, lds1, t, pre, tws);
+    if constexpr (NS * RD < L)
+        fft_from<L, E, NS * RD, INV, TWS, NH, S, 1 - BUF, PP, PRE, C>(v, lds0, lds1, t, pre, tws);
 }
 
 // Full transform of NH arrays (unnormalised; INV uses conjugate twiddles).
-// tw: the stage tables of length L (all E, see stage_tables_offset).  The
-// caller must have a barrier between any earlier use of the LDS views and
-// this call, and one between this call and any later LDS write.
-template <int L, int E, bool INV, int TWS, int NH, int S, typename C>
+// tw: the stage tables of length L (all E, see stage_tables_offset).  With
+// PRE the twiddle rows of all stages are loaded into registers first (their
+// latency overlaps the first stage); without, each stage loads its rows after
+// the previous barrier (fewer live registers, for kernels that hold other
+// values across the transform).  The caller must have a barrier between any
+// earlier use of the LDS views and this call, and one between this call and
+// any later LDS write.
+template <int L, int E, bool INV, int TWS, int NH, int S, bool PRE = true, typename C>
 __device__ __forceinline__ void fft(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
                                     const C* __restrict__ tw) {
-    fft_from<L, E, 1, INV, TWS, NH, S, 0, false, C>(v, lds, lds, t, tw + stage_tables_offset(L, E));
+    const C* tws = tw + stage_tables_offset(L, E);
+    C pre[tw_pre_count(L, E)];
+    if constexpr (PRE) tw_preload<L, E, C>(pre, t, tw);
+    fft_from<L, E, 1, INV, TWS, NH, S, 0, false, PRE, C>(v, lds, lds, t, pre, tws);
 }
 
 // The same with two LDS arrays used alternately (one barrier per stage).
-template <int L, int E, bool INV, int TWS, int NH, int S, typename C>
+template <int L, int E, bool INV, int TWS, int NH, int S, bool PRE = true, typename C>
 __device__ __forceinline__ void fft_pp(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
                                        const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw) {
-    fft_from<L, E, 1, INV, TWS, NH, S, 0, true, C>(v, lds0, lds1, t, tw + stage_tables_offset(L, E));
+    const C* tws = tw + stage_tables_offset(L, E);
+    C pre[tw_pre_count(L, E)];
+    if constexpr (PRE) tw_preload<L, E, C>(pre, t, tw);
+    fft_from<L, E, 1, INV, TWS, NH, S, 0, true, PRE, C>(v, lds0, lds1, t, pre, tws);
 }
 
 // ---------------------------------------------------------------------------

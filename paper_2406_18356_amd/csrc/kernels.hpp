@@ -144,11 +144,24 @@ constexpr int row_min_waves() {
 #ifndef MSR_REFETCH
 #define MSR_REFETCH 1
 #endif
+#ifndef MSR_TW_PRELOAD_INV
+#define MSR_TW_PRELOAD_INV 0
+#endif
 constexpr size_t kLdsBytes = 160 * 1024;
+
+// LDS slots of one row pair's line: the staged Hermitian line of length PT
+// (one pad slot per 16) and the NH half transforms of length L placed over it.
+__host__ __device__ constexpr int row_line_len(int L, bool padded, int E) {
+    const int PT = padded ? 2 * L : L;
+    const int NH = padded ? 2 : 1;
+    const int a = padded_len(PT);
+    const int b = NH * fft_lds_len(L, E < L ? E : L, 1);
+    return a > b ? a : b;
+}
 constexpr bool row_pingpong(size_t line_bytes, int threads, int grid_blocks) {
     const int waves = threads >= 64 ? threads / 64 : 1;
     const int resident = (16 + waves - 1) / waves;
-    return MSR_ROW_PINGPONG && 2 * line_bytes <= kLdsBytes &&
+    return MSR_ROW_PINGPONG && 2 * line_bytes <= kLdsBytes - 4096 &&
            (grid_blocks <= 256 || (size_t)resident * 2 * line_bytes <= kLdsBytes);
 }
 
@@ -190,7 +203,10 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     using C = cplx<R>;
     constexpr int E = Cf::E, TPF = Cf::TPF, NH = Cf::NH, PT = Cf::PT, HALF = Cf::HALF;
-    constexpr int ZLEN = padded_len(PT);
+    // one pair's LDS: the staged Hermitian line (padded_len(PT) slots) and,
+    // over the same memory, the NH half transforms (HLEN slots each)
+    constexpr int HLEN = fft_lds_len(L, E, 1);
+    constexpr int ZLEN = row_line_len(L, PADDED, E);
     constexpr int NT = PAIRS * TPF;
     constexpr int NQ = Epi::NQ;
     constexpr bool PP = row_pingpong(PAIRS * ZLEN * sizeof(C), NT, L / (2 * PAIRS));
@@ -215,8 +231,8 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     LdsView<1, C> hv[NH], hw[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
-        hv[h] = LdsView<1, C>{lds + pair * ZLEN + h * padded_len(L), 0};
-        hw[h] = LdsView<1, C>{lds + (PP ? PAIRS * ZLEN : 0) + pair * ZLEN + h * padded_len(L), 0};
+        hv[h] = LdsView<1, C>{lds + pair * ZLEN + h * HLEN, 0};
+        hw[h] = LdsView<1, C>{lds + (PP ? PAIRS * ZLEN : 0) + pair * ZLEN + h * HLEN, 0};
     }
 
     C v[NH][E];
@@ -284,8 +300,12 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 #pragma unroll
             for (int h = 0; h < NH; ++h) v[h][m] = zv[NH * (t + m * TPF) + h];
         __syncthreads();
-        if constexpr (PP) fft_pp<L, E, true, Cf::TWS, NH, 1, C>(v, hv, hw, t, a.tws);
-        else fft<L, E, true, Cf::TWS, NH, 1, C>(v, hv, t, a.tws);
+        // The update epilogue keeps beta_{k-1} in registers across the inverse
+        // transform within a four-wave budget: its inverse loads the twiddles
+        // stage by stage.
+        constexpr bool PRE_INV = MSR_TW_PRELOAD_INV || Epi::MIN_WAVES == 1;
+        if constexpr (PP) fft_pp<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, hw, t, a.tws);
+        else fft<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, t, a.tws);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             C s = v[0][m];
@@ -325,8 +345,8 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
             if constexpr (PADDED) v[1][m] = cmul(z[m], el(tw_f, tf + m * TPF));
         }
         __syncthreads();
-        if constexpr (PP) fft_pp<L, E, false, Cf::TWS, NH, 1, C>(v, hv, hw, tf, tws_f);
-        else fft<L, E, false, Cf::TWS, NH, 1, C>(v, hv, tf, tws_f);
+        if constexpr (PP) fft_pp<L, E, false, Cf::TWS, NH, 1>(v, hv, hw, tf, tws_f);
+        else fft<L, E, false, Cf::TWS, NH, 1>(v, hv, tf, tws_f);
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < E; ++m)
@@ -595,7 +615,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
     constexpr int E = Cf::E, TPF = Cf::TPF, NH = Cf::NH;
     constexpr int NT = CB * TPF;
     constexpr int NQ = Mode::NQ;
-    constexpr int HL = padded_len(L);
+    constexpr int HL = fft_lds_len(L, E, CB);
     static_assert(T % CB == 0, "CB must divide T");
 
     const int tid = threadIdx.x;
@@ -624,7 +644,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
         v[0][m] = y;
         if constexpr (PADDED) v[1][m] = cmul(y, el(a.tw, i));
     }
-    fft<L, E, false, Cf::TWS, NH, CB, C>(v, hv, t, a.tws);
+    fft<L, E, false, Cf::TWS, NH, CB>(v, hv, t, a.tws);
 
     double acc[NQ > 0 ? NQ : 1];
 #pragma unroll
@@ -651,7 +671,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
         asm volatile("" : "+v"(ti), "+v"(base_i));
 #endif
         __syncthreads();
-        fft<L, E, true, Cf::TWS, NH, CB, C>(v, hv, ti, tws_i);
+        fft<L, E, true, Cf::TWS, NH, CB>(v, hv, ti, tws_i);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int i = ti + m * TPF;
@@ -683,7 +703,7 @@ col_kernel(ColArgs<R> a0, Mode m0) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     constexpr int NT = CB * Cf::TPF;
     constexpr int NQ = Mode::NQ;
-    __shared__ cplx<R> lds[Cf::NH * CB * padded_len(L)];
+    __shared__ cplx<R> lds[Cf::NH * CB * fft_lds_len(L, Cf::E, CB)];
     __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
     ColArgs<R> a = a0;
     Mode md = m0;
@@ -703,7 +723,7 @@ col_dual_kernel(ColArgs<R> a1, M1 m1, int g1, ColArgs<R> a2, M2 m2) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     constexpr int NT = CB * Cf::TPF;
     constexpr int NQ = M1::NQ > M2::NQ ? M1::NQ : M2::NQ;
-    __shared__ cplx<R> lds[Cf::NH * CB * padded_len(L)];
+    __shared__ cplx<R> lds[Cf::NH * CB * fft_lds_len(L, Cf::E, CB)];
     __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
     const int b = xcd_block(blockIdx.x, gridDim.x);
     if (b < g1) col_body<R, L, PADDED, EMAX, T, CB, M1>(a1, m1, b, b, lds, red);

@@ -24,10 +24,11 @@ __host__ __device__ constexpr int tile_width(int L, int esize) {
 // unless that does not fit a CU's LDS or the variant asks for single columns;
 // then one column (the block reads every T-th value of each row run, and the
 // tile's other columns are read by neighbouring blocks through the L2).
-__host__ __device__ constexpr int col_block(int L, bool padded, int esize, bool onecol) {
+__host__ __device__ constexpr int col_block(int L, bool padded, int esize, int emax, bool onecol) {
     const int NH = padded ? 2 : 1;
     const int T = tile_width(L, esize);
-    const int whole = NH * T * (L + L / 16) * esize;
+    const int E = L >= emax ? emax : L;
+    const int whole = NH * T * fft_lds_len(L, E, T) * esize;
     return (onecol || whole > 160 * 1024 - 4096) ? 1 : T;
 }
 
@@ -40,8 +41,7 @@ __host__ __device__ constexpr int default_emax(int esize) { return esize == 8 ? 
 __host__ __device__ constexpr int row_pairs(int L, bool padded, int esize, int emax) {
     const int E = L >= emax ? emax : L;
     const int TPF = L / E;
-    const int PT = padded ? 2 * L : L;
-    const int lds_pair = (PT + PT / 16) * esize;
+    const int lds_pair = row_line_len(L, padded, E) * esize;
     int p = TPF >= 256 ? 1 : 256 / TPF;
     while (p > 1 && p * lds_pair > 72 * 1024) p /= 2;
     if (p > L / 2) p = L / 2;
@@ -54,11 +54,10 @@ __host__ __device__ constexpr int row_pairs(int L, bool padded, int esize, int e
 __host__ __device__ constexpr bool fits_lds(int L, bool padded, int esize, int emax, bool onecol) {
     const int NH = padded ? 2 : 1;
     const int E = L >= emax ? emax : L;
-    const int CB = col_block(L, padded, esize, onecol);
-    const int col = NH * CB * (L + L / 16) * esize;
-    const int PT = padded ? 2 * L : L;
+    const int CB = col_block(L, padded, esize, emax, onecol);
+    const int col = NH * CB * fft_lds_len(L, E, CB) * esize;
     const int pairs = row_pairs(L, padded, esize, emax);
-    const int row = pairs * (PT + PT / 16) * esize;
+    const int row = pairs * row_line_len(L, padded, E) * esize;
     return col <= 160 * 1024 - 4096 && row <= 160 * 1024 - 4096 && CB * (L / E) <= 1024 && pairs * (L / E) <= 1024;
 }
 

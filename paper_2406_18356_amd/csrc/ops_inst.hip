@@ -17,7 +17,7 @@ struct Inst {
     static constexpr int ES = (int)sizeof(cplx<R>);
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     static constexpr int T = tile_width(L, ES);
-    static constexpr int CB = col_block(L, PADDED, ES, ONECOL);
+    static constexpr int CB = col_block(L, PADDED, ES, EMAX, ONECOL);
     static constexpr int PAIRS = row_pairs(L, PADDED, ES, EMAX);
     static constexpr int RT = PAIRS * Cf::TPF;
     static constexpr int CT = CB * Cf::TPF;
