@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSR_ABI_VERSION 1
+#define MSR_ABI_VERSION 2  /* 2: msr_step2_full_res takes image_out */
 
 typedef enum msr_status {
     MSR_OK = 0,
@@ -184,10 +184,14 @@ msr_status msr_step1_low_res(msr_ctx* ctx, const msr_solve* opt, const void* x0,
                              void* model_out, void* image_out, msr_result* res, void* stream);
 
 /* Step 2: FISTA on Eq. 5 with the constraint image l = low_res (N x N), from
- * x0 (NULL: zeros; any warm start may be passed here).  Requires
- * msr_set_dirty_psf(step 2) and msr_set_filters, else MSR_ERR_STATE. */
+ * x0 (NULL: zeros; any warm start may be passed here).  Writes beta_K to
+ * model_out; if image_out is not NULL it receives the reconstructed image
+ * i^ = beta_K + (i_H~ - H_H beta_K) (Sect. 3.3: the model plus the residual
+ * image left after it, one major cycle).  Requires msr_set_dirty_psf(step 2)
+ * and msr_set_filters, else MSR_ERR_STATE.  Blocks until the results are
+ * written. */
 msr_status msr_step2_full_res(msr_ctx* ctx, const msr_solve* opt, const void* low_res, const void* x0,
-                              void* model_out, msr_result* res, void* stream);
+                              void* model_out, void* image_out, msr_result* res, void* stream);
 
 /* `cycles` major cycles of step s (Sect. 3.2 for step 1, Sect. 3.3 for step 2)
  * with the residual image formed in the image domain: cycle n solves its
@@ -294,7 +298,13 @@ msr_status msr_default_lambda(msr_ctx* ctx, int step, int cycle, double c, doubl
  * default variant's only by rounding.  Writes the step-1 choices (0 = default)
  * to *row_variant / *col_variant and, if times_ms is not NULL, the step-1 mean
  * times in ms to times_ms[2*v] (column pass) and times_ms[2*v + 1] (row pass)
- * for v < MSR_MAX_VARIANTS (-1: not built).  Any output pointer may be NULL. */
+ * for v < MSR_MAX_VARIANTS (-1: not built).  Any output pointer may be NULL.
+ * The winners are cached for the process, keyed by image size, padding,
+ * precision, dictionary, the kept spectral columns of both PSFs and of the
+ * filters, and which passes were tuned: a later call on any context with the
+ * same key applies them (and reports the cached times) without timing.
+ * reps < 0 times again with -reps launches and replaces the cached entry;
+ * reps = 0 means 10. */
 msr_status msr_autotune(msr_ctx* ctx, int reps, int* row_variant, int* col_variant, double* times_ms,
                         void* stream);
 

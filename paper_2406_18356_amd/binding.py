@@ -90,7 +90,7 @@ SYMBOLS = {
     "msr_lipschitz": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int), _P]),
     "msr_set_lipschitz": (_ST, [_P, C.c_int, C.c_double]),
     "msr_step1_low_res": (_ST, [_P, C.POINTER(SolveOptions), _P, _P, _P, C.POINTER(Result), _P]),
-    "msr_step2_full_res": (_ST, [_P, C.POINTER(SolveOptions), _P, _P, _P, C.POINTER(Result), _P]),
+    "msr_step2_full_res": (_ST, [_P, C.POINTER(SolveOptions), _P, _P, _P, _P, C.POINTER(Result), _P]),
     "msr_major_cycles": (_ST, [_P, C.c_int, C.c_int, C.c_double, C.c_int, _P, _P, _P, C.POINTER(Result), _P]),
     "msr_objective": (_ST, [_P, C.c_int, C.c_double, _P, _P, C.POINTER(C.c_double), _P]),
     "msr_gradient": (_ST, [_P, C.c_int, _P, _P, _P, _P]),
@@ -282,13 +282,16 @@ class Solver:
                                                 C.byref(res), _stream(stream)))
         return (beta, img, res) if image else (beta, res)
 
-    def step2(self, lam, low_res, iters, x0=None, check_every=0, tol=0.0, f_ref=0.0, out=None, stream=None):
+    def step2(self, lam, low_res, iters, x0=None, check_every=0, tol=0.0, f_ref=0.0, out=None, stream=None,
+              image=False):
+        """(beta_K, res), or (beta_K, image, res) with image = beta_K + (i_H~ - H_H beta_K)."""
         opt = SolveOptions(float(lam), int(iters), int(check_every), float(tol), float(f_ref))
         res = Result()
         beta = out if out is not None else self._img()
+        img = self._img() if image else None
         self._check(self._lib.msr_step2_full_res(self._h, C.byref(opt), self._p(low_res), self._p(x0), self._p(beta),
-                                                 C.byref(res), _stream(stream)))
-        return beta, res
+                                                 self._p(img), C.byref(res), _stream(stream)))
+        return (beta, img, res) if image else (beta, res)
 
     def major_cycles(self, step, cycles, iters, c=0.05, low_res=None, stream=None):
         """(image, sum of the cycle images, per-cycle results) of `cycles`

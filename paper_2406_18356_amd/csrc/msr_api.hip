@@ -25,7 +25,9 @@
 #include <cstdio>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -922,7 +924,8 @@ struct Impl {
     }
 
     // After `done` iterations: the exact objective of beta_done (F, data term,
-    // l1 norm), the model copied out and, if asked, i_L = beta + (i~ - H beta).
+    // l1 norm), the model copied out and, if asked, the step's image
+    // beta + (i~ - H beta) (i_L in step 1, Sect. 3.2; the final image in step 2, Sect. 3.3).
     msr_status finish(int step, double lambda, int done, R* model_out, R* image_out, double F[3], hipStream_t s) {
         const size_t nb = c->sh.rs * c->sh.img_elems;
         const R* bK = beta(done);
@@ -1719,8 +1722,8 @@ msr_status msr_step1_low_res(msr_ctx* c, const msr_solve* opt, const void* x0, v
 }
 
 msr_status msr_step2_full_res(msr_ctx* c, const msr_solve* opt, const void* low_res, const void* x0, void* model_out,
-                              msr_result* res, void* stream) {
-    return solve_entry(c, 2, opt, low_res, x0, model_out, nullptr, res, stream);
+                              void* image_out, msr_result* res, void* stream) {
+    return solve_entry(c, 2, opt, low_res, x0, model_out, image_out, res, stream);
 }
 
 msr_status msr_major_cycles(msr_ctx* c, int step, int cycles, double cl, int iters, const void* low_res,
@@ -1793,12 +1796,62 @@ msr_status msr_default_lambda(msr_ctx* c, int step, int cycle, double cc, double
     return MSR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The autotuner's winners, per process, keyed by what decides them: image
+// size, padding, precision, dictionary, the kept spectral columns of both
+// PSFs and of the filters, and which passes were tuned.
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int, int>;
+struct TuneVal {
+    int row[2], col[2], filt;
+    double times[2 * MSR_MAX_VARIANTS];
+};
+std::map<TuneKey, TuneVal> g_tune;
+std::mutex g_tune_mu;
+
+TuneKey tune_key(const msr_ctx* c) {
+    return TuneKey{c->sh.N, c->cfg.pad, c->sh.prec, c->cfg.dictionary, c->K[0], c->K[1], c->KL,
+                   (int)c->have_psf[0], (int)c->have_psf[1], (int)c->have_filters};
+}
+}  // namespace
+
+extern "C" {
+
 msr_status msr_autotune(msr_ctx* c, int reps, int* row_variant, int* col_variant, double* times_ms, void* stream) {
     TRY(check_step(c, 1, false));
-    if (reps <= 0) reps = 10;
-    if (times_ms)
-        for (int i = 0; i < 2 * MSR_MAX_VARIANTS; ++i) times_ms[i] = -1.0;
-    TRY(with_impl(c, [&](auto& im) { return im.autotune(reps, times_ms, S(stream)); }));
+    const bool force = reps < 0;
+    reps = reps == 0 ? 10 : (reps < 0 ? -reps : reps);
+    double t[2 * MSR_MAX_VARIANTS];
+    for (int i = 0; i < 2 * MSR_MAX_VARIANTS; ++i) t[i] = -1.0;
+    const TuneKey key = tune_key(c);
+    bool cached = false;
+    if (!force) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            for (int s = 0; s < 2; ++s) {
+                c->var_row[s] = it->second.row[s];
+                c->var_col[s] = it->second.col[s];
+            }
+            c->var_filt = it->second.filt;
+            std::memcpy(t, it->second.times, sizeof t);
+            cached = true;
+        }
+    }
+    if (!cached) {
+        TRY(with_impl(c, [&](auto& im) { return im.autotune(reps, t, S(stream)); }));
+        TuneVal v{};
+        for (int s = 0; s < 2; ++s) {
+            v.row[s] = c->var_row[s];
+            v.col[s] = c->var_col[s];
+        }
+        v.filt = c->var_filt;
+        std::memcpy(v.times, t, sizeof t);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = v;
+    }
+    if (times_ms) std::memcpy(times_ms, t, sizeof t);
     if (row_variant) *row_variant = c->var_row[0];
     if (col_variant) *col_variant = c->var_col[0];
     return MSR_OK;
