@@ -275,6 +275,13 @@ __device__ __forceinline__ void tw_preload(C (&pre)[tw_pre_count(L, E)], int t, 
     tw_preload_from<L, E, 1, C>(pre, t, tw + stage_tables_offset(L, E));
 }
 
+// A callable run by every thread at the start of a transform's last stage,
+// when every exchange through LDS is done (all threads are past the last
+// barrier): the LDS views are free from there until the caller's next write.
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 // One Stockham stage on NH arrays at once.  Butterfly b of thread t owns the
 // register slots b + r*NB (r < RD), so results go back into the same slots
 // (last stage) or straight to LDS (other stages): no second register copy.
@@ -284,16 +291,18 @@ __device__ __forceinline__ void tw_preload(C (&pre)[tw_pre_count(L, E)], int t, 
 // and two barriers.  Twiddles come from the preloaded rows `pre` of the stage
 // tables of this (L, E): w^r for power-of-two r directly, the others as
 // products of two.
-template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, bool PRE, typename C>
+template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, bool PRE, typename C,
+          class Hook>
 __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
                                           const LdsView<S, C> (&lds1)[NH], int t, const C* pre,
-                                          const C* __restrict__ tws) {
+                                          const C* __restrict__ tws, const Hook& hook) {
     constexpr int TPF = L / E;
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
     constexpr int NB = E / RD;
     constexpr bool LAST = (NS * RD == L);
     constexpr LdsPad PD = stage_pad(NS, RD, S);
     const LdsView<S, C>(&lds)[NH] = (PP && BUF) ? lds1 : lds0;
+    if constexpr (LAST) hook();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + b * TPF;
@@ -346,14 +355,15 @@ __device__ __forceinline__ void fft_stage(RegArr<NH, E, C>& v, const LdsView<S, 
     }
 }
 
-template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, bool PRE, typename C>
+template <int L, int E, int NS, bool INV, int TWS, int NH, int S, int BUF, bool PP, bool PRE, typename C,
+          class Hook>
 __device__ __forceinline__ void fft_from(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
                                          const LdsView<S, C> (&lds1)[NH], int t, const C* pre,
-                                         const C* __restrict__ tws) {
+                                         const C* __restrict__ tws, const Hook& hook) {
     constexpr int RD = (L / NS) >= E ? E : (L / NS);
-    fft_stage<L, E, NS, INV, TWS, NH, S, BUF, PP, PRE, C>(v, lds0, lds1, t, pre, tws);
+    fft_stage<L, E, NS, INV, TWS, NH, S, BUF, PP, PRE, C, Hook>(v, lds0, lds1, t, pre, tws, hook);
     if constexpr (NS * RD < L)
-        fft_from<L, E, NS * RD, INV, TWS, NH, S, 1 - BUF, PP, PRE, C>(v, lds0, lds1, t, pre, tws);
+        fft_from<L, E, NS * RD, INV, TWS, NH, S, 1 - BUF, PP, PRE, C, Hook>(v, lds0, lds1, t, pre, tws, hook);
 }
 
 // Full transform of NH arrays (unnormalised; INV uses conjugate twiddles).
@@ -364,23 +374,24 @@ __device__ __forceinline__ void fft_from(RegArr<NH, E, C>& v, const LdsView<S, C
 // values across the transform).  The caller must have a barrier between any
 // earlier use of the LDS views and this call, and one between this call and
 // any later LDS write.
-template <int L, int E, bool INV, int TWS, int NH, int S, bool PRE = true, typename C>
+template <int L, int E, bool INV, int TWS, int NH, int S, bool PRE = true, typename C, class Hook = NoHook>
 __device__ __forceinline__ void fft(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds)[NH], int t,
-                                    const C* __restrict__ tw) {
+                                    const C* __restrict__ tw, const Hook& hook = Hook{}) {
     const C* tws = tw + stage_tables_offset(L, E);
     C pre[tw_pre_count(L, E)];
     if constexpr (PRE) tw_preload<L, E, C>(pre, t, tw);
-    fft_from<L, E, 1, INV, TWS, NH, S, 0, false, PRE, C>(v, lds, lds, t, pre, tws);
+    fft_from<L, E, 1, INV, TWS, NH, S, 0, false, PRE, C, Hook>(v, lds, lds, t, pre, tws, hook);
 }
 
 // The same with two LDS arrays used alternately (one barrier per stage).
-template <int L, int E, bool INV, int TWS, int NH, int S, bool PRE = true, typename C>
+template <int L, int E, bool INV, int TWS, int NH, int S, bool PRE = true, typename C, class Hook = NoHook>
 __device__ __forceinline__ void fft_pp(RegArr<NH, E, C>& v, const LdsView<S, C> (&lds0)[NH],
-                                       const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw) {
+                                       const LdsView<S, C> (&lds1)[NH], int t, const C* __restrict__ tw,
+                                       const Hook& hook = Hook{}) {
     const C* tws = tw + stage_tables_offset(L, E);
     C pre[tw_pre_count(L, E)];
     if constexpr (PRE) tw_preload<L, E, C>(pre, t, tw);
-    fft_from<L, E, 1, INV, TWS, NH, S, 0, true, PRE, C>(v, lds0, lds1, t, pre, tws);
+    fft_from<L, E, 1, INV, TWS, NH, S, 0, true, PRE, C, Hook>(v, lds0, lds1, t, pre, tws, hook);
 }
 
 // ---------------------------------------------------------------------------

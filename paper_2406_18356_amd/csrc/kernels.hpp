@@ -147,6 +147,34 @@ constexpr int row_min_waves() {
 #ifndef MSR_TW_PRELOAD_INV
 #define MSR_TW_PRELOAD_INV 0
 #endif
+#ifndef MSR_LATE_LDS
+#define MSR_LATE_LDS 1
+#endif
+
+// LDS pointer type (ds_read / ds_write, not flat accesses).
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+
+// Copies the n reals at src (global, 16-byte aligned, n a multiple of
+// 64 * 16 / sizeof(R) per wave) into LDS at dst without passing through
+// registers: each of the nw waves of a line issues direct-to-LDS loads
+// (global_load_lds_dwordx4) for its share; wave w of lane l moves 16 bytes at
+// offset (w * share + c * 64 + l) * 16.  The data is in LDS once the issuing
+// wave has waited for its vector memory counter; other waves see it after a
+// barrier that follows that wait.
+template <typename R, int N, int NW>
+__device__ __forceinline__ void load_to_lds(const R* __restrict__ src, R* dst, int t) {
+    constexpr int EL = 16 / (int)sizeof(R);
+    constexpr int SHARE = N / NW;
+    constexpr int NI = SHARE / (64 * EL);
+    static_assert(N % NW == 0 && SHARE % (64 * EL) == 0, "share must be whole 1 KiB wave loads");
+    const int w = t >> 6, lane = t & 63;
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+        const int off = w * SHARE + c * 64 * EL;
+        __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * EL), (lds_ptr<void>)(dst + off), 16, 0, 0);
+    }
+}
 constexpr size_t kLdsBytes = 160 * 1024;
 
 // LDS slots of one row pair's line: the staged Hermitian line of length PT
@@ -249,6 +277,14 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
         }
     };
 
+    // An epilogue that reads an image late (the update's beta_{k-2}) gets
+    // the pair's two rows copied straight into the pair's LDS line while
+    // the inverse transform's last stage computes (the LDS is idle then),
+    // instead of a global load that stalls the epilogue.
+    constexpr bool LATE = INV_IN && MSR_LATE_LDS && Epi::LATE_ROWS && !PP && TPF % 64 == 0 &&
+                          (2 * L) % ((TPF / 64) * 64 * (16 / (int)sizeof(R))) == 0;
+    lds_ptr<const R> late = nullptr;
+
     if constexpr (INV_IN) {
         // Half-plane columns of both rows -> full Hermitian-combined line Z in
         // LDS.  Item q covers column kx of one pair (kx % T fastest, then the
@@ -304,8 +340,19 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
         // transform within a four-wave budget: its inverse loads the twiddles
         // stage by stage.
         constexpr bool PRE_INV = MSR_TW_PRELOAD_INV || Epi::MIN_WAVES == 1;
-        if constexpr (PP) fft_pp<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, hw, t, a.tws);
-        else fft<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, t, a.tws);
+        if constexpr (LATE) {
+            R* line = reinterpret_cast<R*>(lds + pair * ZLEN);
+            const R* src = epi.late_src(ra);
+            auto hook = [&]() { load_to_lds<R, 2 * L, TPF / 64>(src, line, t); };
+            fft<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, t, a.tws, hook);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            late = (lds_ptr<const R>)line;
+        } else if constexpr (PP) {
+            fft_pp<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, hw, t, a.tws);
+        } else {
+            fft<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, t, a.tws);
+        }
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             C s = v[0][m];
@@ -321,8 +368,13 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     double acc[NQ > 0 ? NQ : 1];
 #pragma unroll
     for (int q = 0; q < (NQ > 0 ? NQ : 1); ++q) acc[q] = 0.0;
+    if constexpr (LATE) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) z[m] = epi.apply(ra, t + m * TPF, z[m], acc, pre[m]);
+        for (int m = 0; m < E; ++m) z[m] = epi.apply_late(ra, t + m * TPF, z[m], acc, pre[m], late);
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) z[m] = epi.apply(ra, t + m * TPF, z[m], acc, pre[m]);
+    }
 
     if constexpr (FWD_OUT) {
         // The forward transform reads the same twiddles, and computes the same
@@ -404,6 +456,7 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
 template <typename R>
 struct EpiLoad {
     static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
+    static constexpr bool LATE_ROWS = false;
     const R* __restrict__ img;
     int ld;
     R scale;
@@ -420,6 +473,7 @@ struct EpiLoad {
 template <typename R>
 struct EpiLoadShift {
     static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
+    static constexpr bool LATE_ROWS = false;
     const R* __restrict__ img;
     int P;
     __device__ __forceinline__ void to_channel(long long off) { img = shifted(img, off); }
@@ -437,6 +491,7 @@ struct EpiLoadShift {
 template <typename R>
 struct EpiStore {
     static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
+    static constexpr bool LATE_ROWS = false;
     R* __restrict__ out;
     int ld;
     R scale;
@@ -455,6 +510,7 @@ struct EpiStore {
 template <typename R>
 struct EpiResid {
     static constexpr int NQ = 1, NPRE = 2, MIN_WAVES = 1;
+    static constexpr bool LATE_ROWS = false;
     const R* __restrict__ y;
     R* __restrict__ r_out;
     int ld;
@@ -493,9 +549,12 @@ struct EpiResid {
 template <typename R>
 struct EpiUpdate {
     static constexpr int NQ = 1, NPRE = 2, MIN_WAVES = 4;
+    static constexpr bool LATE_ROWS = true;  // beta_{k-2} of the pair's rows via LDS (row_kernel)
     const R* __restrict__ b1;
     R* __restrict__ b2;  // in: beta_{k-2}; out: beta_k
     int ld;
+    // rows (r, r + 1) of beta_{k-2}, which the row kernel copies to LDS
+    __device__ __forceinline__ const R* late_src(int r) const { return b2 + (size_t)r * ld; }
     R two_mu;     // 2 mu
     R thr;        // mu * lambda
     R t_prev, t_cur;
@@ -526,8 +585,16 @@ struct EpiUpdate {
         p[1] = el(b1, ia + ld);
     }
     __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc, const R* p) const {
-        const uint32_t ia = (uint32_t)r * ld + i, ib = ia + ld;
-        R pa = el(b2, ia), pb = el(b2, ib);
+        const uint32_t ia = (uint32_t)r * ld + i;
+        return update(ia, z, acc, p, el(b2, ia), el(b2, ia + ld));
+    }
+    // The same with beta_{k-2} of rows (r, r + 1) in LDS (late, ld apart).
+    __device__ __forceinline__ cplx<R> apply_late(int r, int i, cplx<R> z, double* acc, const R* p,
+                                                  lds_ptr<const R> late) const {
+        return update((uint32_t)r * ld + i, z, acc, p, late[i], late[ld + i]);
+    }
+    __device__ __forceinline__ cplx<R> update(uint32_t ia, cplx<R> z, double* acc, const R* p, R pa, R pb) const {
+        const uint32_t ib = ia + ld;
         const R qa = upd(z.x, p[0], pa);
         const R qb = upd(z.y, p[1], pb);
         el(b2, ia) = pa;
@@ -541,6 +608,7 @@ struct EpiUpdate {
 template <typename R>
 struct EpiPower {
     static constexpr int NQ = 2, NPRE = 0, MIN_WAVES = 1;
+    static constexpr bool LATE_ROWS = false;
     const R* __restrict__ vprev;
     R* __restrict__ w_out;
     int ld;
