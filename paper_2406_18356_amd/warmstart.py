@@ -10,6 +10,7 @@ tensors between those calls.
 """
 from __future__ import annotations
 
+import json
 import time
 
 import numpy as np
@@ -19,7 +20,7 @@ def _dev_f32(torch, a, dev):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
 
 
-def solve_pairs(problems, iters1=500, iters2=3000, c=0.05, positivity=True, chunk=32, device=0):
+def solve_pairs(problems, iters1=500, iters2=3000, c=0.05, positivity=True, chunk=32, device=0, log=None):
     """Runs the two-step method on `problems` (objects with n, dirty_L, psf_L,
     dirty_H, psf_H, ell, delta; one image size) in batches of `chunk` channels.
 
@@ -52,6 +53,9 @@ def solve_pairs(problems, iters1=500, iters2=3000, c=0.05, positivity=True, chun
         b2_all += b2
         lam_all += lam2
         del b
+        if log:
+            torch.cuda.synchronize()
+            log(f"solve_pairs: {min(s + chunk, len(problems))}/{len(problems)} pairs")
     return torch.stack(dh_all), torch.stack(il_all), torch.stack(b2_all), lam_all
 
 
@@ -100,3 +104,116 @@ def timed_forward(net, dh, il):
     x0 = net.forward(dh, il)
     torch.cuda.synchronize()
     return x0, (time.perf_counter() - t) * 1e3
+
+
+# --------------------------------------------------------------------------
+# A certified reference objective F* for the time-to-tolerance metric
+# --------------------------------------------------------------------------
+def duality_gap(F, data, grad, x, lam, positivity=True):
+    """Upper bound on F(x) - F* from one gradient evaluation (any array type
+    with .max(), .abs() and elementwise products: NumPy or torch).
+
+    Step 2 (and step 1) minimise f(x) + lam ||x||_1 [+ x >= 0] with
+    f(x) = ||M x - y||^2, M and y stacking the filtered PSF operator and the
+    constraint term.  With r = y - M x, grad f = -2 M^T r, and the dual of
+    min_{x >= 0} ||M x - y||^2 + lam 1^T x is
+        max_u  -||u||^2 / 4 - u^T y   subject to  M^T u >= -lam
+    (|M^T u| <= lam without positivity).  The point u = -2 s r is feasible for
+    s = min(1, lam / max(-grad)) (max |grad| without positivity), and its dual
+    value is (2 s - s^2) f(x) - s <grad, x>, using r^T y = f - <grad, x> / 2.
+    Returns (gap, s); gap = F(x) - dual >= F(x) - F* >= 0, and gap = 0 at the
+    minimiser (s = 1 by the optimality conditions)."""
+    worst = float((-grad).max()) if positivity else float(abs(grad).max())
+    s = 1.0 if worst <= lam else lam / worst
+    gx = float((grad * x).sum())
+    dual = (2.0 * s - s * s) * data - s * gx
+    return F - dual, s
+
+
+def certified_fstar(dirty_L, psf_L, dirty_H, psf_H, ell, delta, sigma2, lam, low_res, x_start=None, chunk=5000,
+                    max_iters=200000, gap_tol=1e-9, device=0, positivity=True, log=None):
+    """F* of step 2 from the FP64 path on the given data (arrays or tensors,
+    e.g. the float32 inputs of an FP32 solve, converted exactly): FISTA
+    (Algorithm 1) continued in chunks of `chunk` iterations (msr_get_state /
+    msr_set_state, so the momentum runs on) until the duality gap of the
+    iterate is <= gap_tol |F|.  Returns a dict with F (the objective of the
+    last iterate, >= F*), the gap (F - gap <= F* <= F), the iterations, the
+    wall time and the FP64 iterate."""
+    import torch
+
+    from .binding import Solver
+
+    dev = torch.device("cuda", device)
+    T = lambda a: a.to(dev, torch.float64).contiguous() if torch.is_tensor(a) else \
+        torch.from_numpy(np.ascontiguousarray(a, np.float64)).to(dev)  # noqa: E731
+    dh = T(dirty_H)
+    s = Solver(dh.shape[0], positivity=positivity, precision=64)
+    s.set_dirty_psf(1, T(dirty_L), T(psf_L))
+    s.set_dirty_psf(2, dh, T(psf_H))
+    s.set_filters(ell, delta, sigma2, 1e-3 * sigma2)
+    l64 = T(low_res)
+    s.lipschitz(2)
+    x0 = None if x_start is None else T(x_start)
+    done, rec = 0, None
+    t0 = time.perf_counter()
+    while done < max_iters:
+        if done > 0:
+            s.set_state(2, bk, bp, k)
+            beta, r = s.step2(lam, l64, chunk)
+        else:
+            beta, r = s.step2(lam, l64, chunk, x0=x0)
+        bk, bp, k = s.get_state(2)
+        done += chunk
+        g = s.gradient(2, beta, l64)
+        F, data, _ = s.objective(2, lam, beta, l64)
+        gap, sc = duality_gap(F, data, g, beta, lam, positivity)
+        rec = {"F": F, "gap": gap, "rel_gap": gap / abs(F), "iters": done, "scale": sc,
+               "s": time.perf_counter() - t0}
+        if log:
+            log(f"certified F*: {done} FP64 iterations, F = {F:.15g}, gap/|F| = {gap / abs(F):.3g}")
+        if gap <= gap_tol * abs(F):
+            break
+    rec["beta"] = beta
+    return rec
+
+
+# --------------------------------------------------------------------------
+# Objective trajectories and the time to a tolerance read from them
+# --------------------------------------------------------------------------
+def trajectory(solver, lam, low_res, x0=None, iters=20000, every=500, momentum_k=0):
+    """Step 2 run for `iters` iterations of Algorithm 1 in chunks of `every`
+    (continued exactly through msr_get_state / msr_set_state), from x0 (None:
+    zero) restarted at k = 1, or, with momentum_k > 0, entered at iteration
+    momentum_k + 1 with zero velocity.  Records after each chunk the
+    iteration count, the exact objective F (FP64 reductions) and the
+    cumulative HIP-event time of the iteration loops (objective evaluations
+    excluded).  Returns {"k": [...], "F": [...], "ms": [...]}."""
+    import torch
+
+    if momentum_k > 0:
+        z = x0 if x0 is not None else torch.zeros_like(low_res)
+        solver.set_state(2, z, z, momentum_k)
+        x0 = None
+    out = {"k": [], "F": [], "ms": []}
+    done, ms = 0, 0.0
+    while done < iters:
+        step = min(every, iters - done)
+        if done > 0:
+            solver.set_state(2, bk, bp, kk)
+        beta, r = solver.step2(lam, low_res, step, x0=x0 if done == 0 else None)
+        bk, bp, kk = solver.get_state(2)
+        done += step
+        ms += r.elapsed_ms
+        out["k"].append(done)
+        out["F"].append(r.objective)
+        out["ms"].append(ms)
+    return out
+
+
+def crossing(traj, f_ref, tol=1e-6, warm_ms=0.0):
+    """First recorded point of a trajectory with (F - f_ref) / |f_ref| <= tol:
+    {"iters", "ms" (plus warm_ms), "converged"}; iters -1 if never."""
+    for k, F, ms in zip(traj["k"], traj["F"], traj["ms"]):
+        if (F - f_ref) / abs(f_ref) <= tol:
+            return {"iters": int(k), "ms": ms + warm_ms, "converged": True}
+    return {"iters": -1, "ms": -1.0, "converged": False}

@@ -1,0 +1,227 @@
+"""The learned warm start measured against the method without it.
+
+    python -m paper_2406_18356_amd.warmstart_study --phase all --train 512 --eval 100 --out study.json
+
+Workload: 1024x1024 images on a 2048x2048 grid, skies of the 2048^2
+workload's source density (500 points + 12 Gaussians), one fixed array (197
+antennas at the 2048^2 workload's layout, 4 h at 60 s), cut 20 %; training
+skies and held-out skies come from disjoint seed streams of the same
+observation (synth.sky_set).
+
+Phases.
+* train: the two-step method produces the pairs -- step 1 (500 iterations)
+  gives i_L, step 2 runs `--target-iters` FP32 iterations from zero, far past
+  the 1e-6 tolerance -- in batched solves; the network is trained on them
+  (MSE, Adam) and its parameters saved (`--save-params`).
+* eval: for every held-out sky step 2 runs on the FP32 path from six starts
+  -- zero, i_L and the network's prediction, each restarted at k = 1
+  (Algorithm 1 as written) and entered at momentum index --momentum-k with
+  zero velocity -- for --horizon iterations, recording the exact objective
+  every --every iterations (warmstart.trajectory).  The reference F_ref is
+  the lowest objective any of the six runs reaches; the time to a tolerance
+  is read off each trajectory ((F - F_ref) / |F_ref| <= tol), also against
+  the lowest objective within half the horizon to show how much the metric
+  depends on it.  On the first --certify skies the FP64 path runs on with a
+  duality-gap certificate (warmstart.certified_fstar) to show where F_ref
+  sits relative to the true minimum: the FP32 iteration stalls a few 1e-5
+  above it on this workload, so tolerances are relative to what the FP32
+  path can reach.  Times are HIP event times of the iteration loops, plus
+  the network's forward pass for its starts.
+
+The output JSON holds every per-sky record and the medians and quartiles.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(f"[{time.strftime('%H:%M:%S')}]", *a, flush=True)
+
+
+def base_problem(n=1024, seed=0):
+    import synth
+    from synth.generator import SkyConfig, ArrayConfig
+
+    f = (n / 2048) ** 2
+    cfg = synth.preset("sky2048").replace(
+        n=n, sky=SkyConfig(max(2, int(2000 * f)), max(1, int(50 * f))),
+        array=ArrayConfig(197, 4.0, 60.0, layout_seed=0), cut=0.20, seed=seed)
+    return synth.make_problem(cfg, with_full=False)
+
+
+def summarize(vals):
+    v = np.asarray([x for x in vals if x is not None and x >= 0], np.float64)
+    if v.size == 0:
+        return None
+    q1, med, q3 = np.percentile(v, [25, 50, 75])
+    return {"median": float(med), "q1": float(q1), "q3": float(q3), "count": int(v.size)}
+
+
+def phase_train(args, base):
+    import torch
+    import synth
+    from paper_2406_18356_amd import UNet, unet_init_params, warmstart as ws
+
+    t0 = time.perf_counter()
+    probs = synth.sky_set(base, args.train, 1000)
+    log(f"train: {len(probs)} skies synthesised in {time.perf_counter() - t0:.1f} s")
+    t1 = time.perf_counter()
+    dh, il, b2, _ = ws.solve_pairs(probs, iters2=args.target_iters, chunk=args.chunk, log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"train: {len(probs)} pairs solved ({args.target_iters} step-2 iterations) in {t2 - t1:.1f} s")
+    net = UNet(args.batch, base.n)
+    net.set_params(unet_init_params(seed=0))
+    losses = ws.train(net, dh, il, b2, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    params = net.get_params()
+    params.cpu().numpy().astype(np.float32).tofile(args.save_params)
+    log(f"train: {args.epochs} epochs in {t3 - t2:.1f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}; "
+        f"parameters in {args.save_params}")
+    return {"image": base.n, "pairs": len(probs), "target_iters": args.target_iters, "epochs": args.epochs,
+            "batch": args.batch, "lr": args.lr, "losses": losses, "solve_pairs_s": t2 - t1, "train_s": t3 - t2}
+
+
+def phase_eval(args, base, params):
+    import torch
+    import synth
+    from paper_2406_18356_amd import Solver, UNet, warmstart as ws
+
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
+    probs = synth.sky_set(base, args.eval_start + args.eval, 2000)[args.eval_start:]
+    net = UNet(1, base.n)
+    net.set_params(params)
+    K0 = args.momentum_k
+    recs = []
+    t0 = time.perf_counter()
+    for i, p in enumerate(probs):
+        s = Solver(p.n, positivity=True)
+        dl, dh = T(p.dirty_L), T(p.dirty_H)
+        s.set_dirty_psf(1, dl, T(p.psf_L))
+        s.set_dirty_psf(2, dh, T(p.psf_H))
+        s.lipschitz(1)
+        lam1 = s.default_lambda(1, 1, 0.05)
+        _, il, _ = s.step1(lam1, 500, image=True)
+        sig2 = s.estimate_sigma2(dh)
+        s.set_filters(p.ell, p.delta, sig2, 1e-3 * sig2)
+        s.lipschitz(2)
+        lam2 = s.default_lambda(2, 1, 0.05)
+        x_net, fms = ws.timed_forward(net, dh[None].contiguous(), il[None].contiguous())
+        x_net = x_net[0].contiguous()
+        starts = {"cold": (None, 0.0), "low_res": (il, 0.0), "unet": (x_net, fms)}
+        trajs, warm = {}, {}
+        for name, (x0, wms) in starts.items():
+            trajs[name] = ws.trajectory(s, lam2, il, x0=x0, iters=args.horizon, every=args.every)
+            trajs[f"{name}_momentum_{K0}"] = ws.trajectory(s, lam2, il, x0=x0, iters=args.horizon, every=args.every,
+                                                           momentum_k=K0)
+            warm[name] = warm[f"{name}_momentum_{K0}"] = wms
+        # the reference: the best objective any of the six runs reaches within
+        # the horizon, and within half of it (the metric's dependence on it)
+        f_ref = min(min(t["F"]) for t in trajs.values())
+        half = [F for t in trajs.values() for k, F in zip(t["k"], t["F"]) if k <= args.horizon // 2]
+        f_ref_half = min(half)
+        rec = {"sky": args.eval_start + i, "f_ref": f_ref, "f_ref_half_horizon": f_ref_half,
+               "f_ref_half_rel": (f_ref_half - f_ref) / abs(f_ref)}
+        for name, t in trajs.items():
+            F0 = s.objective(2, lam2, starts[name.split("_momentum")[0]][0] if starts[name.split("_momentum")[0]][0]
+                             is not None else torch.zeros_like(dh), il)[0]
+            rec[f"{name}_initial_gap"] = (F0 - f_ref) / abs(f_ref)
+            for tol in args.tols:
+                rec[f"{name}@{tol:g}"] = ws.crossing(t, f_ref, tol, warm[name])
+                rec[f"{name}@{tol:g}_half_ref"] = ws.crossing(t, f_ref_half, tol, warm[name])
+        rec["ms_per_iter"] = trajs["cold"]["ms"][-1] / trajs["cold"]["k"][-1]
+        if i < args.certify:
+            cert = ws.certified_fstar(dl, T(p.psf_L), dh, T(p.psf_H), p.ell, p.delta, sig2, lam2, il,
+                                      chunk=args.cert_chunk, max_iters=args.cert_iters, gap_tol=args.gap_tol)
+            rec["fp64"] = {k: cert[k] for k in ("F", "gap", "rel_gap", "iters", "s")}
+            rec["fp64"]["f_ref_minus_fp64_rel"] = (f_ref - cert["F"]) / abs(cert["F"])
+        recs.append(rec)
+        log(f"eval sky {rec['sky']}: " + ", ".join(
+            f"{k} {rec[k]['iters']}" for k in rec if isinstance(rec[k], dict) and "@1e-06" in k and "half" not in k)
+            + (f"; FP64 F below f_ref by {rec['fp64']['f_ref_minus_fp64_rel']:.3g} (gap {rec['fp64']['rel_gap']:.2g})"
+               if "fp64" in rec else ""))
+        del s
+    keys = [k for k in recs[0] if isinstance(recs[0][k], dict) and "@" in k]
+    table = {k: {"ms": summarize([r[k]["ms"] for r in recs]), "iters": summarize([r[k]["iters"] for r in recs]),
+                 "converged": int(sum(r[k]["converged"] for r in recs))} for k in keys}
+    # per-sky speed-up of the network over the best non-learned start under the same entry rule
+    gain = {}
+    for tol in args.tols:
+        for suffix in ("", f"_momentum_{K0}"):
+            g = []
+            for r in recs:
+                plain = [r[f"{x}{suffix}@{tol:g}"]["ms"] for x in ("cold", "low_res")]
+                plain = [x for x in plain if x >= 0]
+                u = r[f"unet{suffix}@{tol:g}"]["ms"]
+                if plain and u > 0:
+                    g.append(1.0 - u / min(plain))
+            key = f"{'restart_k1' if not suffix else f'entered_at_{K0}'}@{tol:g}"
+            if g:
+                q1, med, q3 = np.percentile(g, [25, 50, 75])
+                gain[key] = {"median": float(med), "q1": float(q1), "q3": float(q3), "mean": float(np.mean(g)),
+                             "count": len(g), "wins": int(sum(x > 0 for x in g))}
+            else:
+                gain[key] = None
+    return {"image": base.n, "skies": len(recs), "tols": args.tols, "momentum_k": K0, "horizon": args.horizon,
+            "every": args.every, "eval_s": time.perf_counter() - t0, "table": table,
+            "network_gain_over_best_plain_start": gain, "records": recs}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--phase", choices=("train", "eval", "all"), default="all")
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--train", type=int, default=512)
+    ap.add_argument("--eval", type=int, default=100)
+    ap.add_argument("--eval-start", type=int, default=0, help="first held-out sky (to split the evaluation)")
+    ap.add_argument("--target-iters", type=int, default=40000)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--chunk", type=int, default=32)
+    ap.add_argument("--momentum-k", type=int, default=3000)
+    ap.add_argument("--horizon", type=int, default=60000, help="iterations of every recorded run")
+    ap.add_argument("--every", type=int, default=500, help="iterations between recorded objectives")
+    ap.add_argument("--tols", type=float, nargs="+", default=[1e-6, 1e-5])
+    ap.add_argument("--certify", type=int, default=4, help="held-out skies whose reference is checked on FP64")
+    ap.add_argument("--cert-iters", type=int, default=200000)
+    ap.add_argument("--cert-chunk", type=int, default=5000)
+    ap.add_argument("--gap-tol", type=float, default=1e-9)
+    ap.add_argument("--save-params", default="unet_params.f32")
+    ap.add_argument("--load-params", default=None)
+    ap.add_argument("--out", default="warmstart_study.json")
+    args = ap.parse_args(argv)
+
+    base = base_problem(args.n)
+    log(f"workload: {args.n}^2, counts {base.counts}")
+    out = {"config": vars(args)}
+    if args.phase in ("train", "all"):
+        out["train"] = phase_train(args, base)
+        params = np.fromfile(args.save_params, np.float32)
+    else:
+        params = np.fromfile(args.load_params, np.float32)
+    if args.phase in ("eval", "all"):
+        out["eval"] = phase_eval(args, base, params)
+        log("table:", json.dumps(out["eval"]["table"]))
+        log("network gain:", json.dumps(out["eval"]["network_gain_over_best_plain_start"]))
+    with open(args.out, "w") as f:
+        json.dump(out, f)
+    log(f"wrote {args.out}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
