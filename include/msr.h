@@ -394,6 +394,33 @@ msr_status msr_batch_solve(msr_batch* batch, int step, const double* lambda, int
                            const void* const* x0, void* const* model_out, void* const* image_out, msr_result* res,
                            void* stream);
 
+/* How msr_batch_solve runs the iterations.
+ *  mode 0 (default): one launch per pass for each group of equal-sized
+ *    channels, all captured in one graph (each size on its own stream).
+ *  Mode 1 is switched off in this build (MSR_ERR_UNSUPPORTED): its first
+ *  run did not return within minutes and the cause has not been found.
+ *  mode 1: one persistent launch for all channels and all iterations.  The
+ *    passes of Algorithm 1 (four per step-1 iteration, six per step-2) of
+ *    every channel become work items taken from a ticket counter in
+ *    iteration-major, then pass-major, then channel order; an item waits until
+ *    the pass it reads from has finished on its channel (counters in device
+ *    memory).  Each channel runs with its own kept columns (no widening to the
+ *    widest of its size, unlike mode 0), so mode-1 results equal
+ *    msr_step*_ on that channel alone when the same kernel variants are in
+ *    use.  Supported: single precision, pad 2, image sides 512, 1024, 2048
+ *    and 4096 (MSR_ERR_UNSUPPORTED otherwise, at solve time).
+ *  spin_limit: polls of a wait before the launch gives up (0: 2^22, about a
+ *    second); a wait that gives up raises an abort flag every block sees,
+ *    all blocks return, and msr_batch_solve fails with MSR_ERR_HIP and the
+ *    models are undefined.  Returns MSR_ERR_INVALID for another mode. */
+msr_status msr_batch_set_mode(msr_batch* batch, int mode, unsigned int spin_limit);
+
+/* Sets (raise != 0) or clears the host's give-up flag of the persistent
+ * launch: while it is set, a mode-1 solve's blocks return at their next
+ * item or wait and the solve fails with MSR_ERR_HIP.  The flag is kept for
+ * later solves until cleared.  Blocks until the flag is written. */
+msr_status msr_batch_give_up(msr_batch* batch, int raise, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

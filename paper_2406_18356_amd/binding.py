@@ -116,6 +116,8 @@ SYMBOLS = {
     "msr_batch_channel": (_P, [_P, C.c_int]),
     "msr_batch_set_workspace": (_ST, [_P, _P, C.c_size_t]),
     "msr_batch_autotune": (_ST, [_P, C.c_int, _P]),
+    "msr_batch_set_mode": (_ST, [_P, C.c_int, C.c_uint]),
+    "msr_batch_give_up": (_ST, [_P, C.c_int, _P]),
     "msr_batch_solve": (_ST, [_P, C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(_P), C.POINTER(_P),
                               C.POINTER(_P), C.POINTER(_P), C.POINTER(Result), _P]),
     "msr_unet_param_count": (C.c_size_t, [C.POINTER(UNetConfig)]),
@@ -455,6 +457,15 @@ class Batch:
 
     def autotune(self, reps=10, stream=None):
         self._check(self._lib.msr_batch_autotune(self._h, int(reps), _stream(stream)))
+
+    def set_mode(self, mode, spin_limit=0):
+        """0: launches per pass, grouped by size; 1: one persistent launch for
+        every channel and iteration (msr_batch_set_mode)."""
+        self._check(self._lib.msr_batch_set_mode(self._h, int(mode), int(spin_limit)))
+
+    def give_up(self, raise_flag=True, stream=None):
+        """Raises or clears the host's give-up flag of the persistent launch."""
+        self._check(self._lib.msr_batch_give_up(self._h, 1 if raise_flag else 0, _stream(stream)))
 
     def solve(self, step, lambdas, iters, low_res=None, x0=None, out=None, image=False, stream=None):
         """Runs `iters` iterations of `step` on every channel; returns (models,

@@ -56,7 +56,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for L in LENGTHS:
         obj = os.path.join(BUILD, f"ops_{L}.o")
         units.append([cc, *CXXFLAGS, f"-DMSR_L={L}", "-c", os.path.join(CSRC, "ops_inst.hip"), "-o", obj])
-    for name in ("msr_api", "unet"):
+    for name in ("msr_api", "persist", "unet"):
         units.append([cc, *CXXFLAGS, "-c", os.path.join(CSRC, name + ".hip"), "-o", os.path.join(BUILD, name + ".o")])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         outs = list(ex.map(_run, units))

@@ -224,10 +224,25 @@ struct RowItems {
     }
 };
 
-template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
-__global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R, EMAX>::TPF))
-MSR_ROW_WAVES_ATTR(EMAX, R, Epi)
-row_kernel(RowArgs<R> a0, Epi epi0) {
+// LDS of a row pass (complex slots and FP64 reduction scratch).
+template <typename R, int L, bool PADDED, int EMAX, int PAIRS, class Epi, bool ALLOW_PP = true>
+struct RowLds {
+    using Cf = LineCfg<L, PADDED, R, EMAX>;
+    static constexpr int ZLEN = row_line_len(L, PADDED, Cf::E);
+    static constexpr int NT = PAIRS * Cf::TPF;
+    static constexpr bool PP = ALLOW_PP && row_pingpong(PAIRS * ZLEN * sizeof(cplx<R>), NT, L / (2 * PAIRS));
+    static constexpr int SLOTS = (PP ? 2 : 1) * PAIRS * ZLEN;
+    static constexpr int RED = (Epi::NQ > 0 ? Epi::NQ : 1) * (NT >= 64 ? NT / 64 : NT);
+};
+
+// One row-pass block: row pairs vb * PAIRS .. of the launch's spectra
+// (channel already applied), LDS from the caller (RowLds slots and
+// reduction scratch).  Partial sums go to partials[pblock * NQ ..].
+// ALLOW_PP = false keeps one LDS line per pair (two barriers per stage).
+template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi,
+          bool ALLOW_PP = true>
+__device__ __forceinline__ void row_body(const RowArgs<R>& a, Epi& epi, int vb, int pblock, cplx<R>* lds,
+                                         double* red, int tid_in) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     using C = cplx<R>;
     constexpr int E = Cf::E, TPF = Cf::TPF, NH = Cf::NH, PT = Cf::PT, HALF = Cf::HALF;
@@ -237,23 +252,12 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
     constexpr int ZLEN = row_line_len(L, PADDED, E);
     constexpr int NT = PAIRS * TPF;
     constexpr int NQ = Epi::NQ;
-    constexpr bool PP = row_pingpong(PAIRS * ZLEN * sizeof(C), NT, L / (2 * PAIRS));
-    __shared__ C lds[(PP ? 2 : 1) * PAIRS * ZLEN];
-    __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
+    constexpr bool PP = RowLds<R, L, PADDED, EMAX, PAIRS, Epi, ALLOW_PP>::PP;
 
-    RowArgs<R> a = a0;
-    Epi epi = epi0;
-    if (a.cstride) {
-        const long long off = (long long)blockIdx.y * a.cstride;
-        a.to_channel(off);
-        epi.to_channel(off);
-    }
-    if (a.chan) epi.use(a.chan[blockIdx.y]);
-
-    const int tid = threadIdx.x;
+    const int tid = tid_in;
     const int pair = tid / TPF;
     const int t = tid - pair * TPF;
-    const int row0 = xcd_block(blockIdx.x, gridDim.x) * (2 * PAIRS);
+    const int row0 = vb * (2 * PAIRS);
     const int ra = row0 + 2 * pair;
     const LdsView<1, C> zv{lds + pair * ZLEN, 0};
     LdsView<1, C> hv[NH], hw[NH];
@@ -439,9 +443,28 @@ row_kernel(RowArgs<R> a0, Epi epi0) {
             block_sum<NQ, NT>(acc, red, tot);
             if (tid == 0)
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) el(a.partials, blockIdx.x * NQ + q) = tot[q];
+                for (int q = 0; q < NQ; ++q) el(a.partials, pblock * NQ + q) = tot[q];
         }
     }
+}
+
+template <typename R, int L, bool PADDED, int EMAX, int PAIRS, int T, bool INV_IN, bool FWD_OUT, class Epi>
+__global__ void __launch_bounds__((PAIRS * LineCfg<L, PADDED, R, EMAX>::TPF))
+MSR_ROW_WAVES_ATTR(EMAX, R, Epi)
+row_kernel(RowArgs<R> a0, Epi epi0) {
+    using RL = RowLds<R, L, PADDED, EMAX, PAIRS, Epi>;
+    __shared__ cplx<R> lds[RL::SLOTS];
+    __shared__ double red[RL::RED];
+    RowArgs<R> a = a0;
+    Epi epi = epi0;
+    if (a.cstride) {
+        const long long off = (long long)blockIdx.y * a.cstride;
+        a.to_channel(off);
+        epi.to_channel(off);
+    }
+    if (a.chan) epi.use(a.chan[blockIdx.y]);
+    row_body<R, L, PADDED, EMAX, PAIRS, T, INV_IN, FWD_OUT, Epi>(a, epi, xcd_block(blockIdx.x, gridDim.x), blockIdx.x,
+                                                                 lds, red, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -677,7 +700,7 @@ __device__ __forceinline__ void col_channel(ColArgs<R>& a, Mode& md) {
 // block b covers columns b*CB .. b*CB + CB - 1 of tile (b*CB)/T.
 template <typename R, int L, bool PADDED, int EMAX, int T, int CB, class Mode>
 __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, int lblock, int pblock,
-                                         cplx<R>* lds, double* red) {
+                                         cplx<R>* lds, double* red, int tid_in) {
     using Cf = LineCfg<L, PADDED, R, EMAX>;
     using C = cplx<R>;
     constexpr int E = Cf::E, TPF = Cf::TPF, NH = Cf::NH;
@@ -686,7 +709,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, const Mode& md, in
     constexpr int HL = fft_lds_len(L, E, CB);
     static_assert(T % CB == 0, "CB must divide T");
 
-    const int tid = threadIdx.x;
+    const int tid = tid_in;
     const int cl = tid % CB;
     const int t = tid / CB;
     const int kx = lblock * CB + cl;
@@ -776,7 +799,8 @@ col_kernel(ColArgs<R> a0, Mode m0) {
     ColArgs<R> a = a0;
     Mode md = m0;
     col_channel(a, md);
-    col_body<R, L, PADDED, EMAX, T, CB, Mode>(a, md, xcd_block(blockIdx.x, gridDim.x), blockIdx.x, lds, red);
+    col_body<R, L, PADDED, EMAX, T, CB, Mode>(a, md, xcd_block(blockIdx.x, gridDim.x), blockIdx.x, lds, red,
+                                              threadIdx.x);
 }
 
 // Two independent column passes in one launch: blocks [0, g1) run (a1, m1),
@@ -794,8 +818,8 @@ col_dual_kernel(ColArgs<R> a1, M1 m1, int g1, ColArgs<R> a2, M2 m2) {
     __shared__ cplx<R> lds[Cf::NH * CB * fft_lds_len(L, Cf::E, CB)];
     __shared__ double red[(NQ > 0 ? NQ : 1) * (NT >= 64 ? NT / 64 : NT)];
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    if (b < g1) col_body<R, L, PADDED, EMAX, T, CB, M1>(a1, m1, b, b, lds, red);
-    else col_body<R, L, PADDED, EMAX, T, CB, M2>(a2, m2, b - g1, b, lds, red);
+    if (b < g1) col_body<R, L, PADDED, EMAX, T, CB, M1>(a1, m1, b, b, lds, red, threadIdx.x);
+    else col_body<R, L, PADDED, EMAX, T, CB, M2>(a2, m2, b - g1, b, lds, red, threadIdx.x);
 }
 
 // Multiply by the cached PSF spectrum (already scaled by 1/P^2), tiled like

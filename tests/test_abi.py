@@ -99,8 +99,9 @@ def test_batch_workspace_bytes_host_only(lib):
 
     one = {n: binding.workspace_bytes(n) for n in (64, 128, 256)}
     tot = ws([256, 64, 128, 64])
-    # every channel's own workspace plus a small per-channel parameter area
-    assert sum(one[n] for n in (256, 64, 128, 64)) <= tot <= sum(one[n] for n in (256, 64, 128, 64)) + 4 * 4096
+    # every channel's own workspace plus a small per-channel area (parameters
+    # and the persistent launch's pass descriptors)
+    assert sum(one[n] for n in (256, 64, 128, 64)) <= tot <= sum(one[n] for n in (256, 64, 128, 64)) + 4 * 16384
     assert ws([64]) >= one[64]
     assert ws([]) == 0
     assert ws([64, 12]) == 0  # one invalid channel
