@@ -44,10 +44,13 @@ struct LineCfg {
 // XCD b % 8), and each XCD has its own L2.  Remapping the block index so that
 // consecutive logical blocks run on the same XCD lets neighbours share the L2
 // lines of the tiled spectra (a 128-byte line holds several rows of a tile).
+// XCD x runs blocks x, x + 8, ...: q + 1 of them for x < r and q for the
+// others (nblocks = 8 q + r); they take the logical range starting at
+// x q + min(x, r), so the map is a bijection for any grid size.
 __device__ __forceinline__ int xcd_block(int b, int nblocks) {
     constexpr int NX = 8;
-    if (nblocks % NX) return b;
-    return (b % NX) * (nblocks / NX) + b / NX;
+    const int q = nblocks / NX, r = nblocks % NX, x = b % NX;
+    return x * q + (x < r ? x : r) + b / NX;
 }
 
 __device__ __forceinline__ uint32_t spec_idx(int kx, int row, int NR, int T) {
