@@ -81,11 +81,21 @@ __device__ __forceinline__ bf16x8 im2col8(const ConvIn<T>& in, int H, int W, int
 
 // ---------------------------------------------------------------------------
 // 3x3 convolution as an implicit GEMM: D[p][co] = sum_k A[p][k] W[co][k],
-// A = im2col of the input.  Block: 128 pixels x 64 output channels, 4 waves
-// of 32 pixels x 64 channels (two 32x32 MFMA tiles each); K staged through LDS
-// 32 at a time.
+// A = im2col of the input, k = tap * cin + ci.  A block computes an 8 x 16
+// pixel tile of one image for 64 output channels; its 4 waves take two tile
+// rows (32 pixels) x 64 channels each (two 32x32 MFMA tiles).  The input is
+// staged 32 channels at a time as the 10 x 18 halo tile around the output
+// tile (zero outside the image), once per chunk, so each of the nine taps of
+// a chunk reads its A operand from LDS at a shifted pixel: no per-step
+// index arithmetic or bounds checks.  The weights of one (chunk, tap) step
+// (64 x 32) go through a second double buffer, loaded one step ahead.
 // ---------------------------------------------------------------------------
-constexpr int CBM = 128, CBN = 64, CBK = 32, CLD = CBK + 8;
+constexpr int CBK = 32, CLD = CBK + 8;
+constexpr int TR = 8, TC = 16, HR = TR + 2, HC = TC + 2;  // output tile, halo tile
+constexpr int NHALO = HR * HC;                             // 180 halo pixels
+constexpr int HLD = CBK + 8;                               // bf16 per halo pixel in LDS (80 B: spreads the banks)
+constexpr int HITEMS = NHALO * (CBK / 8);                  // 16-byte groups of one halo chunk
+constexpr int HPT = (HITEMS + 255) / 256;                  // ... per thread
 
 struct ConvOut {
     int B, H, W;
@@ -104,97 +114,163 @@ struct ConvOut {
     int split, acc2;
 };
 
-template <typename T, bool BWD>
+// Output tiles of a layer (grid x of the convolution).
+__host__ __device__ inline int conv_tiles(int B, int H, int W) { return B * ((H + TR - 1) / TR) * ((W + TC - 1) / TC); }
+
+// Channels [ci, ci + 8) of input pixel (b, sy, sx); zero outside the image or
+// beyond the input's channels (ci is a multiple of 8, and so is c1).
+template <typename T>
+__device__ __forceinline__ bf16x8 pixel8(const ConvIn<T>& in, int cin, int H, int W, int b, int sy, int sx, int ci) {
+    if (ci >= cin || sy < 0 || sy >= H || sx < 0 || sx >= W) return zero8();
+    if (ci < in.c1) {
+        const int h = H >> in.up1, w = W >> in.up1;
+        return load8(in.x1 + (((size_t)b * h + (sy >> in.up1)) * w + (sx >> in.up1)) * in.c1 + ci);
+    }
+    return load8(in.x2 + (((size_t)b * H + sy) * W + sx) * in.c2 + (ci - in.c1));
+}
+
+// NT 32-channel output tiles per wave (1 for layers of at most 32 output
+// channels, else 2); the weights of a step are fetched WD steps ahead.
+constexpr int WD = 3;
+
+// ONE: the input has at most 32 channels (one chunk, one halo buffer: half
+// the LDS, so twice the resident blocks to cover the load latency).
+template <typename T, bool BWD, int NT, bool ONE>
 __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
-    // two LDS buffers: step i computes from one while step i + 1's operands,
-    // loaded into registers before step i's MFMAs, go into the other
-    __shared__ __attribute__((aligned(16))) bf16 As[2][CBM * CLD];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[2][CBN * CLD];
+    constexpr int BN = 32 * NT;  // output channels of a block
+    __shared__ __attribute__((aligned(16))) bf16 Hs[ONE ? 1 : 2][NHALO * HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * CLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int P = o.B * o.H * o.W;
-    const int p0 = blockIdx.x * CBM, n0 = blockIdx.y * CBN;
+    const int tiles_x = (o.W + TC - 1) / TC, tiles_y = (o.H + TR - 1) / TR;
+    const int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, b = blockIdx.x / (tiles_x * tiles_y);
+    const int y0 = ty * TR, x0 = tx * TC, n0 = blockIdx.y * BN;
+    const int cin = in.c1 + in.c2;
+    const int nsteps = 9 * ((cin + CBK - 1) / CBK);  // (chunk, tap) steps, a multiple of WD
 
-    // the two A groups of this thread: pixel p0 + q/4, k offset 8 (q % 4)
-    int pb[2], py[2], px[2];
-    bool pv[2];
+    // halo items of this thread: pixel q / 4 of the halo tile, channels 8 (q % 4) of the chunk
+    bf16x8 rh[HPT];
+    auto fetch_halo = [&](int c0) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int q = tid + u * 256;
-        const int p = p0 + q / 4;
-        pv[u] = p < P;
-        const int hw = o.H * o.W;
-        pb[u] = pv[u] ? p / hw : 0;
-        const int r = pv[u] ? p - pb[u] * hw : 0;
-        py[u] = r / o.W;
-        px[u] = r - py[u] * o.W;
-    }
+        for (int u = 0; u < HPT; ++u) {
+            const int q = tid + u * 256;
+            const int hp = q >> 2;
+            rh[u] = q < HITEMS ? pixel8(in, cin, o.H, o.W, b, y0 - 1 + hp / HC, x0 - 1 + hp % HC, c0 + (q & 3) * 8)
+                               : zero8();
+        }
+    };
+    auto stage_halo = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < HPT; ++u) {
+            const int q = tid + u * 256;
+            if (q < HITEMS) *reinterpret_cast<bf16x8*>(&Hs[buf][(q >> 2) * HLD + (q & 3) * 8]) = rh[u];
+        }
+    };
+    // weights of step s = chunk * 9 + tap: row co, k = tap * cin + chunk * 32 + [0, 32);
+    // WD steps in flight, in registers
     const int bco = n0 + tid / 4, bg = (tid % 4) * 8;
-    bf16x8 ra[2], rb;
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int q = tid + u * 256;
-            ra[u] = pv[u] ? im2col8(in, o.H, o.W, pb[u], py[u], px[u], k0 + (q % 4) * 8) : zero8();
-        }
-        rb = bco < o.cout ? load8(o.w + (size_t)bco * o.kpad + k0 + bg) : zero8();
+    const bool bthr = tid < 4 * BN;
+    bf16x8 rb[WD];
+    auto fetch_w = [&](int st, bf16x8& r) {
+        const int c = st / 9, t = st - 9 * c;
+        const int ci = c * CBK + bg;
+        r = (bthr && st < nsteps && bco < o.cout && ci < cin) ? load8(o.w + (size_t)bco * o.kpad + t * cin + ci)
+                                                               : zero8();
     };
-    auto stage = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int q = tid + u * 256;
-            *reinterpret_cast<bf16x8*>(&As[buf][(q / 4) * CLD + (q % 4) * 8]) = ra[u];
-        }
-        *reinterpret_cast<bf16x8*>(&Bs[buf][(tid / 4) * CLD + bg]) = rb;
+    auto stage_w = [&](int buf, const bf16x8& r) {
+        if (bthr) *reinterpret_cast<bf16x8*>(&Bs[buf][(tid / 4) * CLD + bg]) = r;
     };
 
-    f32x16 acc0 = {}, acc1 = {};
-    fetch(0);
-    stage(0);
-    __syncthreads();
-    int cur = 0;
-    for (int k0 = 0; k0 < o.kpad; k0 += CBK) {
-        const bool more = k0 + CBK < o.kpad;
-        if (more) fetch(k0 + CBK);  // in flight during this step's MFMAs
+    // A operand rows of this lane: tile pixel (2 wave + (l >> 4), l & 15), l = lane & 31
+    const int pl = lane & 31;
+    const int hbase = (2 * wave + (pl >> 4) + 1) * HC + (pl & 15) + 1;  // halo index of the pixel itself
+    const int ko = (lane >> 5) * 8;
+
+    f32x16 acc[NT];
 #pragma unroll
-        for (int kk = 0; kk < CBK; kk += 16) {
-            const int ko = kk + (lane >> 5) * 8;
-            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&As[cur][(wave * 32 + (lane & 31)) * CLD + ko]);
-            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[cur][(lane & 31) * CLD + ko]);
-            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[cur][(32 + (lane & 31)) * CLD + ko]);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
+    for (int j = 0; j < NT; ++j) acc[j] = f32x16{};
+    fetch_halo(0);
+    fetch_w(0, rb[0]);
+    stage_halo(0);
+    stage_w(0, rb[0]);
+#pragma unroll
+    for (int d = 1; d < WD; ++d) fetch_w(d, rb[d]);
+    __syncthreads();
+    int hcur = 0;
+    // steps st = s0 + j, j < WD: register slot j holds step st + 1's weights
+    // at the top of step st (for j = WD - 1, slot 0 receives step st + WD)
+    for (int s0 = 0; s0 < nsteps; s0 += WD) {
+#pragma unroll
+        for (int j = 0; j < WD; ++j) {
+            const int st = s0 + j;
+            const int t = st % 9;
+            const int cur = st & 1;
+            const bool more = st + 1 < nsteps;
+            if (!ONE && t == 0 && st + 9 < nsteps) fetch_halo((st / 9 + 1) * CBK);  // the next chunk, in registers
+            const int hp = hbase + (t / 3 - 1) * HC + (t % 3 - 1);
+#pragma unroll
+            for (int kk = 0; kk < CBK; kk += 16) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(&Hs[hcur][hp * HLD + kk + ko]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Bs[cur][(32 * n + pl) * CLD + kk + ko]);
+                    acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[n], 0, 0, 0);
+                }
+            }
+            // the other buffers were last read in the previous step (weights)
+            // or chunk (halo), which every thread finished before the barrier
+            // that ended it
+            const int nxt = (j + 1) % WD;  // slot of step st + 1
+            if (more) stage_w(cur ^ 1, rb[nxt]);
+            fetch_w(st + WD, rb[j]);            // slot j is free again: step st + WD
+            if constexpr (!ONE) {
+                if (t == 8 && more) stage_halo(hcur ^ 1);
+            }
+            __syncthreads();
+            if (!ONE && t == 8) hcur ^= 1;
         }
-        // the other buffer was last read in the previous step, which every
-        // thread finished before the barrier that ended it
-        if (more) stage(cur ^ 1);
-        __syncthreads();
-        cur ^= 1;
     }
 
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        const int co = n0 + nt * 32 + (lane & 31);
+    for (int nt = 0; nt < NT; ++nt) {
+        const int co = n0 + nt * 32 + pl;
         if (co >= o.cout) continue;
         const float bias = o.bias ? o.bias[co] : 0.0f;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int p = p0 + wave * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-            if (p >= P) continue;
-            const float v = (nt == 0 ? acc0[r] : acc1[r]) + bias;
+            const int q = wave * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);  // tile pixel
+            const int y = y0 + (q >> 4), x = x0 + (q & 15);
+            if (y >= o.H || x >= o.W) continue;
+            const size_t p = ((size_t)b * o.H + y) * o.W + x;
+            const float v = acc[nt][r] + bias;
             if constexpr (!BWD) {
-                o.y[(size_t)p * o.cout + co] = (bf16)(o.relu ? fmaxf(v, 0.0f) : v);
+                o.y[p * o.cout + co] = (bf16)(o.relu ? fmaxf(v, 0.0f) : v);
             } else {
                 if (co < o.split) {
-                    const size_t i = (size_t)p * o.split + co;
+                    const size_t i = p * o.split + co;
                     o.g1[i] = (o.m1 && !((float)o.m1[i] > 0.0f)) ? 0.0f : v;
                 } else {
                     const int l2 = o.cout - o.split;
-                    const size_t i = (size_t)p * l2 + (co - o.split);
+                    const size_t i = p * l2 + (co - o.split);
                     const float g = (o.m2 && !((float)o.m2[i] > 0.0f)) ? 0.0f : v;
                     o.g2[i] = o.acc2 ? o.g2[i] + g : g;
                 }
             }
         }
+    }
+}
+
+// Launches the convolution with the output-channel blocking of `cout`.
+template <typename T, bool BWD>
+void launch_conv(const ConvIn<T>& in, const ConvOut& o, hipStream_t s) {
+    const unsigned tiles = (unsigned)conv_tiles(o.B, o.H, o.W);
+    const bool one = in.c1 + in.c2 <= CBK;
+    if (o.cout <= 32) {
+        if (one) hipLaunchKernelGGL((conv3x3_kernel<T, BWD, 1, true>), dim3(tiles, 1), dim3(256), 0, s, in, o);
+        else hipLaunchKernelGGL((conv3x3_kernel<T, BWD, 1, false>), dim3(tiles, 1), dim3(256), 0, s, in, o);
+    } else {
+        const dim3 g(tiles, (o.cout + 63) / 64);
+        if (one) hipLaunchKernelGGL((conv3x3_kernel<T, BWD, 2, true>), g, dim3(256), 0, s, in, o);
+        else hipLaunchKernelGGL((conv3x3_kernel<T, BWD, 2, false>), g, dim3(256), 0, s, in, o);
     }
 }
 
@@ -772,9 +848,7 @@ struct Run {
         o.bias = params() + l.b_off;
         o.y = act(i);
         o.relu = 1;
-        const int P = np(l.level);
-        hipLaunchKernelGGL((conv3x3_kernel<bf16, false>), dim3((P + CBM - 1) / CBM, (l.cout + CBN - 1) / CBN), dim3(256),
-                           0, s, input(i), o);
+        launch_conv<bf16, false>(input(i), o, s);
         ULAUNCH(u);
         return MSR_OK;
     }
@@ -856,9 +930,7 @@ struct Run {
         o.m2 = m2;
         o.split = l.c1;
         o.acc2 = acc2;
-        const int P = np(l.level);
-        hipLaunchKernelGGL((conv3x3_kernel<float, true>), dim3((P + CBM - 1) / CBM, (l.cin + CBN - 1) / CBN), dim3(256),
-                           0, s, in, o);
+        launch_conv<float, true>(in, o, s);
         ULAUNCH(u);
         return MSR_OK;
     }

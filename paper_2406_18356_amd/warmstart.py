@@ -11,6 +11,7 @@ tensors between those calls.
 from __future__ import annotations
 
 import json
+import os
 import time
 
 import numpy as np
@@ -175,6 +176,22 @@ def certified_fstar(dirty_L, psf_L, dirty_H, psf_H, ell, delta, sigma2, lam, low
             break
     rec["beta"] = beta
     return rec
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+
+def load_weights(name="unet_w32_l4_1024"):
+    """Parameters of a trained warm-start network stored with the package
+    (bfloat16, the order of UNet.get_params) as float32, and their record
+    (how and on what they were trained).  None if the file is absent."""
+    path = os.path.join(WEIGHTS, name + ".bf16")
+    if not os.path.exists(path):
+        return None, None
+    raw = np.fromfile(path, dtype="<u2").astype(np.uint32) << 16
+    with open(os.path.join(WEIGHTS, name + ".json")) as f:
+        meta = json.load(f)
+    return raw.view(np.float32), meta
 
 
 # --------------------------------------------------------------------------

@@ -201,7 +201,8 @@ def main(argv=None):
     ap.add_argument("--cert-chunk", type=int, default=5000)
     ap.add_argument("--gap-tol", type=float, default=1e-9)
     ap.add_argument("--save-params", default="unet_params.f32")
-    ap.add_argument("--load-params", default=None)
+    ap.add_argument("--load-params", default=None,
+                    help="float32 parameter file, or 'packaged' for the network stored with the package")
     ap.add_argument("--out", default="warmstart_study.json")
     args = ap.parse_args(argv)
 
@@ -211,6 +212,10 @@ def main(argv=None):
     if args.phase in ("train", "all"):
         out["train"] = phase_train(args, base)
         params = np.fromfile(args.save_params, np.float32)
+    elif args.load_params == "packaged":
+        from paper_2406_18356_amd import warmstart as ws
+
+        params, _ = ws.load_weights()
     else:
         params = np.fromfile(args.load_params, np.float32)
     if args.phase in ("eval", "all"):

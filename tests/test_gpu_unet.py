@@ -1,8 +1,10 @@
 """The learned warm start on the GPU (msr_unet_*): forward pass, loss and
 every parameter gradient against the FP64 oracle -- with no rounding at all
-for the check of record (the production network at 128^2), and, as a
-secondary check of accumulation order, against the oracle that rounds the
-same tensors to bfloat16 as the library stores -- and the Adam step."""
+for the checks of record (the forward pass at 32^2 to 128^2 with a bar set by
+what bfloat16 storage alone does to the output, the production network's
+gradients at 128^2), and, as a secondary check of accumulation order,
+against the oracle that rounds the same tensors to bfloat16 as the library
+stores -- and the Adam step."""
 import numpy as np
 import pytest
 
@@ -10,7 +12,15 @@ from oracle import unet as ou
 
 pytestmark = pytest.mark.gpu
 
-FWD_TOL = 1e-2   # warm start, max-abs error over the oracle's peak (bf16 storage, FP32 vs FP64 sums)
+# Warm start, max-abs error over the oracle's peak.  The check of record is
+# against the plain FP64 oracle: the library stores every activation in
+# bfloat16, which by itself moves the output by d = the distance between the
+# oracle that rounds those tensors and the plain one (0.9-1.6e-2 at these
+# sizes); the GPU may be at most FWD_FACTOR d + FWD_ABS from the plain oracle.
+# Against the rounding oracle the difference is FP32 accumulation order
+# flipping bf16 roundings, at most FWD_TOL.
+FWD_FACTOR, FWD_ABS = 1.5, 1e-3
+FWD_TOL = 2e-2
 GRAD_TOL = 1e-2  # each parameter block, max-abs error over that block's peak
 
 
@@ -66,14 +76,19 @@ def rel(a, b):
     return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / max(float(np.max(np.abs(b))), 1e-30))
 
 
-@pytest.mark.parametrize("n,B,levels", [(32, 2, 4), (48, 1, 3), (64, 3, 4)])
+@pytest.mark.parametrize("n,B,levels", [(32, 2, 4), (48, 1, 3), (64, 3, 4), (128, 1, 4)])
 def test_forward_matches_oracle(torch_dev, n, B, levels):
     print(f"unet forward n={n} B={B} levels={levels}", flush=True)
     net, p = _net(torch_dev, B, n, levels=levels)
     dh, low, _ = _batch(n, B, seed=n)
     x0 = net.forward(_t(torch_dev, dh), _t(torch_dev, low)).cpu().numpy()
+    plain = ou.warm_start(p.astype(np.float64), dh, low, 32, levels)
     ref = ou.warm_start(p.astype(np.float64), dh, low, 32, levels, rnd=ou.bf16)
+    d = rel(ref, plain)
+    print(f"error vs plain FP64 {rel(x0, plain):.4g} (bf16 storage alone: {d:.4g}), "
+          f"vs the rounding oracle {rel(x0, ref):.4g}", flush=True)
     assert np.all(x0 >= 0)
+    assert rel(x0, plain) <= FWD_FACTOR * d + FWD_ABS, (rel(x0, plain), d)
     assert rel(x0, ref) <= FWD_TOL, rel(x0, ref)
 
 
