@@ -7,6 +7,8 @@
         --pass NAME SUBSTRING I [--pass ...]
     python -m paper_2406_18356_amd.prof_summary counters DIR PREFIX OUT.txt --command "..." \
         --pass NAME SUBSTRING I [--pass ...]
+    python -m paper_2406_18356_amd.prof_summary mfma DIR PREFIX OUT.txt --command "..." \
+        --group NAME SUBSTRING [--group ...]
 
 ``stats`` condenses ``<PREFIX>_kernel_stats.csv`` (rocprofv3 --kernel-trace
 --stats --output-format csv) into a table.  ``traffic`` reads two --pmc runs
@@ -190,6 +192,40 @@ def counters(d, prefix, out, command, specs):
     return out
 
 
+# one 32x32x16 bf16 MFMA instruction: 32768 flops, 512 of them per MOP
+MOP_FLOPS = 512
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def mfma(d, prefix, out, command, specs):
+    """Matrix-core use per kernel group (one --pmc run of
+    SQ_INSTS_VALU_MFMA_MOPS_BF16, SQ_VALU_MFMA_BUSY_CYCLES,
+    SQ_INSTS_VALU_MFMA_BF16 and GRBM_GUI_ACTIVE): MFMA busy cycles over the
+    SIMD cycles of the group's dispatches, and its counted bf16 MFMA flops
+    per second of GPU-active time against the dense peak."""
+    names = ("GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_INSTS_VALU_MFMA_BF16")
+    per = {n: _per_dispatch(d, prefix, n) for n in names}
+    lines = ["# rocprofv3 MFMA counters per kernel group (sums over every matching dispatch)", f"# command: {command}",
+             "", f"{'group':22s} {'dispatches':>10s} {'mfma_insts':>11s} {'tflop':>9s} {'active_ms':>10s} "
+                 f"{'mfma_busy':>9s} {'tflop/s':>8s} {'of_peak':>7s}"]
+    for name, sub in specs:
+        v = {}
+        for n in names:
+            ds = _pick(per[n], sub, "Kernel_Name")
+            if not ds:
+                raise SystemExit(f"no dispatch matching {sub!r} for {n}")
+            v[n] = sum(r["value"] for r in ds)
+            v["n"] = len(ds)
+        cyc = v["GRBM_GUI_ACTIVE"] / XCDS
+        busy = v["SQ_VALU_MFMA_BUSY_CYCLES"] / (SIMDS * cyc)
+        fl = v["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * MOP_FLOPS
+        secs = cyc / (CLOCK_GHZ * 1e9)
+        lines.append(f"{name:22s} {v['n']:10d} {v['SQ_INSTS_VALU_MFMA_BF16']:11.4g} {fl / 1e12:9.3f} "
+                     f"{secs * 1e3:10.2f} {busy:9.3f} {fl / secs / 1e12:8.1f} {fl / secs / 1e12 / BF16_PEAK_TFLOPS:7.3f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    return out
+
+
 def traffic(d, fprefix, wprefix, out, kernel, alg_bytes, copy_bytes, command, segment):
     fr = _per_dispatch(d, fprefix, "FETCH_SIZE")
     wr = _per_dispatch(d, wprefix, "WRITE_SIZE")
@@ -245,8 +281,16 @@ def main(argv=None):
     c.add_argument("--command", required=True)
     c.add_argument("--pass", dest="specs", nargs=3, action="append", required=True,
                    metavar=("NAME", "SUBSTRING", "SEGMENT"))
+    m = sub.add_parser("mfma")
+    m.add_argument("dir")
+    m.add_argument("prefix")
+    m.add_argument("out")
+    m.add_argument("--command", required=True)
+    m.add_argument("--group", dest="specs", nargs=2, action="append", required=True, metavar=("NAME", "SUBSTRING"))
     a = ap.parse_args(argv)
-    if a.cmd == "counters":
+    if a.cmd == "mfma":
+        print(mfma(a.dir, a.prefix, a.out, a.command, a.specs))
+    elif a.cmd == "counters":
         print(counters(a.dir, a.prefix, a.out, a.command, a.specs))
     elif a.cmd == "stats":
         print(stats(a.dir, a.prefix, a.out, a.command))

@@ -104,3 +104,28 @@ def test_a_run_without_marker_copies_is_refused(tmp_path):
     with pytest.raises(SystemExit):
         ps.passes(str(tmp_path), "p", str(tmp_path / "o.txt"), "cmd", [("k", "k", "0")])
     assert not os.path.exists(tmp_path / "o.txt")
+
+
+def test_mfma_use_per_group(tmp_path):
+    """Busy cycles over SIMD cycles (GRBM_GUI_ACTIVE summed over the 8 XCDs)
+    and counted flops (512 per MOP) over GPU-active time; the first dispatch
+    of each group is dropped as the warm launch."""
+    rows, d = [], 0
+    # per dispatch: GRBM = 8 x 2.4e6 cycles (1 ms), 1.6e6 MFMA instructions of 32 busy cycles
+    for name in ["conv3x3_kernelIDF16bLb0E"] * 3 + ["conv3x3_wgrad_kernelIDF16b"] * 2:
+        for cname, v in (("GRBM_GUI_ACTIVE", 8 * 2.4e6), ("SQ_INSTS_VALU_MFMA_BF16", 1.6e6),
+                         ("SQ_INSTS_VALU_MFMA_MOPS_BF16", 64 * 1.6e6), ("SQ_VALU_MFMA_BUSY_CYCLES", 32 * 1.6e6)):
+            rows.append({"Dispatch_Id": d, "Kernel_Name": name, "Grid_Size": 256, "Counter_Name": cname,
+                         "Counter_Value": v})
+        d += 1
+    _write(tmp_path / "m_counter_collection.csv",
+           ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"], rows)
+    out = tmp_path / "mfma.txt"
+    ps.mfma(str(tmp_path), "m", str(out), "cmd", [("fwd", "conv3x3_kernelIDF16b"), ("wgrad", "wgrad_kernel")])
+    fwd = next(ln for ln in out.read_text().splitlines() if ln.startswith("fwd")).split()
+    assert fwd[1] == "2"                                   # two timed dispatches
+    assert float(fwd[3]) == pytest.approx(2 * 1.6e6 * 32768 / 1e12, abs=5e-4)  # TFLOP, printed to 3 places
+    assert float(fwd[4]) == pytest.approx(2.0, rel=1e-3)   # active ms
+    busy = 2 * 32 * 1.6e6 / (1024 * 2 * 2.4e6)
+    assert float(fwd[5]) == pytest.approx(busy, abs=1e-3)
+    assert float(fwd[7]) == pytest.approx(2 * 1.6e6 * 32768 / 2e-3 / 1e12 / 2500, abs=1e-3)
