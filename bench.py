@@ -91,7 +91,11 @@ def batch_bench(torch, dev, count, iters, seed=4, sizes=(512, 1024, 2048, 4096))
 
     t = time.perf_counter()
     cfgs = synth.channel_set(count, sizes=sizes, seed=seed)
-    prs = [synth.make_problem(c, with_full=False) for c in cfgs]
+    prs = []
+    for i, c in enumerate(cfgs):
+        prs.append(synth.make_problem(c, with_full=False))
+        if (i + 1) % 8 == 0 or i + 1 == len(cfgs):
+            log(f"batch: {i + 1}/{len(cfgs)} channels generated")
     log(f"batch: {count} channels {[p.n for p in prs]} generated in {time.perf_counter() - t:.1f} s")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
     b = Batch([p.n for p in prs], positivity=True)
@@ -263,6 +267,7 @@ def psnr_study(torch, cycles=5, iters=100):
                 row["psnr_model" + tag] = psnr(rep["model"].cpu().numpy(), pr.sky)
                 row["ms" + tag] = rep["step1_ms"] + rep["step2_ms"]
             rows.append(row)
+            log(f"partition study: ell {ell} delta {delta} done")
     return {"workload": "paper-shaped 512^2 sky, 64 antennas 4 h at 120 s, natural weighting, "
                         f"{cycles} major cycles x {iters} FISTA iterations per step, positivity on; "
                         "two-step with eta2 = 1e-3 sigma2_hat (the paper's estimate) and with eta2 = sigma2_hat; "
@@ -381,8 +386,13 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-unet", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
+    ap.add_argument("--psnr-iters", type=int, default=100,
+                    help="FISTA iterations per major cycle and step in the partition study")
+    ap.add_argument("--psnr-only", action="store_true", help="run only the partition study and print it")
     ap.add_argument("--no-dict", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=8)
+    ap.add_argument("--batch-sizes", type=int, nargs="+", default=[512, 1024, 2048, 4096],
+                    help="image sizes the batch's channels are drawn from")
     ap.add_argument("--batch-replicas", type=int, default=0, metavar="C",
                     help="also batch C copies of the workload's problem (about 1.5 GiB of HBM each at 4096^2)")
     ap.add_argument("--ttt-horizon", type=int, default=24000,
@@ -414,6 +424,13 @@ def main(argv=None):
     import torch
     import synth
     from paper_2406_18356_amd import Solver
+
+    if args.psnr_only:
+        t = time.perf_counter()
+        rep = psnr_study(torch, iters=args.psnr_iters)
+        rep["wall_s"] = time.perf_counter() - t
+        print(json.dumps({"partition_study": rep}), flush=True)
+        return 0
 
     preset, desc = WORKLOADS[args.size]
     cfg = synth.preset(preset)
@@ -662,7 +679,7 @@ def main(argv=None):
 
     batch = None
     if not args.no_batch:
-        batch = batch_bench(torch, dev, args.batch_channels, iters)
+        batch = batch_bench(torch, dev, args.batch_channels, iters, sizes=tuple(args.batch_sizes))
         log("batch:", json.dumps(batch))
 
     dictionary = None
@@ -679,7 +696,7 @@ def main(argv=None):
 
     psnr = None
     if not args.no_psnr:
-        psnr = psnr_study(torch)
+        psnr = psnr_study(torch, iters=args.psnr_iters)
         log("partition study:", json.dumps(psnr))
 
     cpu = None
