@@ -625,6 +625,10 @@ def main(argv=None):
             x0 = starts[base][0]
             F0 = s.objective(2, lam2, x0 if x0 is not None else torch.zeros_like(iL), iL)[0]
             ttt[name] = {f"{tol:g}": ws.crossing(t, f_ref, tol, starts[base][1]) for tol in tols}
+            # the same against the reference of half the horizon: how much the
+            # metric depends on the reference run's length
+            ttt[name].update({f"{tol:g}_half_horizon_ref": ws.crossing(t, f_half, tol, starts[base][1])
+                              for tol in tols})
             ttt[name]["initial_rel_gap"] = (F0 - f_ref) / abs(f_ref)
         if "unet" in starts:
             # the network against the best non-learned start under the same entry rule
