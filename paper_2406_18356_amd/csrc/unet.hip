@@ -91,8 +91,13 @@ __device__ __forceinline__ bf16x8 im2col8(const ConvIn<T>& in, int H, int W, int
 // (64 x 32) go through a second double buffer, loaded one step ahead.
 // ---------------------------------------------------------------------------
 constexpr int CBK = 32, CLD = CBK + 8;
-constexpr int TR = 8, TC = 16, HR = TR + 2, HC = TC + 2;  // output tile, halo tile
-constexpr int NHALO = HR * HC;                             // 180 halo pixels
+#ifndef MSR_UNET_WAVE_ROWS
+#define MSR_UNET_WAVE_ROWS 2
+#endif
+constexpr int WROWS = MSR_UNET_WAVE_ROWS;                  // tile rows of a wave: 32 pixels per two rows
+constexpr int MT = WROWS / 2;                              // 32-pixel MFMA tiles per wave
+constexpr int TR = 4 * WROWS, TC = 16, HR = TR + 2, HC = TC + 2;  // output tile, halo tile
+constexpr int NHALO = HR * HC;                             // halo pixels
 constexpr int HLD = CBK + 8;                               // bf16 per halo pixel in LDS (80 B: spreads the banks)
 constexpr int HITEMS = NHALO * (CBK / 8);                  // 16-byte groups of one halo chunk
 constexpr int HPT = (HITEMS + 255) / 256;                  // ... per thread
@@ -180,14 +185,17 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
         if (bthr) *reinterpret_cast<bf16x8*>(&Bs[buf][(tid / 4) * CLD + bg]) = r;
     };
 
-    // A operand rows of this lane: tile pixel (2 wave + (l >> 4), l & 15), l = lane & 31
+    // A operand rows of this lane in MFMA tile m: tile pixel
+    // (WROWS wave + 2 m + (l >> 4), l & 15), l = lane & 31
     const int pl = lane & 31;
-    const int hbase = (2 * wave + (pl >> 4) + 1) * HC + (pl & 15) + 1;  // halo index of the pixel itself
+    const int hbase = (WROWS * wave + (pl >> 4) + 1) * HC + (pl & 15) + 1;  // halo index of the pixel (m = 0)
     const int ko = (lane >> 5) * 8;
 
-    f32x16 acc[NT];
+    f32x16 acc[MT][NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x16{};
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x16{};
     fetch_halo(0);
     fetch_w(0, rb[0]);
     stage_halo(0);
@@ -209,12 +217,18 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
             const int hp = hbase + (t / 3 - 1) * HC + (t % 3 - 1);
 #pragma unroll
             for (int kk = 0; kk < CBK; kk += 16) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8*>(&Hs[hcur][hp * HLD + kk + ko]);
+                bf16x8 av[MT], bv[NT];
 #pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Bs[cur][(32 * n + pl) * CLD + kk + ko]);
-                    acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[n], 0, 0, 0);
-                }
+                for (int m = 0; m < MT; ++m)
+                    av[m] = *reinterpret_cast<const bf16x8*>(&Hs[hcur][(hp + 2 * m * HC) * HLD + kk + ko]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    bv[n] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(32 * n + pl) * CLD + kk + ko]);
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
             }
             // the other buffers were last read in the previous step (weights)
             // or chunk (halo), which every thread finished before the barrier
@@ -231,17 +245,19 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
     }
 
 #pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int co = n0 + nt * 32 + pl;
         if (co >= o.cout) continue;
         const float bias = o.bias ? o.bias[co] : 0.0f;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int q = wave * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);  // tile pixel
+            const int q = (WROWS * wave + 2 * m) * 16 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);  // tile pixel
             const int y = y0 + (q >> 4), x = x0 + (q & 15);
             if (y >= o.H || x >= o.W) continue;
             const size_t p = ((size_t)b * o.H + y) * o.W + x;
-            const float v = acc[nt][r] + bias;
+            const float v = acc[m][nt][r] + bias;
             if constexpr (!BWD) {
                 o.y[p * o.cout + co] = (bf16)(o.relu ? fmaxf(v, 0.0f) : v);
             } else {
