@@ -136,14 +136,25 @@ __device__ __forceinline__ bf16x8 pixel8(const ConvIn<T>& in, int cin, int H, in
 
 // NT 32-channel output tiles per wave (1 for layers of at most 32 output
 // channels, else 2); the weights of a step are fetched WD steps ahead.
-constexpr int WD = 3;
+#ifndef MSR_UNET_WD
+#define MSR_UNET_WD 3
+#endif
+#ifndef MSR_UNET_HALO_BUFS
+#define MSR_UNET_HALO_BUFS 1
+#endif
+constexpr int WD = MSR_UNET_WD;
+static_assert(9 % WD == 0, "the step loop advances WD steps at a time over 9 steps per chunk");
+// halo buffers of a multi-chunk layer: 2 (the next chunk is written while the
+// current one is read) or 1 (written after a barrier at the chunk's end: less
+// LDS, one more barrier per chunk)
+constexpr int HBUFS = MSR_UNET_HALO_BUFS;
 
 // ONE: the input has at most 32 channels (one chunk, one halo buffer: half
 // the LDS, so twice the resident blocks to cover the load latency).
 template <typename T, bool BWD, int NT, bool ONE>
 __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
     constexpr int BN = 32 * NT;  // output channels of a block
-    __shared__ __attribute__((aligned(16))) bf16 Hs[ONE ? 1 : 2][NHALO * HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Hs[ONE ? 1 : HBUFS][NHALO * HLD];
     __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * CLD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (o.W + TC - 1) / TC, tiles_y = (o.H + TR - 1) / TR;
@@ -236,11 +247,20 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
             const int nxt = (j + 1) % WD;  // slot of step st + 1
             if (more) stage_w(cur ^ 1, rb[nxt]);
             fetch_w(st + WD, rb[j]);            // slot j is free again: step st + WD
-            if constexpr (!ONE) {
+            if constexpr (!ONE && HBUFS == 2) {
                 if (t == 8 && more) stage_halo(hcur ^ 1);
             }
             __syncthreads();
-            if (!ONE && t == 8) hcur ^= 1;
+            if constexpr (!ONE && HBUFS == 2) {
+                if (t == 8) hcur ^= 1;
+            }
+            if constexpr (!ONE && HBUFS == 1) {
+                // every wave has read this chunk's halo (the barrier above)
+                if (t == 8 && more) {
+                    stage_halo(0);
+                    __syncthreads();
+                }
+            }
         }
     }
 

@@ -74,7 +74,7 @@ def phase_train(args, base):
     from paper_2406_18356_amd import UNet, unet_init_params, warmstart as ws
 
     t0 = time.perf_counter()
-    probs = synth.sky_set(base, args.train, 1000)
+    probs = synth.sky_set(base, args.train, 1000, workers=args.workers)
     log(f"train: {len(probs)} skies synthesised in {time.perf_counter() - t0:.1f} s")
     t1 = time.perf_counter()
     dh, il, b2, _ = ws.solve_pairs(probs, iters2=args.target_iters, chunk=args.chunk, log=log)
@@ -101,7 +101,7 @@ def phase_eval(args, base, params):
 
     dev = torch.device("cuda:0")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
-    probs = synth.sky_set(base, args.eval_start + args.eval, 2000)[args.eval_start:]
+    probs = synth.sky_set(base, args.eval_start + args.eval, 2000, workers=args.workers)[args.eval_start:]
     net = UNet(1, base.n)
     net.set_params(params)
     K0 = args.momentum_k
@@ -204,6 +204,7 @@ def main(argv=None):
     ap.add_argument("--load-params", default=None,
                     help="float32 parameter file, or 'packaged' for the network stored with the package")
     ap.add_argument("--out", default="warmstart_study.json")
+    ap.add_argument("--workers", type=int, default=16, help="host processes synthesising the skies")
     args = ap.parse_args(argv)
 
     base = base_problem(args.n)

@@ -329,21 +329,42 @@ def coarse_low(pr: Problem, d: int, seed: int = 0):
     return sky_s, _dirty_from_weights(sky_s, w_s, pr.cfg.noise_rel, rng), _psf_from_weights(w_s)
 
 
-def sky_set(base: Problem, count: int, seed: int) -> list:
+def _sky_member(base: Problem, seed: int, i: int):
+    s_sky, s_nL, s_nH = np.random.SeedSequence([seed, i]).spawn(3)
+    gen = lambda s: np.random.Generator(np.random.PCG64(s))  # noqa: E731
+    sky = make_sky(base.n, base.cfg.sky, gen(s_sky))
+    return (sky, _dirty_from_weights(sky, base.w_L, base.cfg.noise_rel, gen(s_nL)),
+            _dirty_from_weights(sky, base.w_H, base.cfg.noise_rel, gen(s_nH)))
+
+
+_SET_BASE = None
+
+
+def _sky_member_of_set(args):
+    seed, i = args
+    return _sky_member(_SET_BASE, seed, i)
+
+
+def sky_set(base: Problem, count: int, seed: int, workers: int = 1) -> list:
     """`count` problems observed with `base`'s uv coverage (same PSFs and
     partition) but new skies and noise, drawn from its sky configuration: many
-    fields, or many epochs, of one observation."""
-    out = []
-    for i in range(count):
-        s_sky, s_nL, s_nH = np.random.SeedSequence([seed, i]).spawn(3)
-        gen = lambda s: np.random.Generator(np.random.PCG64(s))  # noqa: E731
-        sky = make_sky(base.n, base.cfg.sky, gen(s_sky))
-        out.append(dataclasses.replace(
-            base, sky=sky, psf_full=None, dirty_full=None,
-            dirty_L=_dirty_from_weights(sky, base.w_L, base.cfg.noise_rel, gen(s_nL)),
-            dirty_H=_dirty_from_weights(sky, base.w_H, base.cfg.noise_rel, gen(s_nH)),
-        ))
-    return out
+    fields, or many epochs, of one observation.  Member i draws from the seed
+    sequence [seed, i] alone, so the set does not depend on `workers` (forked
+    processes sharing `base`)."""
+    if workers > 1 and count > 1:
+        import multiprocessing as mp
+
+        global _SET_BASE
+        _SET_BASE = base
+        try:
+            with mp.get_context("fork").Pool(workers) as pool:
+                members = pool.map(_sky_member_of_set, [(seed, i) for i in range(count)], chunksize=4)
+        finally:
+            _SET_BASE = None
+    else:
+        members = [_sky_member(base, seed, i) for i in range(count)]
+    return [dataclasses.replace(base, sky=sky, psf_full=None, dirty_full=None, dirty_L=dl, dirty_H=dh)
+            for sky, dl, dh in members]
 
 
 # --------------------------------------------------------------------------

@@ -69,3 +69,15 @@ def test_seeded_reproducible():
     np.testing.assert_array_equal(a.dirty_H, b.dirty_H)
     c = synth.make_problem(tiny(16, seed=4))
     assert not np.array_equal(a.dirty_H, c.dirty_H)
+
+
+def test_sky_set_does_not_depend_on_workers():
+    """Member i of a sky set draws from the seed sequence [seed, i] alone, so
+    the forked workers give the serial set exactly."""
+    base = synth.make_problem(tiny(64, seed=3), with_full=False)
+    a = synth.sky_set(base, 5, 1000)
+    b = synth.sky_set(base, 5, 1000, workers=3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.sky, y.sky)
+        assert np.array_equal(x.dirty_L, y.dirty_L) and np.array_equal(x.dirty_H, y.dirty_H)
+    assert not np.array_equal(a[0].sky, a[1].sky)
