@@ -397,7 +397,7 @@ msr_status msr_batch_solve(msr_batch* batch, int step, const double* lambda, int
 /* How msr_batch_solve runs the iterations.
  *  mode 0 (default): one launch per pass for each group of equal-sized
  *    channels, all captured in one graph (each size on its own stream).
- *  Mode 1 is switched off in this build (MSR_ERR_UNSUPPORTED): its first
+ *  Mode 1 is switched off (msr_batch_set_mode returns MSR_ERR_UNSUPPORTED): its first
  *  run did not return within minutes and the cause has not been found.
  *  mode 1: one persistent launch for all channels and all iterations.  The
  *    passes of Algorithm 1 (four per step-1 iteration, six per step-2) of

@@ -2540,7 +2540,7 @@ msr_status msr_batch_set_mode(msr_batch* b, int mode, unsigned int spin_limit) {
     // 512 .. 2048, 30 step-1 iterations) did not return within minutes, and
     // no cause has been found in its code; it stays off until one is.
     if (mode == 1 && !kPersistentEnabled)
-        return bfail(b, MSR_ERR_UNSUPPORTED, "the persistent launch (mode 1) is switched off in this build");
+        return bfail(b, MSR_ERR_UNSUPPORTED, "the persistent launch (mode 1) is switched off");
     b->mode = mode;
     b->spin_limit = spin_limit;
     return MSR_OK;
