@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MSR_ABI_VERSION 2  /* 2: msr_step2_full_res takes image_out */
+#define MSR_ABI_VERSION 3  /* 2: msr_step2_full_res takes image_out; 3: msr_config.iterate_precision */
 
 typedef enum msr_status {
     MSR_OK = 0,
@@ -78,6 +78,13 @@ typedef struct msr_config {
     int32_t dictionary;  /* 0: W = I (the image itself is sparse); 1: W = the concatenation of the
                             orthonormal Daubechies bases db1 .. db8 (Sect. 3, App. A.1): separable 2-D,
                             periodic, 4 levels, needs N >= 16; positivity is not available with it */
+    int32_t iterate_precision; /* 0 (or = precision): the iterates beta_k are stored in the context's
+                            precision; 64 with precision 32: float32 transforms and pointwise
+                            spectral work, float64 iterates and update (prox, momentum), so that
+                            the iterate is not rounded to float32 between iterations.  Single
+                            contexts with dictionary 0 only (batches, msr_major_cycles and the
+                            dictionary return MSR_ERR_UNSUPPORTED); msr_get_state / msr_set_state
+                            then exchange float64 images. */
 } msr_config;
 
 typedef struct msr_solve {
@@ -209,8 +216,9 @@ msr_status msr_major_cycles(msr_ctx* ctx, int step, int cycles, double c, int it
 
 /* Checkpoint and resume of a solve (the FISTA state of Algorithm 1).
  * msr_get_state copies the last two iterates beta_K, beta_{K-1} of the latest
- * solve of step s on this context (N x N images; with the wavelet dictionary
- * the coefficient arrays, 8 x N x N each) to beta_k / beta_km1 (device,
+ * solve of step s on this context (N x N images in the iterate precision,
+ * float64 with iterate_precision 64; with the wavelet dictionary the
+ * coefficient arrays, 8 x N x N each) to beta_k / beta_km1 (device,
  * caller-owned) and writes K to *k (may be NULL).  The iterates stay
  * available until the next solve, msr_major_cycles, msr_time_pass or
  * msr_set_workspace on the context, else MSR_ERR_STATE.

@@ -37,6 +37,7 @@ class Config(C.Structure):
         ("prune_tol", C.c_double),
         ("precision", C.c_int32),
         ("dictionary", C.c_int32),
+        ("iterate_precision", C.c_int32),
     ]
 
 
@@ -162,13 +163,15 @@ def abi_version() -> int:
     return lib().msr_abi_version()
 
 
-def _cfg(n, pad=2, positivity=False, device=0, seed=0, prune_tol=1e-6, precision=32, dictionary=0) -> Config:
+def _cfg(n, pad=2, positivity=False, device=0, seed=0, prune_tol=1e-6, precision=32, dictionary=0,
+         iterate_precision=0) -> Config:
     return Config(int(n), int(pad), int(bool(positivity)), int(device), int(seed), float(prune_tol),
-                  int(precision), int(dictionary))
+                  int(precision), int(dictionary), int(iterate_precision))
 
 
-def workspace_bytes(n, pad=2, positivity=False, seed=0, prune_tol=1e-6, precision=32, dictionary=0) -> int:
-    c = _cfg(n, pad, positivity, 0, seed, prune_tol, precision, dictionary)
+def workspace_bytes(n, pad=2, positivity=False, seed=0, prune_tol=1e-6, precision=32, dictionary=0,
+                    iterate_precision=0) -> int:
+    c = _cfg(n, pad, positivity, 0, seed, prune_tol, precision, dictionary, iterate_precision)
     return int(lib().msr_workspace_bytes(C.byref(c)))
 
 
@@ -203,7 +206,7 @@ class Solver:
 
     def __init__(self, n: int, pad: int = 2, positivity: bool = False, device: int = 0, seed: int = 0,
                  prune_tol: float = 1e-6, precision: int = 32, dictionary: int = 0, static_workspace: bool = False,
-                 _borrowed=None):
+                 iterate_precision: int = 0, _borrowed=None):
         import torch
 
         self._lib = lib()
@@ -220,7 +223,9 @@ class Solver:
         self.dtype = torch.float32 if precision == 32 else torch.float64
         self.device = torch.device("cuda", device)
         self.dictionary = int(dictionary)
-        cfg = _cfg(n, pad, positivity, device, seed, prune_tol, precision, dictionary)
+        # float64 iterates with float32 transforms: the state images are float64
+        self.state_dtype = torch.float64 if (iterate_precision == 64 or precision == 64) else self.dtype
+        cfg = _cfg(n, pad, positivity, device, seed, prune_tol, precision, dictionary, iterate_precision)
         h = C.c_void_p()
         st = self._lib.msr_init(C.byref(cfg), C.byref(h))
         if st != OK:
@@ -328,16 +333,18 @@ class Solver:
         """(beta_K, beta_{K-1}, K) of the latest solve of `step` (msr_get_state)."""
         import torch
 
-        bk = torch.empty(self._state_shape(), dtype=self.dtype, device=self.device)
+        bk = torch.empty(self._state_shape(), dtype=getattr(self, "state_dtype", self.dtype), device=self.device)
         bp = torch.empty_like(bk)
         k = C.c_int()
-        self._check(self._lib.msr_get_state(self._h, int(step), self._p(bk), self._p(bp), C.byref(k),
+        sd = getattr(self, "state_dtype", self.dtype)
+        self._check(self._lib.msr_get_state(self._h, int(step), _ptr(bk, sd), _ptr(bp, sd), C.byref(k),
                                             _stream(stream)))
         return bk, bp, k.value
 
     def set_state(self, step, beta_k, beta_km1, k, stream=None):
         """Loads a state: the next solve of `step` continues from iteration k + 1."""
-        self._check(self._lib.msr_set_state(self._h, int(step), self._p(beta_k), self._p(beta_km1), int(k),
+        sd = getattr(self, "state_dtype", self.dtype)
+        self._check(self._lib.msr_set_state(self._h, int(step), _ptr(beta_k, sd), _ptr(beta_km1, sd), int(k),
                                             _stream(stream)))
 
     def upsample(self, small, factor, stream=None):

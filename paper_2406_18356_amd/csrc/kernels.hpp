@@ -276,7 +276,7 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& a, Epi& epi, int vb, 
     // Image values the epilogue reads, loaded up front (after the spectrum
     // columns) so that their latency hides behind the inverse transform.
     constexpr int NPRE = Epi::NPRE > 0 ? Epi::NPRE : 1;
-    R pre[E][NPRE];
+    typename Epi::Pre pre[E][NPRE];
     auto prefetch = [&]() {
         if constexpr (Epi::NPRE > 0) {
 #pragma unroll
@@ -483,6 +483,7 @@ template <typename R>
 struct EpiLoad {
     static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
     static constexpr bool LATE_ROWS = false;
+    using Pre = R;  // type of the prefetched image values
     const R* __restrict__ img;
     int ld;
     R scale;
@@ -500,6 +501,7 @@ template <typename R>
 struct EpiLoadShift {
     static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
     static constexpr bool LATE_ROWS = false;
+    using Pre = R;  // type of the prefetched image values
     const R* __restrict__ img;
     int P;
     __device__ __forceinline__ void to_channel(long long off) { img = shifted(img, off); }
@@ -518,6 +520,7 @@ template <typename R>
 struct EpiStore {
     static constexpr int NQ = 0, NPRE = 0, MIN_WAVES = 1;
     static constexpr bool LATE_ROWS = false;
+    using Pre = R;  // type of the prefetched image values
     R* __restrict__ out;
     int ld;
     R scale;
@@ -537,6 +540,7 @@ template <typename R>
 struct EpiResid {
     static constexpr int NQ = 1, NPRE = 2, MIN_WAVES = 1;
     static constexpr bool LATE_ROWS = false;
+    using Pre = R;  // type of the prefetched image values
     const R* __restrict__ y;
     R* __restrict__ r_out;
     int ld;
@@ -572,18 +576,24 @@ struct EpiResid {
 //   beta_k      = prox(alpha_{k-1} - mu * 2 s)  (soft threshold at mu*lambda, or its positive part)
 //   alpha_k     = beta_k + t_cur (beta_k - b1)
 // beta_k overwrites b2 (same element, same thread); alpha_k is forwarded.
-template <typename R>
+// I is the type of the stored iterates and of this arithmetic: R, or double
+// with R = float (FP32 transforms, FP64 iterates: the iterate is not rounded
+// to float between iterations).
+template <typename R, typename I = R>
 struct EpiUpdate {
-    static constexpr int NQ = 1, NPRE = 2, MIN_WAVES = 4;
-    static constexpr bool LATE_ROWS = true;  // beta_{k-2} of the pair's rows via LDS (row_kernel)
-    const R* __restrict__ b1;
-    R* __restrict__ b2;  // in: beta_{k-2}; out: beta_k
+    // float64 iterates double the prefetched registers: a lower wave target
+    static constexpr int NQ = 1, NPRE = 2, MIN_WAVES = std::is_same<R, I>::value ? 4 : 2;
+    // beta_{k-2} of the pair's rows via LDS (row_kernel), for float iterates
+    static constexpr bool LATE_ROWS = std::is_same<R, I>::value;
+    using Pre = I;
+    const I* __restrict__ b1;
+    I* __restrict__ b2;  // in: beta_{k-2}; out: beta_k
     int ld;
     // rows (r, r + 1) of beta_{k-2}, which the row kernel copies to LDS
-    __device__ __forceinline__ const R* late_src(int r) const { return b2 + (size_t)r * ld; }
-    R two_mu;     // 2 mu
-    R thr;        // mu * lambda
-    R t_prev, t_cur;
+    __device__ __forceinline__ const I* late_src(int r) const { return b2 + (size_t)r * ld; }
+    I two_mu;     // 2 mu
+    I thr;        // mu * lambda
+    I t_prev, t_cur;
     int positivity;
     __device__ __forceinline__ void to_channel(long long off) {
         b1 = shifted(b1, off);
@@ -593,11 +603,11 @@ struct EpiUpdate {
         two_mu = c.two_mu;
         thr = c.thr;
     }
-    __device__ __forceinline__ R upd(R s, R p1, R& p2) const {
-        const R alpha = fmaR(t_prev, p1 - p2, p1);
-        const R zz = fmaR(-two_mu, s, alpha);
-        R beta;
-        const R zero = 0;
+    __device__ __forceinline__ I upd(R s, I p1, I& p2) const {
+        const I alpha = fmaR(t_prev, p1 - p2, p1);
+        const I zz = fmaR(-two_mu, (I)s, alpha);
+        I beta;
+        const I zero = 0;
         if (positivity) beta = fmax(zz - thr, zero);
         else beta = copysign(fmax(fabs(zz) - thr, zero), zz);
         p2 = beta;
@@ -605,28 +615,28 @@ struct EpiUpdate {
     }
     // beta_{k-1} of both rows is prefetched; beta_{k-2} too would not fit the
     // register budget
-    __device__ __forceinline__ void load(int r, int i, R* p) const {
+    __device__ __forceinline__ void load(int r, int i, I* p) const {
         const uint32_t ia = (uint32_t)r * ld + i;
         p[0] = el(b1, ia);
         p[1] = el(b1, ia + ld);
     }
-    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc, const R* p) const {
+    __device__ __forceinline__ cplx<R> apply(int r, int i, cplx<R> z, double* acc, const I* p) const {
         const uint32_t ia = (uint32_t)r * ld + i;
         return update(ia, z, acc, p, el(b2, ia), el(b2, ia + ld));
     }
     // The same with beta_{k-2} of rows (r, r + 1) in LDS (late, ld apart).
-    __device__ __forceinline__ cplx<R> apply_late(int r, int i, cplx<R> z, double* acc, const R* p,
-                                                  lds_ptr<const R> late) const {
+    __device__ __forceinline__ cplx<R> apply_late(int r, int i, cplx<R> z, double* acc, const I* p,
+                                                  lds_ptr<const I> late) const {
         return update((uint32_t)r * ld + i, z, acc, p, late[i], late[ld + i]);
     }
-    __device__ __forceinline__ cplx<R> update(uint32_t ia, cplx<R> z, double* acc, const R* p, R pa, R pb) const {
+    __device__ __forceinline__ cplx<R> update(uint32_t ia, cplx<R> z, double* acc, const I* p, I pa, I pb) const {
         const uint32_t ib = ia + ld;
-        const R qa = upd(z.x, p[0], pa);
-        const R qb = upd(z.y, p[1], pb);
+        const I qa = upd(z.x, p[0], pa);
+        const I qb = upd(z.y, p[1], pb);
         el(b2, ia) = pa;
         el(b2, ib) = pb;
         acc[0] += (double)fabs(pa) + (double)fabs(pb);
-        return mk<cplx<R>>(qa, qb);
+        return mk<cplx<R>>((R)qa, (R)qb);
     }
 };
 
@@ -635,6 +645,7 @@ template <typename R>
 struct EpiPower {
     static constexpr int NQ = 2, NPRE = 0, MIN_WAVES = 1;
     static constexpr bool LATE_ROWS = false;
+    using Pre = R;  // type of the prefetched image values
     const R* __restrict__ vprev;
     R* __restrict__ w_out;
     int ld;

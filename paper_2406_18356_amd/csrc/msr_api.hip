@@ -205,7 +205,9 @@ struct Shapes {
     bool padded;
     bool dict;           // wavelet dictionary: 8 coefficient arrays of N x N per state
     int prec;            // 32 or 64
+    bool it64;           // float64 iterates with float32 transforms
     size_t rs, cs;       // bytes of a real / complex element
+    size_t is;           // bytes of an iterate element
     size_t spec_elems;   // N * Cpad complex
     size_t hh_elems;     // P * Cpad reals
     size_t img_elems;    // N * N
@@ -249,6 +251,16 @@ bool make_shapes(const msr_config* c, Shapes& s, std::string* why) {
         if (why) *why = "the wavelet dictionary needs n >= 16";
         return false;
     }
+    const int ip = c->iterate_precision;
+    if (ip != 0 && ip != c->precision && !(ip == 64 && c->precision == 32)) {
+        if (why) *why = "iterate_precision must be 0, the precision, or 64 with precision 32";
+        return false;
+    }
+    s.it64 = ip == 64 && c->precision == 32;
+    if (s.it64 && c->dictionary != 0) {
+        if (why) *why = "float64 iterates need dictionary 0";
+        return false;
+    }
     s.dict = c->dictionary == 1;
     s.N = c->n;
     s.padded = c->pad == 2;
@@ -262,6 +274,7 @@ bool make_shapes(const msr_config* c, Shapes& s, std::string* why) {
     }
     s.rs = s.prec == 32 ? 4 : 8;
     s.cs = 2 * s.rs;
+    s.is = s.it64 ? 8 : s.rs;
     s.Cfull = s.P / 2 + 1;
     s.Cpad = (int)align_up(s.Cfull, s.T);
     s.Cpad_psf = (int)align_up(s.Cfull, s.Tpsf);
@@ -294,8 +307,8 @@ Layout make_layout(const Shapes& s) {
     l.hh2 = take(s.rs * s.hh_elems);
     l.d1 = take(s.rs * s.img_elems);
     l.d2 = take(s.rs * s.img_elems);
-    l.b0 = take(s.rs * s.img_elems);
-    l.b1 = take(s.rs * s.img_elems);
+    l.b0 = take(s.is * s.img_elems);
+    l.b1 = take(s.is * s.img_elems);
     l.t0 = take(s.rs * s.img_elems);
     l.t1 = take(s.rs * s.img_elems);
     // major cycles: original dirty image, sum of the cycle images, constraint, cycle image
@@ -490,6 +503,25 @@ struct Impl {
     R* hh(int step) const { return at<R>(step == 1 ? c->lay.hh1 : c->lay.hh2); }
     R* dirty(int step) const { return at<R>(step == 1 ? c->lay.d1 : c->lay.d2); }
     R* beta(int k) const { return at<R>((k & 1) ? c->lay.b1 : c->lay.b0); }
+    // float64 iterates (iterate_precision 64): the same buffers, 8 bytes an element
+    bool it64() const { return c->sh.it64; }
+    double* beta64(int k) const { return at<double>((k & 1) ? c->lay.b1 : c->lay.b0); }
+    void* iter_buf(int k) const { return at<char>((k & 1) ? c->lay.b1 : c->lay.b0); }
+    // beta_k as an R image: the iterate itself, or (float64 iterates) rounded
+    // into the major-cycle buffer mc3 (no single solve uses it then)
+    msr_status beta_r(int k, const R** out, hipStream_t s) {
+        if (!it64()) {
+            *out = beta(k);
+            return MSR_OK;
+        }
+        R* dst = at<R>(c->lay.mc3);
+        const size_t n = c->sh.img_elems;
+        hipLaunchKernelGGL((convert_image<R, double>), dim3(blocks_for(n)), dim3(256), 0, s, dst,
+                           (const double*)beta64(k), n);
+        LAUNCHCHK(c);
+        *out = dst;
+        return MSR_OK;
+    }
     R* tmp(int i) const { return at<R>(i ? c->lay.t1 : c->lay.t0); }
     bool dict() const { return c->sh.dict; }
     size_t cn() const { return (size_t)kWaveletBases * c->sh.img_elems; }
@@ -678,6 +710,24 @@ struct Impl {
     // One FISTA iteration k (1-based) of step s.
     msr_status iterate(int step, int k, double mu, double lambda, hipStream_t s) {
         TRY(grad_chain(step, dirty(step), true, s));
+        if (it64()) {
+            if (rec_) return fail(c, MSR_ERR_UNSUPPORTED, "float64 iterates in a persistent launch");
+            EpiUpdate<R, double> u{};
+            u.b1 = beta64(k - 1);
+            u.b2 = beta64(k);
+            u.ld = N();
+            u.two_mu = 2.0 * mu;
+            u.thr = mu * lambda;
+            u.t_prev = momentum(k - 1);
+            u.t_cur = momentum(k);
+            u.positivity = c->cfg.positivity;
+            const int K = Ks(step);
+            RowArgs<R> a = step == 1 ? row_args(SB(), K, nullptr, 0, SA(), KA(1))
+                                     : row_args(SB(), K, SG(), KLs(), SA(), KA(2));
+            opr(step)->row_update_fwd_it64(a, u, s);
+            LAUNCHCHK(c);
+            return MSR_OK;
+        }
         EpiUpdate<R> u{};
         u.b1 = beta(k - 1);
         u.b2 = beta(k);
@@ -962,6 +1012,20 @@ struct Impl {
             c->have_theta[step - 1] = true;
         }
         *mu = 1.0 / c->theta[step - 1];
+        if (it64()) {
+            // beta_0 = beta_{-1} = (double) x0; alpha_0's spectrum from x0 itself
+            const size_t n = c->sh.img_elems;
+            if (x0) {
+                hipLaunchKernelGGL((convert_image<double, R>), dim3(blocks_for(n)), dim3(256), 0, s, beta64(0), x0, n);
+                LAUNCHCHK(c);
+            } else {
+                HIPCHK(c, hipMemsetAsync(beta64(0), 0, sizeof(double) * n, s));
+                HIPCHK(c, hipMemsetAsync(tmp(0), 0, c->sh.rs * n, s));
+            }
+            HIPCHK(c, hipMemcpyAsync(beta64(1), beta64(0), sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            if (step == 2) TRY(fwd_image(2, low_res, (R)1, SL(), std::max(kl, KLs()), s));
+            return fwd_image(step, x0 ? x0 : tmp(0), (R)1, SA(), std::max(ka, KA(step)), s);
+        }
         const size_t nb = c->sh.rs * c->sh.img_elems;
         if (x0) {
             HIPCHK(c, hipMemcpyAsync(beta(0), x0, nb, hipMemcpyDeviceToDevice, s));
@@ -979,9 +1043,16 @@ struct Impl {
     msr_status finish(int step, double lambda, int done, R* model_out, R* image_out, double F[3], hipStream_t s) {
         const size_t nb = c->sh.rs * c->sh.img_elems;
         const R* bK = beta(done);
+        if (it64()) {  // the model is the float64 iterate rounded once
+            const size_t n = c->sh.img_elems;
+            hipLaunchKernelGGL((convert_image<R, double>), dim3(blocks_for(n)), dim3(256), 0, s, model_out,
+                               (const double*)beta64(done), n);
+            LAUNCHCHK(c);
+            bK = model_out;
+        }
         TRY(objective_at(step, lambda, bK, F, s));
         if (!std::isfinite(F[0])) return fail(c, MSR_ERR_NUMERIC, "objective is not finite after %d iterations", done);
-        HIPCHK(c, hipMemcpyAsync(model_out, bK, nb, hipMemcpyDeviceToDevice, s));
+        if (bK != model_out) HIPCHK(c, hipMemcpyAsync(model_out, bK, nb, hipMemcpyDeviceToDevice, s));
         if (image_out) {
             // i_L = beta + (i~ - H beta) = beta - r
             TRY(fwd_image(step, bK, (R)1, SB(), c->K[step - 1], s));
@@ -1218,9 +1289,14 @@ struct Impl {
         if (step == 2) TRY(set_low_res(low_res, s));
         const size_t n = dict() ? cn() : c->sh.img_elems;
         R* a = dict() ? cA() : tmp(0);
-        const R* bk = dict() ? coef(K) : beta(K);
-        const R* bp = dict() ? coef(K - 1) : beta(K - 1);
-        hipLaunchKernelGGL(momentum_point<R>, dim3(blocks_for(n)), dim3(256), 0, s, a, bk, bp, (R)momentum(K), n);
+        if (it64()) {
+            hipLaunchKernelGGL(momentum_point_it64<R>, dim3(blocks_for(n)), dim3(256), 0, s, a,
+                               (const double*)beta64(K), (const double*)beta64(K - 1), momentum(K), n);
+        } else {
+            const R* bk = dict() ? coef(K) : beta(K);
+            const R* bp = dict() ? coef(K - 1) : beta(K - 1);
+            hipLaunchKernelGGL(momentum_point<R>, dim3(blocks_for(n)), dim3(256), 0, s, a, bk, bp, (R)momentum(K), n);
+        }
         LAUNCHCHK(c);
         if (!dict()) TRY(fwd_image(step, a, (R)1, SA(), KA(step), s));
         return MSR_OK;
@@ -1254,7 +1330,9 @@ struct Impl {
         for (k = K0 + 1; k <= kend; ++k) {
             if ((st = iterate(step, k, mu, opt->lambda, s)) != MSR_OK) break;
             if (opt->check_every > 0 && (k % opt->check_every == 0)) {
-                if ((st = objective_at(step, opt->lambda, beta(k), F, s)) != MSR_OK) break;
+                const R* bk = nullptr;
+                if ((st = beta_r(k, &bk, s)) != MSR_OK) break;
+                if ((st = objective_at(step, opt->lambda, bk, F, s)) != MSR_OK) break;
                 if (!std::isfinite(F[0])) {
                     st = fail(c, MSR_ERR_NUMERIC, "objective is not finite at iteration %d", k);
                     break;
@@ -1501,6 +1579,16 @@ struct Impl {
             if (which == 1) {
                 opr(step)->row_resid_fwd(row_args(SB(), K, nullptr, 0, SC(), K), EpiResid<R>{dirty(step), nullptr, Nn},
                                          s);
+                LAUNCHCHK(c);
+                return MSR_OK;
+            }
+            if (it64()) {
+                EpiUpdate<R, double> u{};
+                u.b1 = beta64(0);
+                u.b2 = beta64(1);
+                u.ld = Nn;
+                u.positivity = c->cfg.positivity;
+                opr(step)->row_update_fwd_it64(row_args(SB(), K, Kin2 ? SL() : nullptr, Kin2, SC(), Kout), u, s);
                 LAUNCHCHK(c);
                 return MSR_OK;
             }
@@ -1782,6 +1870,7 @@ msr_status msr_major_cycles(msr_ctx* c, int step, int cycles, double cl, int ite
     if (cycles < 1 || iters < 0 || !(cl >= 0) || !std::isfinite(cl) || (step == 2 && !low_res) ||
         (!model_out && !image_out))
         return fail(c, MSR_ERR_INVALID, "bad arguments");
+    if (c->sh.it64) return fail(c, MSR_ERR_UNSUPPORTED, "major cycles store float32 iterates");
     return with_impl(c, [&](auto& im) {
         using R = std::remove_pointer_t<decltype(im.dirty(1))>;
         return im.multi_cycle(step, cycles, cl, iters, static_cast<const R*>(low_res), static_cast<R*>(model_out),
@@ -1916,10 +2005,11 @@ msr_status msr_get_state(msr_ctx* c, int step, void* beta_k, void* beta_km1, int
     const int K = c->state_k;
     return with_impl(c, [&](auto& im) {
         const bool d = im.dict();
-        const size_t bytes = c->sh.rs * (d ? im.cn() : c->sh.img_elems);
-        HIPCHK(c, hipMemcpyAsync(beta_k, d ? im.coef(K) : im.beta(K), bytes, hipMemcpyDeviceToDevice, S(stream)));
-        HIPCHK(c, hipMemcpyAsync(beta_km1, d ? im.coef(K - 1) : im.beta(K - 1), bytes, hipMemcpyDeviceToDevice,
+        const size_t bytes = d ? c->sh.rs * im.cn() : c->sh.is * c->sh.img_elems;
+        HIPCHK(c, hipMemcpyAsync(beta_k, d ? (void*)im.coef(K) : im.iter_buf(K), bytes, hipMemcpyDeviceToDevice,
                                  S(stream)));
+        HIPCHK(c, hipMemcpyAsync(beta_km1, d ? (void*)im.coef(K - 1) : im.iter_buf(K - 1), bytes,
+                                 hipMemcpyDeviceToDevice, S(stream)));
         HIPCHK(c, hipStreamSynchronize(S(stream)));
         if (k) *k = K;
         return MSR_OK;
@@ -1933,10 +2023,11 @@ msr_status msr_set_state(msr_ctx* c, int step, const void* beta_k, const void* b
     HIPCHK(c, hipSetDevice(c->cfg.device));
     return with_impl(c, [&](auto& im) {
         const bool d = im.dict();
-        const size_t bytes = c->sh.rs * (d ? im.cn() : c->sh.img_elems);
-        HIPCHK(c, hipMemcpyAsync(d ? im.coef(k - 1) : im.beta(k - 1), beta_km1, bytes, hipMemcpyDeviceToDevice,
+        const size_t bytes = d ? c->sh.rs * im.cn() : c->sh.is * c->sh.img_elems;
+        HIPCHK(c, hipMemcpyAsync(d ? (void*)im.coef(k - 1) : im.iter_buf(k - 1), beta_km1, bytes,
+                                 hipMemcpyDeviceToDevice, S(stream)));
+        HIPCHK(c, hipMemcpyAsync(d ? (void*)im.coef(k) : im.iter_buf(k), beta_k, bytes, hipMemcpyDeviceToDevice,
                                  S(stream)));
-        HIPCHK(c, hipMemcpyAsync(d ? im.coef(k) : im.beta(k), beta_k, bytes, hipMemcpyDeviceToDevice, S(stream)));
         HIPCHK(c, hipStreamSynchronize(S(stream)));
         c->state_step = 0;
         c->resume_k[step - 1] = k;
@@ -2113,6 +2204,10 @@ bool plan_batch(int nch, const msr_config* cfgs, std::vector<msr_batch::Group>& 
         }
         if (cfgs[i].dictionary != 0) {
             if (why) *why = "batched channels solve in the image domain (dictionary 0)";
+            return false;
+        }
+        if (s.it64) {
+            if (why) *why = "batched channels store iterates in the context's precision";
             return false;
         }
     }

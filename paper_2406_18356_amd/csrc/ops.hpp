@@ -90,6 +90,8 @@ struct Ops {
     void (*row_resid_fwd)(const RowArgs<R>&, const EpiResid<R>&, hipStream_t) = nullptr;  // -> (x - y) -> spectrum
     void (*row_resid)(const RowArgs<R>&, const EpiResid<R>&, hipStream_t) = nullptr;      // -> (x - y), sums/stored
     void (*row_update_fwd)(const RowArgs<R>&, const EpiUpdate<R>&, hipStream_t) = nullptr;  // FISTA update
+    // the same update with float64 iterates (R = float only)
+    void (*row_update_fwd_it64)(const RowArgs<R>&, const EpiUpdate<R, double>&, hipStream_t) = nullptr;
     void (*row_power)(const RowArgs<R>&, const EpiPower<R>&, hipStream_t) = nullptr;        // power iteration
     void (*col_psf)(const ColArgs<R>&, const ModePsf<R>&, hipStream_t) = nullptr;
     void (*col_filtw)(const ColArgs<R>&, const ModeFilterW<R>&, hipStream_t) = nullptr;

@@ -66,6 +66,7 @@ struct Inst {
             o.row_resid_fwd = &row<true, true, EpiResid<R>>;
             o.row_resid = &row<true, false, EpiResid<R>>;
             o.row_update_fwd = &row<true, true, EpiUpdate<R>>;
+            if constexpr (std::is_same<R, float>::value) o.row_update_fwd_it64 = &row<true, true, EpiUpdate<R, double>>;
             o.row_power = &row<true, false, EpiPower<R>>;
             o.col_psf = &col<ModePsf<R>>;
             o.col_filtw = &col<ModeFilterW<R>>;

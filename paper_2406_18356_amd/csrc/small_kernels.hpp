@@ -129,6 +129,24 @@ __global__ void momentum_point(R* __restrict__ out, const R* __restrict__ bk, co
     out[i] = fmaR(t, b - bp[i], b);
 }
 
+// The same from float64 iterates, rounded once to R.
+template <typename R>
+__global__ void momentum_point_it64(R* __restrict__ out, const double* __restrict__ bk,
+                                    const double* __restrict__ bp, double t, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double b = bk[i];
+    out[i] = (R)fma(t, b - bp[i], b);
+}
+
+// out[i] = (To) in[i]: float images to float64 iterates and back.
+template <typename To, typename From>
+__global__ void convert_image(To* __restrict__ out, const From* __restrict__ in, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = (To)in[i];
+}
+
 // Power-iteration start vector: v[n] = splitmix64_mix(seed + n) * 2^-64 - 1/2,
 // taking the top 53 bits for an exact double, then rounding to R.
 __device__ __forceinline__ unsigned long long splitmix64_mix(unsigned long long c) {

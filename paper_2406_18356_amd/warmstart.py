@@ -90,7 +90,8 @@ def time_to_tol(solver, lam, low_res, f_ref, x0=None, tol=1e-6, max_iters=20000,
     velocity (msr_set_state), so that the momentum weight starts near 1
     instead of at 0 (Algorithm 1 itself restarts at k = 1)."""
     if momentum_k > 0:
-        solver.set_state(2, x0, x0, momentum_k)
+        z = x0.to(getattr(solver, "state_dtype", x0.dtype))
+        solver.set_state(2, z, z, momentum_k)
     _, r = solver.step2(lam, low_res, max_iters, x0=x0, check_every=check_every, tol=tol, f_ref=f_ref)
     ms = (r.time_to_tol_ms + warm_ms) if r.converged else -1.0
     return {"ms": ms, "iters": int(r.iters), "converged": bool(r.converged), "warm_start_ms": warm_ms}
@@ -209,6 +210,7 @@ def trajectory(solver, lam, low_res, x0=None, iters=20000, every=500, momentum_k
 
     if momentum_k > 0:
         z = x0 if x0 is not None else torch.zeros_like(low_res)
+        z = z.to(getattr(solver, "state_dtype", z.dtype))  # float64 iterates take a float64 state
         solver.set_state(2, z, z, momentum_k)
         x0 = None
     out = {"k": [], "F": [], "ms": []}

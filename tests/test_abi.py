@@ -70,6 +70,23 @@ def test_workspace_bytes_host_only(lib):
     assert binding.workspace_bytes(256, precision=16) == 0
 
 
+def test_iterate_precision_host_only(lib):
+    """float64 iterates: two N x N images of 8 instead of 4 bytes; only with
+    precision 32 (or equal to the precision) and without the dictionary."""
+    from paper_2406_18356_amd import binding
+
+    b = binding.workspace_bytes(256)
+    b64 = binding.workspace_bytes(256, iterate_precision=64)
+    assert b64 - b >= 2 * 4 * 256 * 256 and b64 - b <= 2 * 4 * 256 * 256 + 2 * 256
+    assert binding.workspace_bytes(256, iterate_precision=32) == b
+    assert binding.workspace_bytes(256, precision=64, iterate_precision=64) == binding.workspace_bytes(256, precision=64)
+    assert binding.workspace_bytes(256, precision=64, iterate_precision=32) == 0
+    assert binding.workspace_bytes(256, iterate_precision=16) == 0
+    assert binding.workspace_bytes(64, dictionary=1, iterate_precision=64) == 0
+    cfgs = (binding.Config * 2)(binding._cfg(64), binding._cfg(64, iterate_precision=64))
+    assert lib.msr_batch_workspace_bytes(2, cfgs) == 0  # batches keep the context's precision
+
+
 def test_init_rejects_bad_config_before_touching_a_device(lib):
     from paper_2406_18356_amd import binding
 
