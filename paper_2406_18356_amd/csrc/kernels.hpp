@@ -288,9 +288,13 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& a, Epi& epi, int vb, 
     // the pair's two rows copied straight into the pair's LDS line while
     // the inverse transform's last stage computes (the LDS is idle then),
     // instead of a global load that stalls the epilogue.
+    // The rows are of the epilogue's prefetch type (float64 iterates take
+    // twice the bytes: they fit the line of a zero-padded pair, 2L complex).
+    using P = typename Epi::Pre;
     constexpr bool LATE = INV_IN && MSR_LATE_LDS && Epi::LATE_ROWS && !PP && TPF % 64 == 0 &&
-                          (2 * L) % ((TPF / 64) * 64 * (16 / (int)sizeof(R))) == 0;
-    lds_ptr<const R> late = nullptr;
+                          (2 * L) % ((TPF / 64) * 64 * (16 / (int)sizeof(P))) == 0 &&
+                          2 * L * (int)sizeof(P) <= ZLEN * (int)sizeof(C);
+    lds_ptr<const P> late = nullptr;
 
     if constexpr (INV_IN) {
         // Half-plane columns of both rows -> full Hermitian-combined line Z in
@@ -348,13 +352,13 @@ __device__ __forceinline__ void row_body(const RowArgs<R>& a, Epi& epi, int vb, 
         // stage by stage.
         constexpr bool PRE_INV = MSR_TW_PRELOAD_INV || Epi::MIN_WAVES == 1;
         if constexpr (LATE) {
-            R* line = reinterpret_cast<R*>(lds + pair * ZLEN);
-            const R* src = epi.late_src(ra);
-            auto hook = [&]() { load_to_lds<R, 2 * L, TPF / 64>(src, line, t); };
+            P* line = reinterpret_cast<P*>(lds + pair * ZLEN);
+            const P* src = epi.late_src(ra);
+            auto hook = [&]() { load_to_lds<P, 2 * L, TPF / 64>(src, line, t); };
             fft<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, t, a.tws, hook);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
-            late = (lds_ptr<const R>)line;
+            late = (lds_ptr<const P>)line;
         } else if constexpr (PP) {
             fft_pp<L, E, true, Cf::TWS, NH, 1, PRE_INV>(v, hv, hw, t, a.tws);
         } else {
@@ -583,8 +587,8 @@ template <typename R, typename I = R>
 struct EpiUpdate {
     // float64 iterates double the prefetched registers: a lower wave target
     static constexpr int NQ = 1, NPRE = 2, MIN_WAVES = std::is_same<R, I>::value ? 4 : 2;
-    // beta_{k-2} of the pair's rows via LDS (row_kernel), for float iterates
-    static constexpr bool LATE_ROWS = std::is_same<R, I>::value;
+    // beta_{k-2} of the pair's rows via LDS (row_kernel, where they fit)
+    static constexpr bool LATE_ROWS = true;
     using Pre = I;
     const I* __restrict__ b1;
     I* __restrict__ b2;  // in: beta_{k-2}; out: beta_k

@@ -128,3 +128,26 @@ def test_float64_iterates_refused_where_not_built(torch_dev):
     with pytest.raises(MsrError) as e:
         s.major_cycles(1, 2, 5)
     assert e.value.status == binding.ERR_UNSUPPORTED
+
+
+def test_float64_iterates_circular_and_checked_loop(torch_dev):
+    """Circular mode (pad 1) against the FP64 oracle after 100 iterations,
+    and a loop with exact objective checks every 10 iterations (the iterate
+    is rounded into a scratch image for them) giving the same model and
+    objective as the loop without checks."""
+    import torch
+    from oracle import objectives, fista, lipschitz, helpers
+    from synth.generator import tiny
+
+    pr = synth.make_problem(tiny(64, seed=9).replace(pad=1))
+    s = _solver(torch_dev, pr)
+    p1 = objectives.Step1(pr.dirty_L, pr.psf_L)
+    th = 1.01 * lipschitz.power_iteration(p1.normal, pr.n)[0]
+    lam = helpers.default_lambda(pr.dirty_L)
+    ref, _ = fista.fista(p1.grad, np.zeros((pr.n, pr.n)), 1 / th, lam, 100, positivity=True)
+    s.set_lipschitz(1, th)
+    b, r = s.step1(lam, 100)
+    print(f"circular 64^2, K = 100: {rel(b.cpu().numpy(), ref):.3g}", flush=True)
+    assert rel(b.cpu().numpy(), ref) <= TOL
+    b2, r2 = s.step1(lam, 100, check_every=10)
+    assert torch.equal(b2, b) and r2.objective == r.objective
