@@ -61,24 +61,6 @@ struct ConvIn {
     int c2;
 };
 
-// Channels [k, k + 8) of the im2col row of output pixel (b, y, x): tap
-// t = k / cin at offset (t / 3 - 1, t % 3 - 1); zero outside the image and
-// for k >= 9 cin.
-template <typename T>
-__device__ __forceinline__ bf16x8 im2col8(const ConvIn<T>& in, int H, int W, int b, int y, int x, int k) {
-    const int cin = in.c1 + in.c2;
-    if (k >= 9 * cin) return zero8();
-    const int t = k / cin;
-    const int ci = k - t * cin;
-    const int sy = y + t / 3 - 1, sx = x + t % 3 - 1;
-    if (sy < 0 || sy >= H || sx < 0 || sx >= W) return zero8();
-    if (ci < in.c1) {
-        const int h = H >> in.up1, w = W >> in.up1;
-        return load8(in.x1 + (((size_t)b * h + (sy >> in.up1)) * w + (sx >> in.up1)) * in.c1 + ci);
-    }
-    return load8(in.x2 + (((size_t)b * H + sy) * W + sx) * in.c2 + (ci - in.c1));
-}
-
 // ---------------------------------------------------------------------------
 // 3x3 convolution as an implicit GEMM: D[p][co] = sum_k A[p][k] W[co][k],
 // A = im2col of the input, k = tap * cin + ci.  A block computes an 8 x 16
@@ -87,8 +69,9 @@ __device__ __forceinline__ bf16x8 im2col8(const ConvIn<T>& in, int H, int W, int
 // staged 32 channels at a time as the 10 x 18 halo tile around the output
 // tile (zero outside the image), once per chunk, so each of the nine taps of
 // a chunk reads its A operand from LDS at a shifted pixel: no per-step
-// index arithmetic or bounds checks.  The weights of one (chunk, tap) step
-// (64 x 32) go through a second double buffer, loaded one step ahead.
+// index arithmetic or bounds checks.  The weights go through LDS as well,
+// one (chunk, tap) step (64 x 32) at a time in a double buffer loaded ahead,
+// or a whole chunk at once (below: which layers take which).
 // ---------------------------------------------------------------------------
 constexpr int CBK = 32, CLD = CBK + 8;
 #ifndef MSR_UNET_WAVE_ROWS
@@ -135,7 +118,14 @@ __device__ __forceinline__ bf16x8 pixel8(const ConvIn<T>& in, int cin, int H, in
 }
 
 // NT 32-channel output tiles per wave (1 for layers of at most 32 output
-// channels, else 2); the weights of a step are fetched WD steps ahead.
+// channels, else 2).  Two ways to stage the weights: a tap at a time (a
+// barrier per tap; little LDS, so many resident blocks) or a chunk at a time
+// (two barriers per chunk; nine taps of weights in LDS).  These layers wait on
+// their loads more than on the matrix cores, so resident blocks count most:
+// the chunk-wide staging is faster (24 % forward, 7 % backward at 4096^2)
+// only for layers of at most 32 output channels and several input chunks,
+// where its LDS is small and the per-tap path pays the most barriers; at 64
+// output channels it halves the resident blocks and is 8-28 % slower.
 #ifndef MSR_UNET_WD
 #define MSR_UNET_WD 3
 #endif
@@ -144,56 +134,116 @@ __device__ __forceinline__ bf16x8 pixel8(const ConvIn<T>& in, int cin, int H, in
 #endif
 constexpr int WD = MSR_UNET_WD;
 static_assert(9 % WD == 0, "the step loop advances WD steps at a time over 9 steps per chunk");
-// halo buffers of a multi-chunk layer: 2 (the next chunk is written while the
-// current one is read) or 1 (written after a barrier at the chunk's end: less
-// LDS, one more barrier per chunk)
+// halo buffers of a multi-chunk layer (per-tap weights): 2 (the next chunk is
+// written while the current one is read) or 1 (written after a barrier at the
+// chunk's end: less LDS, one more barrier per chunk)
 constexpr int HBUFS = MSR_UNET_HALO_BUFS;
 
-// ONE: the input has at most 32 channels (one chunk, one halo buffer: half
-// the LDS, so twice the resident blocks to cover the load latency).
-template <typename T, bool BWD, int NT, bool ONE>
-__global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
-    constexpr int BN = 32 * NT;  // output channels of a block
-    __shared__ __attribute__((aligned(16))) bf16 Hs[ONE ? 1 : HBUFS][NHALO * HLD];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * CLD];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// Output tile position of this block: image b, rows y0.., columns x0.., output channels n0..
+struct ConvTile {
+    int b, y0, x0, n0;
+};
+__device__ __forceinline__ ConvTile conv_tile(const ConvOut& o, int BN) {
     const int tiles_x = (o.W + TC - 1) / TC, tiles_y = (o.H + TR - 1) / TR;
-    const int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y, b = blockIdx.x / (tiles_x * tiles_y);
-    const int y0 = ty * TR, x0 = tx * TC, n0 = blockIdx.y * BN;
-    const int cin = in.c1 + in.c2;
-    const int nsteps = 9 * ((cin + CBK - 1) / CBK);  // (chunk, tap) steps, a multiple of WD
+    const int tx = blockIdx.x % tiles_x, ty = (blockIdx.x / tiles_x) % tiles_y;
+    return ConvTile{(int)blockIdx.x / (tiles_x * tiles_y), ty * TR, tx * TC, (int)blockIdx.y * BN};
+}
 
-    // halo items of this thread: pixel q / 4 of the halo tile, channels 8 (q % 4) of the chunk
+// Halo items of thread tid: pixel q / 4 of the halo tile, channels 8 (q % 4) of chunk c0.
+template <typename T>
+__device__ __forceinline__ void conv_fetch_halo(const ConvIn<T>& in, const ConvOut& o, const ConvTile& tl, int cin,
+                                                int c0, int tid, bf16x8 (&rh)[HPT]) {
+#pragma unroll
+    for (int u = 0; u < HPT; ++u) {
+        const int q = tid + u * 256;
+        const int hp = q >> 2;
+        rh[u] = q < HITEMS ? pixel8(in, cin, o.H, o.W, tl.b, tl.y0 - 1 + hp / HC, tl.x0 - 1 + hp % HC, c0 + (q & 3) * 8)
+                           : zero8();
+    }
+}
+__device__ __forceinline__ void conv_stage_halo(bf16* hs, int tid, const bf16x8 (&rh)[HPT]) {
+#pragma unroll
+    for (int u = 0; u < HPT; ++u) {
+        const int q = tid + u * 256;
+        if (q < HITEMS) *reinterpret_cast<bf16x8*>(&hs[(q >> 2) * HLD + (q & 3) * 8]) = rh[u];
+    }
+}
+
+// Bias, activation and stores of a wave's MT x NT accumulator tiles:
+// acc[m][nt][r] is tile pixel (WROWS wave + 2 m) * 16 + (r / 4) * 8 +
+// (lane / 32) * 4 + r % 4, output channel n0 + 32 nt + lane % 32.
+template <bool BWD, int NT>
+__device__ __forceinline__ void conv_epilogue(const ConvOut& o, const ConvTile& tl, const f32x16 (&acc)[MT][NT],
+                                              int wave, int lane) {
+    const int pl = lane & 31;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int co = tl.n0 + nt * 32 + pl;
+        if (co >= o.cout) continue;
+        const float bias = o.bias ? o.bias[co] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int q = (WROWS * wave + 2 * m) * 16 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);  // tile pixel
+            const int y = tl.y0 + (q >> 4), x = tl.x0 + (q & 15);
+            if (y >= o.H || x >= o.W) continue;
+            const size_t p = ((size_t)tl.b * o.H + y) * o.W + x;
+            const float v = acc[m][nt][r] + bias;
+            if constexpr (!BWD) {
+                o.y[p * o.cout + co] = (bf16)(o.relu ? fmaxf(v, 0.0f) : v);
+            } else {
+                if (co < o.split) {
+                    const size_t i = p * o.split + co;
+                    o.g1[i] = (o.m1 && !((float)o.m1[i] > 0.0f)) ? 0.0f : v;
+                } else {
+                    const int l2 = o.cout - o.split;
+                    const size_t i = p * l2 + (co - o.split);
+                    const float g = (o.m2 && !((float)o.m2[i] > 0.0f)) ? 0.0f : v;
+                    o.g2[i] = o.acc2 ? o.g2[i] + g : g;
+                }
+            }
+        }
+    }
+}
+
+// Weights staged a chunk at a time.  LDS: the halo tile of the chunk and the
+// chunk's weights, nine taps of BN rows x 32 channels (37 KB at NT = 1).  The next chunk's halo and weights are
+// loaded into registers while the current chunk's 18 MFMA k-steps run from
+// LDS, and written after the barrier that ends it.
+template <typename T, bool BWD, int NT>
+__device__ __forceinline__ void conv_body_chunk(const ConvIn<T>& in, const ConvOut& o) {
+    constexpr int BN = 32 * NT;
+    constexpr int WITEMS = 9 * BN * (CBK / 8);  // 16-byte groups of a chunk's weights
+    constexpr int WPT = (WITEMS + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 Hs[NHALO * HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[9 * BN * CLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const ConvTile tl = conv_tile(o, BN);
+    const int cin = in.c1 + in.c2;
+    const int nchunks = (cin + CBK - 1) / CBK;
+
     bf16x8 rh[HPT];
-    auto fetch_halo = [&](int c0) {
+    // weight item q: tap q / (4 BN), row (q / 4) % BN, channels 8 (q % 4) of the chunk
+    bf16x8 rw[WPT];
+    auto fetch_w = [&](int c) {
 #pragma unroll
-        for (int u = 0; u < HPT; ++u) {
+        for (int u = 0; u < WPT; ++u) {
             const int q = tid + u * 256;
-            const int hp = q >> 2;
-            rh[u] = q < HITEMS ? pixel8(in, cin, o.H, o.W, b, y0 - 1 + hp / HC, x0 - 1 + hp % HC, c0 + (q & 3) * 8)
-                               : zero8();
+            const int t = q / (4 * BN), r = q - t * (4 * BN);
+            const int co = tl.n0 + (r >> 2), ci = c * CBK + (r & 3) * 8;
+            rw[u] = (q < WITEMS && co < o.cout && ci < cin) ? load8(o.w + (size_t)co * o.kpad + t * cin + ci) : zero8();
         }
     };
-    auto stage_halo = [&](int buf) {
+    auto stage_w = [&]() {
 #pragma unroll
-        for (int u = 0; u < HPT; ++u) {
+        for (int u = 0; u < WPT; ++u) {
             const int q = tid + u * 256;
-            if (q < HITEMS) *reinterpret_cast<bf16x8*>(&Hs[buf][(q >> 2) * HLD + (q & 3) * 8]) = rh[u];
+            if (q < WITEMS) {
+                const int t = q / (4 * BN), r = q - t * (4 * BN);
+                *reinterpret_cast<bf16x8*>(&Bs[(t * BN + (r >> 2)) * CLD + (r & 3) * 8]) = rw[u];
+            }
         }
-    };
-    // weights of step s = chunk * 9 + tap: row co, k = tap * cin + chunk * 32 + [0, 32);
-    // WD steps in flight, in registers
-    const int bco = n0 + tid / 4, bg = (tid % 4) * 8;
-    const bool bthr = tid < 4 * BN;
-    bf16x8 rb[WD];
-    auto fetch_w = [&](int st, bf16x8& r) {
-        const int c = st / 9, t = st - 9 * c;
-        const int ci = c * CBK + bg;
-        r = (bthr && st < nsteps && bco < o.cout && ci < cin) ? load8(o.w + (size_t)bco * o.kpad + t * cin + ci)
-                                                               : zero8();
-    };
-    auto stage_w = [&](int buf, const bf16x8& r) {
-        if (bthr) *reinterpret_cast<bf16x8*>(&Bs[buf][(tid / 4) * CLD + bg]) = r;
     };
 
     // A operand rows of this lane in MFMA tile m: tile pixel
@@ -207,9 +257,87 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[m][j] = f32x16{};
-    fetch_halo(0);
+    conv_fetch_halo(in, o, tl, cin, 0, tid, rh);
+    fetch_w(0);
+    conv_stage_halo(Hs, tid, rh);
+    stage_w();
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const bool more = c + 1 < nchunks;
+        if (more) {  // the next chunk, in registers
+            conv_fetch_halo(in, o, tl, cin, (c + 1) * CBK, tid, rh);
+            fetch_w(c + 1);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int hp = hbase + (t / 3 - 1) * HC + (t % 3 - 1);
+#pragma unroll
+            for (int kk = 0; kk < CBK; kk += 16) {
+                bf16x8 av[MT], bv[NT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    av[m] = *reinterpret_cast<const bf16x8*>(&Hs[(hp + 2 * m * HC) * HLD + kk + ko]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    bv[n] = *reinterpret_cast<const bf16x8*>(&Bs[(t * BN + 32 * n + pl) * CLD + kk + ko]);
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
+            }
+        }
+        if (more) {
+            __syncthreads();  // every wave has finished reading this chunk
+            conv_stage_halo(Hs, tid, rh);
+            stage_w();
+            __syncthreads();
+        }
+    }
+    conv_epilogue<BWD, NT>(o, tl, acc, wave, lane);
+}
+
+// Weights staged a tap at a time.  ONE: the input has at most 32 channels
+// (one chunk, one halo buffer: half the LDS, so twice the resident blocks to
+// cover the load latency).
+template <typename T, bool BWD, int NT, bool ONE>
+__device__ __forceinline__ void conv_body_tap(const ConvIn<T>& in, const ConvOut& o) {
+    constexpr int BN = 32 * NT;  // output channels of a block
+    __shared__ __attribute__((aligned(16))) bf16 Hs[ONE ? 1 : HBUFS][NHALO * HLD];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN * CLD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const ConvTile tl = conv_tile(o, BN);
+    const int cin = in.c1 + in.c2;
+    const int nsteps = 9 * ((cin + CBK - 1) / CBK);  // (chunk, tap) steps, a multiple of WD
+
+    bf16x8 rh[HPT];
+    // weights of step s = chunk * 9 + tap: row co, k = tap * cin + chunk * 32 + [0, 32);
+    // WD steps in flight, in registers
+    const int bco = tl.n0 + tid / 4, bg = (tid % 4) * 8;
+    const bool bthr = tid < 4 * BN;
+    bf16x8 rb[WD];
+    auto fetch_w = [&](int st, bf16x8& r) {
+        const int c = st / 9, t = st - 9 * c;
+        const int ci = c * CBK + bg;
+        r = (bthr && st < nsteps && bco < o.cout && ci < cin) ? load8(o.w + (size_t)bco * o.kpad + t * cin + ci)
+                                                               : zero8();
+    };
+    auto stage_w = [&](int buf, const bf16x8& r) {
+        if (bthr) *reinterpret_cast<bf16x8*>(&Bs[buf][(tid / 4) * CLD + bg]) = r;
+    };
+
+    const int pl = lane & 31;
+    const int hbase = (WROWS * wave + (pl >> 4) + 1) * HC + (pl & 15) + 1;
+    const int ko = (lane >> 5) * 8;
+
+    f32x16 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x16{};
+    conv_fetch_halo(in, o, tl, cin, 0, tid, rh);
     fetch_w(0, rb[0]);
-    stage_halo(0);
+    conv_stage_halo(Hs[0], tid, rh);
     stage_w(0, rb[0]);
 #pragma unroll
     for (int d = 1; d < WD; ++d) fetch_w(d, rb[d]);
@@ -224,7 +352,7 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
             const int t = st % 9;
             const int cur = st & 1;
             const bool more = st + 1 < nsteps;
-            if (!ONE && t == 0 && st + 9 < nsteps) fetch_halo((st / 9 + 1) * CBK);  // the next chunk, in registers
+            if (!ONE && t == 0 && st + 9 < nsteps) conv_fetch_halo(in, o, tl, cin, (st / 9 + 1) * CBK, tid, rh);
             const int hp = hbase + (t / 3 - 1) * HC + (t % 3 - 1);
 #pragma unroll
             for (int kk = 0; kk < CBK; kk += 16) {
@@ -246,9 +374,9 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
             // that ended it
             const int nxt = (j + 1) % WD;  // slot of step st + 1
             if (more) stage_w(cur ^ 1, rb[nxt]);
-            fetch_w(st + WD, rb[j]);            // slot j is free again: step st + WD
+            fetch_w(st + WD, rb[j]);  // slot j is free again: step st + WD
             if constexpr (!ONE && HBUFS == 2) {
-                if (t == 8 && more) stage_halo(hcur ^ 1);
+                if (t == 8 && more) conv_stage_halo(Hs[hcur ^ 1], tid, rh);
             }
             __syncthreads();
             if constexpr (!ONE && HBUFS == 2) {
@@ -257,42 +385,19 @@ __global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
             if constexpr (!ONE && HBUFS == 1) {
                 // every wave has read this chunk's halo (the barrier above)
                 if (t == 8 && more) {
-                    stage_halo(0);
+                    conv_stage_halo(Hs[0], tid, rh);
                     __syncthreads();
                 }
             }
         }
     }
+    conv_epilogue<BWD, NT>(o, tl, acc, wave, lane);
+}
 
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int co = n0 + nt * 32 + pl;
-        if (co >= o.cout) continue;
-        const float bias = o.bias ? o.bias[co] : 0.0f;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int q = (WROWS * wave + 2 * m) * 16 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);  // tile pixel
-            const int y = y0 + (q >> 4), x = x0 + (q & 15);
-            if (y >= o.H || x >= o.W) continue;
-            const size_t p = ((size_t)b * o.H + y) * o.W + x;
-            const float v = acc[m][nt][r] + bias;
-            if constexpr (!BWD) {
-                o.y[p * o.cout + co] = (bf16)(o.relu ? fmaxf(v, 0.0f) : v);
-            } else {
-                if (co < o.split) {
-                    const size_t i = p * o.split + co;
-                    o.g1[i] = (o.m1 && !((float)o.m1[i] > 0.0f)) ? 0.0f : v;
-                } else {
-                    const int l2 = o.cout - o.split;
-                    const size_t i = p * l2 + (co - o.split);
-                    const float g = (o.m2 && !((float)o.m2[i] > 0.0f)) ? 0.0f : v;
-                    o.g2[i] = o.acc2 ? o.g2[i] + g : g;
-                }
-            }
-        }
-    }
+template <typename T, bool BWD, int NT, bool ONE>
+__global__ void __launch_bounds__(256) conv3x3_kernel(ConvIn<T> in, ConvOut o) {
+    if constexpr (NT == 1 && !ONE) conv_body_chunk<T, BWD, NT>(in, o);
+    else conv_body_tap<T, BWD, NT, ONE>(in, o);
 }
 
 // Launches the convolution with the output-channel blocking of `cout`.
@@ -311,92 +416,240 @@ void launch_conv(const ConvIn<T>& in, const ConvOut& o, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient: dW[co][k] = sum_p G[p][co] A[p][k] over a chunk of pixels
-// per block (grid z), partial tiles reduced afterwards.  Block: 64 output
-// channels x 64 k, 4 waves of 32 x 32; 32 pixels staged per step, stored
-// transposed in LDS so each MFMA operand is one 16-byte read.
+// Weight gradient as an implicit GEMM over pixels:
+//   dW[co][t cin + ci] = sum_p G[p][co] X[p + off_t][ci]
+// (G the output gradient, X the layer's input, zero outside the image).  A
+// block owns 32 NT output channels x one 32-channel input chunk x the nine
+// taps (9 NT accumulator tiles of 32 x 32) and sums over every nz-th 8 x 16
+// pixel tile (grid z; the partial results are added afterwards).  3 NT
+// waves: wave w takes output subtile w / 3 and the tap row dy = w % 3, one
+// accumulator per dx.  Per pixel tile, G is staged transposed (Gs[co][pixel])
+// and the input chunk's 10 x 18 halo transposed in three copies shifted by
+// dx (Xs[dx][ci][hrow][col] = X(hrow, col + dx)), so that both MFMA operands
+// of a K step (one tile row, 16 pixels) are aligned 16-byte LDS reads at
+// every tap.  The blocks of the first input chunk also sum G over their
+// pixels in float32 (the bias gradient), one partial per pixel-tile group.
 // ---------------------------------------------------------------------------
 struct WGradArgs {
     const float* g;  // [P][cout]
-    int B, H, W, cout, kpad, chunk;
-    float* part;     // [gridDim.z][cout][kpad]
+    int B, H, W, cout, kpad;
+    int nz;          // pixel-tile groups (grid z)
+    float* part;     // [nz][cout][kpad]; entries k >= 9 cin are not written
+    float* bpart;    // [nz][cout]: sums of G over each group's pixels
 };
 
-template <typename T>
-__global__ void __launch_bounds__(256) conv3x3_wgrad_kernel(ConvIn<T> in, WGradArgs a) {
-    __shared__ __attribute__((aligned(16))) bf16 Gs[64 * CLD];
-    __shared__ __attribute__((aligned(16))) bf16 Xs[64 * CLD];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int P = a.B * a.H * a.W, hw = a.H * a.W;
-    const int c0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
-    const int pbeg = blockIdx.z * a.chunk, pend = min(P, pbeg + a.chunk);
-    const int wc = (wave >> 1) * 32, wk = (wave & 1) * 32;
-    const int lp = tid >> 3, lg = (tid & 7) * 8;  // staged pixel, 8-wide group
+constexpr int GLD = TR * TC + 8;        // bf16 per Gs row (one output channel; 272 B)
+constexpr int XCS = HR * TC + 8;        // bf16 per input channel of one Xs copy (336 B)
+constexpr int WG_XITEMS = NHALO * (CBK / 8);  // 16-byte groups of one halo chunk
 
-    f32x16 acc = {};
-    for (int pp = pbeg; pp < pend; pp += 32) {
-        const int p = pp + lp;
-        const bool ok = p < pend;
-        {
-            const int co = c0 + lg;
-            float gv[8];
-            if (ok && co < a.cout) {
-                const float4 u = *reinterpret_cast<const float4*>(a.g + (size_t)p * a.cout + co);
-                const float4 v = *reinterpret_cast<const float4*>(a.g + (size_t)p * a.cout + co + 4);
-                gv[0] = u.x, gv[1] = u.y, gv[2] = u.z, gv[3] = u.w, gv[4] = v.x, gv[5] = v.y, gv[6] = v.z, gv[7] = v.w;
-            } else {
+template <int NT>
+__global__ void __launch_bounds__(192 * NT) conv3x3_wgrad_kernel(ConvIn<bf16> in, WGradArgs a) {
+    constexpr int NTH = 192 * NT;            // threads
+    constexpr int GITEMS = (TR * TC / 2) * 4 * NT;  // (pixel pair, 8-channel group) items of a G tile
+    __shared__ __attribute__((aligned(16))) bf16 Gs[32 * NT * GLD];
+    __shared__ __attribute__((aligned(16))) bf16 Xs[3 * CBK * XCS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n0 = blockIdx.x * 32 * NT, chunk = blockIdx.y;
+    const int cin = in.c1 + in.c2;
+    const int tiles_x = (a.W + TC - 1) / TC, tiles_y = (a.H + TR - 1) / TR;
+    const int ntiles = a.B * tiles_x * tiles_y;
+    const int sub = wave / 3, dy = wave % 3;
+    const int pl = lane & 31, ko = (lane >> 5) * 8;
+
+    f32x16 acc[3];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) gv[j] = 0.0f;
+    for (int dx = 0; dx < 3; ++dx) acc[dx] = f32x16{};
+    // this thread's G items are always channels 8 (tid % (4 NT)) ..: their sums
+    float bsum[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bsum[j] = 0.0f;
+    static_assert(NTH % (4 * NT) == 0, "a thread keeps one channel group");
+    for (int tile = blockIdx.z; tile < ntiles; tile += a.nz) {
+        const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, b = tile / (tiles_x * tiles_y);
+        const int y0 = ty * TR, x0 = tx * TC;
+        __syncthreads();  // the previous tile's operands have been read
+        // G: item q = (pixel pair q / (4 NT), channels 8 (q % (4 NT))), written as bf16 pairs
+        for (int q = tid; q < GITEMS; q += NTH) {
+            const int pp = q / (4 * NT), grp = q - pp * (4 * NT);
+            const int px = 2 * pp, co = n0 + grp * 8;
+            const int y = y0 + px / TC, x = x0 + px % TC;  // both pixels of the pair are in one tile row
+            float g0[8], g1[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) g0[j] = g1[j] = 0.0f;
+            if (y < a.H && co < a.cout) {
+                const size_t p = ((size_t)b * a.H + y) * a.W + x;
+                if (x < a.W) {
+                    const float4 u = *reinterpret_cast<const float4*>(a.g + p * a.cout + co);
+                    const float4 v = *reinterpret_cast<const float4*>(a.g + p * a.cout + co + 4);
+                    g0[0] = u.x, g0[1] = u.y, g0[2] = u.z, g0[3] = u.w, g0[4] = v.x, g0[5] = v.y, g0[6] = v.z, g0[7] = v.w;
+                }
+                if (x + 1 < a.W) {
+                    const float4 u = *reinterpret_cast<const float4*>(a.g + (p + 1) * a.cout + co);
+                    const float4 v = *reinterpret_cast<const float4*>(a.g + (p + 1) * a.cout + co + 4);
+                    g1[0] = u.x, g1[1] = u.y, g1[2] = u.z, g1[3] = u.w, g1[4] = v.x, g1[5] = v.y, g1[6] = v.z, g1[7] = v.w;
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) Gs[(lg + j) * CLD + lp] = (bf16)gv[j];
-        }
-        {
-            bf16x8 xv = zero8();
-            if (ok && k0 + lg < a.kpad) {
-                const int b = p / hw, r = p - b * hw, y = r / a.W, x = r - y * a.W;
-                xv = im2col8(in, a.H, a.W, b, y, x, k0 + lg);
+            for (int j = 0; j < 8; ++j) bsum[j] += g0[j] + g1[j];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+                bf16x2 w2;
+                w2[0] = (bf16)g0[j];
+                w2[1] = (bf16)g1[j];
+                *reinterpret_cast<bf16x2*>(&Gs[(grp * 8 + j) * GLD + px]) = w2;
             }
+        }
+        // X: item q = (halo pixel q / 4, channels 8 (q % 4) of the chunk) into each copy that holds it
+        for (int q = tid; q < WG_XITEMS; q += NTH) {
+            const int hp = q >> 2, ci = (q & 3) * 8;
+            const int hr = hp / HC, hc = hp - hr * HC;
+            const bf16x8 v = pixel8(in, cin, a.H, a.W, b, y0 - 1 + hr, x0 - 1 + hc, chunk * CBK + ci);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) Xs[(lg + j) * CLD + lp] = xv[j];
+            for (int dx = 0; dx < 3; ++dx) {
+                const int col = hc - dx;
+                if (col >= 0 && col < TC) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) Xs[(dx * CBK + ci + j) * XCS + hr * TC + col] = v[j];
+                }
+            }
         }
         __syncthreads();
+        // K steps: tile rows r; A = G^T rows (this wave's 32 channels) over the
+        // row's 16 pixels, B = the input at tap (dy, dx) over the same pixels
 #pragma unroll
-        for (int kk = 0; kk < 32; kk += 16) {
-            const int po = kk + (lane >> 5) * 8;
-            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&Gs[(wc + (lane & 31)) * CLD + po]);
-            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Xs[(wk + (lane & 31)) * CLD + po]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        for (int r = 0; r < TR; ++r) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&Gs[(sub * 32 + pl) * GLD + r * TC + ko]);
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Xs[(dx * CBK + pl) * XCS + (r + dy) * TC + ko]);
+                acc[dx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[dx], 0, 0, 0);
+            }
         }
-        __syncthreads();
     }
-    const int k = k0 + wk + (lane & 31);
-    if (k >= a.kpad) return;
+    if (chunk == 0) {
+        // bias partial of each of the block's channels: its threads' sums in thread order
+        __syncthreads();  // Gs is free: every wave has done its last MFMA reads
+        float* red = reinterpret_cast<float*>(Gs);
+        static_assert(NTH * 8 * sizeof(float) <= sizeof(Gs), "reduction scratch fits Gs");
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[tid * 8 + j] = bsum[j];
+        __syncthreads();
+        if (tid < 32 * NT) {
+            const int grp = tid >> 3, j = tid & 7;
+            float tot = 0.0f;
+            for (int t = grp; t < NTH; t += 4 * NT) tot += red[t * 8 + j];
+            if (n0 + tid < a.cout) a.bpart[(size_t)blockIdx.z * a.cout + n0 + tid] = tot;
+        }
+    }
+    // acc[dx][e]: output channel n0 + 32 sub + (e / 4) * 8 + (lane / 32) * 4 + e % 4, input channel
+    // chunk * 32 + lane % 32, tap 3 dy + dx
+    const int ci = chunk * CBK + pl;
+    if (ci >= cin) return;
     float* part = a.part + (size_t)blockIdx.z * a.cout * a.kpad;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int co = c0 + wc + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        if (co < a.cout) part[(size_t)co * a.kpad + k] = acc[r];
+    for (int dx = 0; dx < 3; ++dx) {
+        const int k = (3 * dy + dx) * cin + ci;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int co = n0 + sub * 32 + (e >> 2) * 8 + (lane >> 5) * 4 + (e & 3);
+            if (co < a.cout) part[(size_t)co * a.kpad + k] = acc[dx][e];
+        }
     }
 }
 
-// out[i] = sum_z part[z][i]  (fixed order: deterministic)
-__global__ void sum_parts_kernel(const float* __restrict__ part, int nz, size_t n, float* __restrict__ out) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int z = 0; z < nz; ++z) s += part[(size_t)z * n + i];
-        out[i] = s;
+// dW[co][k] = sum_z part[z][co][k] for k < kvalid; entries k >= kvalid keep
+// the zero the gradient was cleared to.  A block takes 32 consecutive
+// entries; its 8 thread rows sum every 8th z, then the 8 row sums are added
+// in order (deterministic).
+__global__ void __launch_bounds__(256) sum_wparts_kernel(const float* __restrict__ part, int nz, int cout, int kpad,
+                                                         int kvalid, float* __restrict__ out) {
+    __shared__ float red[8][32];
+    const size_t n = (size_t)cout * kpad;
+    const int l = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    for (size_t i0 = (size_t)blockIdx.x * 32; i0 < n; i0 += (size_t)gridDim.x * 32) {
+        const size_t i = i0 + l;
+        const bool ok = i < n && (int)(i % (size_t)kpad) < kvalid;
+        float sm = 0.0f;
+        if (ok)
+            for (int z = sl; z < nz; z += 8) sm += part[(size_t)z * n + i];
+        red[sl][l] = sm;
+        __syncthreads();
+        if (sl == 0 && ok) {
+            float t = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) t += red[r][l];
+            out[i] = t;
+        }
+        __syncthreads();
     }
 }
 
-// Column sums of G [P][C] over pixel chunks: part[z][c] (bias gradients).
-__global__ void colsum_kernel(const float* __restrict__ g, int P, int C, int chunk, float* __restrict__ part) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    const int pb = blockIdx.y * chunk, pe = min(P, pb + chunk);
+// out[i] = sum_z part[z][i] for few outputs and many partials: one block
+// per output, each thread summing every 256th partial in order, then a fixed
+// tree across the block (deterministic).
+__global__ void __launch_bounds__(256) sum_parts_wide_kernel(const float* __restrict__ part, int nz, int n,
+                                                             float* __restrict__ out) {
+    __shared__ float red[256];
+    const int i = blockIdx.x, t = threadIdx.x;
     float s = 0.0f;
-    for (int p = pb; p < pe; ++p) s += g[(size_t)p * C + c];
-    part[(size_t)blockIdx.y * C + c] = s;
+    for (int z = t; z < nz; z += 256) s += part[(size_t)z * n + i];
+    red[t] = s;
+    __syncthreads();
+#pragma unroll
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[i] = red[0];
+}
+
+// Blocks of a head-gradient sum over P pixels, and the pixels of each.
+inline int head_sum_blocks(int P) { return std::max(1, std::min(1024, (P + 4095) / 4096)); }
+inline int head_sum_chunk(int P) { return (P + head_sum_blocks(P) - 1) / head_sum_blocks(P); }
+
+// The head's weight and bias gradients over pixel chunks: part[z][c] = sum
+// over the chunk's pixels of gout[p] x[p][c] for c < C, and of gout[p] for
+// c = C.  With C + 1 <= 256 columns the block's threads form 256 / (C + 1)
+// rows (thread t: column t % (C + 1), pixels t / (C + 1), + rows, ...), so each
+// step of the block reads whole pixel rows; the rows' sums are added in order
+// in LDS.  Wider heads take columns t, t + 256, ... over every pixel.
+__global__ void __launch_bounds__(256) head_sums_kernel(const float* __restrict__ gout, const bf16* __restrict__ x,
+                                                        int P, int C, int chunk, float* __restrict__ part) {
+    __shared__ float red[256];
+    const int NC = C + 1;  // columns summed
+    const int t = threadIdx.x;
+    const int pb = blockIdx.x * chunk, pe = min(P, pb + chunk);
+    auto val = [&](int p, int c) -> float { return c < C ? gout[p] * (float)x[(size_t)p * C + c] : gout[p]; };
+    if (NC > 256) {
+        for (int c = t; c < NC; c += 256) {
+            float s = 0.0f;
+            for (int p = pb; p < pe; ++p) s += val(p, c);
+            part[(size_t)blockIdx.x * NC + c] = s;
+        }
+        return;
+    }
+    const int rows = 256 / NC, c = t % NC, j = t / NC;
+    float s = 0.0f;
+    if (j < rows) {
+        int p = pb + j;
+        // four independent loads in flight, summed in a fixed order
+        for (; p + 3 * rows < pe; p += 4 * rows) {
+            const float a0 = val(p, c), a1 = val(p + rows, c), a2 = val(p + 2 * rows, c), a3 = val(p + 3 * rows, c);
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; p < pe; p += rows) s += val(p, c);
+    }
+    red[t] = s;
+    __syncthreads();
+    if (t < NC) {
+        float tot = 0.0f;
+        for (int r = 0; r < rows; ++r) tot += red[r * NC + t];
+        part[(size_t)blockIdx.x * NC + t] = tot;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -423,17 +676,19 @@ __global__ void pool_kernel(const bf16* __restrict__ x, int B, int H, int W, int
 // gradient of an encoder output feeding both the pool and the skip.
 __global__ void pool_back_kernel(const float* __restrict__ dpool, const float* __restrict__ dskip,
                                  const bf16* __restrict__ e, int B, int H, int W, int C, float* __restrict__ g) {
-    const size_t n = (size_t)B * H * W * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        size_t r = i / C;
-        const int x = (int)(r % W);
-        r /= W;
-        const int y = (int)(r % H);
-        const int b = (int)(r / H);
-        float v = dskip ? dskip[i] : 0.0f;
-        if (dpool) v += 0.25f * dpool[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
-        g[i] = (float)e[i] > 0.0f ? v : 0.0f;
+    // 256 / C pixels of C channels per block step (C <= 256): one division per pixel
+    const unsigned rows = C <= 256 ? 256 / C : 1, np = (unsigned)B * H * W;
+    const unsigned j = threadIdx.x / C, c = threadIdx.x - j * C;
+    if (j >= rows) return;
+    for (unsigned p = blockIdx.x * rows + j; p < np; p += gridDim.x * rows) {
+        const unsigned x = p % W, r = p / W, y = r % H, b = r / H;
+        const size_t q = ((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2;
+        for (unsigned cc = c; cc < (unsigned)C; cc += 256) {
+            const size_t i = (size_t)p * C + cc;
+            float v = dskip ? dskip[i] : 0.0f;
+            if (dpool) v += 0.25f * dpool[q * C + cc];
+            g[i] = (float)e[i] > 0.0f ? v : 0.0f;
+        }
     }
 }
 
@@ -441,18 +696,18 @@ __global__ void pool_back_kernel(const float* __restrict__ dpool, const float* _
 // nearest upsampling of d (B, H, W, C); dup is (B, 2H, 2W, C).
 __global__ void up_back_kernel(const float* __restrict__ dup, const bf16* __restrict__ d, int B, int H, int W, int C,
                                float* __restrict__ g) {
-    const size_t n = (size_t)B * H * W * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        size_t r = i / C;
-        const int x = (int)(r % W);
-        r /= W;
-        const int y = (int)(r % H);
-        const int b = (int)(r / H);
-        const size_t base = (((size_t)b * 2 * H + 2 * y) * 2 * W + 2 * x) * C + c;
-        const size_t row = (size_t)2 * W * C;
-        const float s = dup[base] + dup[base + C] + dup[base + row] + dup[base + row + C];
-        g[i] = (float)d[i] > 0.0f ? s : 0.0f;
+    const unsigned rows = C <= 256 ? 256 / C : 1, np = (unsigned)B * H * W;
+    const unsigned j = threadIdx.x / C, c = threadIdx.x - j * C;
+    if (j >= rows) return;
+    const size_t row = (size_t)2 * W * C;
+    for (unsigned p = blockIdx.x * rows + j; p < np; p += gridDim.x * rows) {
+        const unsigned x = p % W, r = p / W, y = r % H, b = r / H;
+        const size_t base = (((size_t)b * 2 * H + 2 * y) * 2 * W + 2 * x) * C;
+        for (unsigned cc = c; cc < (unsigned)C; cc += 256) {
+            const size_t i = (size_t)p * C + cc, q = base + cc;
+            const float sm = dup[q] + dup[q + C] + dup[q + row] + dup[q + row + C];
+            g[i] = (float)d[i] > 0.0f ? sm : 0.0f;
+        }
     }
 }
 
@@ -555,24 +810,21 @@ __global__ void sum_double_kernel(const double* __restrict__ part, int n, double
     }
 }
 
-// Head backward: gx[p][c] = gout[p] w[c] (x > 0); per-block partials of
-// dw[c] = sum_p gout[p] x[p][c] and db = sum_p gout[p] (blockDim = 256, C < 256).
+// Head backward, the input gradient: gx[p][c] = gout[p] w[c] where x > 0
+// (the head's weight and bias gradients: head_sums_kernel).
 __global__ void __launch_bounds__(256) head_back_kernel(const bf16* __restrict__ x, const float* __restrict__ gout,
                                                         int P, int C, const float* __restrict__ wb,
-                                                        float* __restrict__ gx, float* __restrict__ part, int chunk) {
-    const int pb = blockIdx.x * chunk, pe = min(P, pb + chunk);
-    // one thread per channel (and one for the bias) accumulates over the chunk
-    float s = 0.0f;
-    if ((int)threadIdx.x <= C) {
-        for (int p = pb; p < pe; ++p) {
-            const float g = gout[p];
-            s += (int)threadIdx.x < C ? g * (float)x[(size_t)p * C + threadIdx.x] : g;
+                                                        float* __restrict__ gx) {
+    // 256 / C pixels of C channels per block step (C <= 256), no division per element
+    const int rows = C <= 256 ? 256 / C : 1;
+    const int j = threadIdx.x / C, c = threadIdx.x - j * C;
+    if (j >= rows) return;
+    for (size_t p = (size_t)blockIdx.x * rows + j; p < (size_t)P; p += (size_t)gridDim.x * rows) {
+        const float g = gout[p];
+        for (int cc = c; cc < C; cc += 256) {
+            const size_t i = p * C + cc;
+            gx[i] = (float)x[i] > 0.0f ? g * wb[cc] : 0.0f;
         }
-        part[(size_t)blockIdx.x * (C + 1) + threadIdx.x] = s;
-    }
-    for (int i = pb * C + threadIdx.x; i < pe * C; i += 256) {
-        const int p = i / C, c = i - p * C;
-        gx[i] = (float)x[i] > 0.0f ? gout[p] * wb[c] : 0.0f;
     }
 }
 
@@ -713,11 +965,19 @@ struct Plan {
 
 int npix(const Plan& p, int level) { return p.B * (p.H >> level) * (p.W >> level); }
 
-// Split-K chunk (pixels) of a weight-gradient launch: about 1024 blocks.
-int wgrad_chunk(int P, int tiles) {
-    int nz = std::max(1, std::min((P + 31) / 32, 1024 / std::max(tiles, 1)));
-    int chunk = round_up((P + nz - 1) / nz, 32);
-    return chunk;
+// Weight-gradient launch of a layer: output-channel blocks (32 NT channels),
+// input chunks and pixel-tile groups (grid z), about 2048 blocks in all.
+struct WGradGrid {
+    int nt, cob, chunks, nz;
+};
+WGradGrid wgrad_grid(int B, int H, int W, int cin, int cout) {
+    WGradGrid g;
+    g.nt = cout <= 32 ? 1 : 2;
+    g.cob = (cout + 32 * g.nt - 1) / (32 * g.nt);
+    g.chunks = (cin + CBK - 1) / CBK;
+    const int ntiles = conv_tiles(B, H, W);
+    g.nz = std::max(1, std::min(ntiles, (2048 + g.cob * g.chunks - 1) / (g.cob * g.chunks)));
+    return g;
 }
 
 bool make_plan(const Net& n, int B, int H, int W, Plan& p) {
@@ -765,14 +1025,10 @@ bool make_plan(const Net& n, int B, int H, int W, Plan& p) {
     p.scale = take(4 * (size_t)B);
     size_t pf = 0;
     for (const Layer& l : n.L) {
-        const int P = npix(p, l.level);
-        const int tiles = ((l.cout + 63) / 64) * ((l.kpad + 63) / 64);
-        const int chunk = wgrad_chunk(P, tiles);
-        const int nz = (P + chunk - 1) / chunk;
-        pf = std::max(pf, (size_t)nz * l.cout * l.kpad);
-        pf = std::max(pf, (size_t)((P + 1023) / 1024) * l.cout);  // bias partials
+        const WGradGrid g = wgrad_grid(B, H >> l.level, W >> l.level, l.cin, l.cout);
+        pf = std::max(pf, (size_t)g.nz * l.cout * (l.kpad + 1));  // weight and bias partials
     }
-    pf = std::max(pf, (size_t)((npix(p, 0) + 1023) / 1024) * (n.width + 1));  // head partials
+    pf = std::max(pf, (size_t)head_sum_blocks(npix(p, 0)) * (n.width + 1));  // head partials
     pf = std::max(pf, (size_t)B * kScaleBlocks);                              // input-scale partials
     p.part_floats = pf;
     p.part = take(4 * pf);
@@ -913,7 +1169,6 @@ struct Run {
     // dW, db of layer i from its output gradient and its input
     msr_status wgrad(int i) {
         const Layer& l = n.L[i];
-        const int P = np(l.level);
         WGradArgs a{};
         a.g = gact(i);
         a.B = B;
@@ -921,24 +1176,24 @@ struct Run {
         a.W = ww(l.level);
         a.cout = l.cout;
         a.kpad = l.kpad;
-        const int tiles = ((l.cout + 63) / 64) * ((l.kpad + 63) / 64);
-        a.chunk = wgrad_chunk(P, tiles);
-        const int nz = (P + a.chunk - 1) / a.chunk;
-        if ((size_t)nz * l.cout * l.kpad > p.part_floats) return ufail(u, MSR_ERR_INVALID, "partials too small");
+        const ConvIn<bf16> in = input(i);
+        const int cin = in.c1 + in.c2;
+        const WGradGrid g = wgrad_grid(B, a.H, a.W, cin, l.cout);
+        a.nz = g.nz;
+        if ((size_t)g.nz * l.cout * (l.kpad + 1) > p.part_floats || 9 * cin > l.kpad)
+            return ufail(u, MSR_ERR_INVALID, "weight-gradient partials too small");
         a.part = at<float>(p.part);
-        hipLaunchKernelGGL(conv3x3_wgrad_kernel<bf16>, dim3((l.cout + 63) / 64, (l.kpad + 63) / 64, nz), dim3(256), 0,
-                           s, input(i), a);
+        a.bpart = a.part + (size_t)g.nz * l.cout * l.kpad;
+        const dim3 grid(g.cob, g.chunks, g.nz);
+        if (g.nt == 1) hipLaunchKernelGGL(conv3x3_wgrad_kernel<1>, grid, dim3(192), 0, s, in, a);
+        else hipLaunchKernelGGL(conv3x3_wgrad_kernel<2>, grid, dim3(384), 0, s, in, a);
         ULAUNCH(u);
         const size_t nw = (size_t)l.cout * l.kpad;
-        hipLaunchKernelGGL(sum_parts_kernel, dim3(grid_for(nw)), dim3(256), 0, s, at<float>(p.part), nz, nw,
-                           grad() + l.w_off);
+        hipLaunchKernelGGL(sum_wparts_kernel, dim3(grid_for(nw, 32)), dim3(256), 0, s, at<float>(p.part), g.nz,
+                           l.cout, l.kpad, 9 * cin, grad() + l.w_off);
         ULAUNCH(u);
-        const int chunk = 1024, nb = (P + chunk - 1) / chunk;
-        hipLaunchKernelGGL(colsum_kernel, dim3((l.cout + 255) / 256, nb), dim3(256), 0, s, gact(i), P, l.cout, chunk,
-                           at<float>(p.part));
-        ULAUNCH(u);
-        hipLaunchKernelGGL(sum_parts_kernel, dim3(grid_for(l.cout)), dim3(256), 0, s, at<float>(p.part), nb,
-                           (size_t)l.cout, grad() + l.b_off);
+        hipLaunchKernelGGL(sum_parts_wide_kernel, dim3(l.cout), dim3(256), 0, s, a.bpart, g.nz, l.cout,
+                           grad() + l.b_off);
         ULAUNCH(u);
         return MSR_OK;
     }
@@ -994,12 +1249,15 @@ struct Run {
         ULAUNCH(u);
         // head
         {
-            const int chunk = 1024, nb = (P0 + chunk - 1) / chunk;
-            hipLaunchKernelGGL(head_back_kernel, dim3(nb), dim3(256), 0, s, act(top), at<float>(p.gout), P0, n.width,
-                               params() + n.head_off, gact(top), at<float>(p.part), chunk);
+            hipLaunchKernelGGL(head_back_kernel, dim3(grid_for((size_t)P0 * n.width)), dim3(256), 0, s, act(top),
+                               at<float>(p.gout), P0, n.width, params() + n.head_off, gact(top));
             ULAUNCH(u);
-            hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, s, at<float>(p.part), nb,
-                               (size_t)(n.width + 1), grad() + n.head_off);
+            const int nb = head_sum_blocks(P0);
+            hipLaunchKernelGGL(head_sums_kernel, dim3(nb), dim3(256), 0, s, at<float>(p.gout), act(top), P0, n.width,
+                               head_sum_chunk(P0), at<float>(p.part));
+            ULAUNCH(u);
+            hipLaunchKernelGGL(sum_parts_wide_kernel, dim3(n.width + 1), dim3(256), 0, s, at<float>(p.part), nb,
+                               n.width + 1, grad() + n.head_off);
             ULAUNCH(u);
         }
         // decoder, top level first
