@@ -138,6 +138,105 @@ def batch_bench(torch, dev, count, iters, seed=4, sizes=(512, 1024, 2048, 4096))
     return out
 
 
+def pipeline_bench(torch, dev, count=16, iters=500, seed=5, sizes=(1024, 2048, 4096, 8192), horizon=24000,
+                   every=500, workers=16):
+    """The whole method on the frequency channels of one observation with
+    uneven image sizes up to 8192^2: `count` channels with sizes drawn from
+    `sizes` (the seed gives at least one of the largest), 512 antennas 4 h at
+    10 s, cut 10 %, positivity on.  Step 1 batched (`iters` iterations), each
+    channel's low-resolution image, sigma2_hat and filters, the packaged
+    network's prediction of each channel's step-2 image, then step 2 batched
+    from zero and from the predictions (`iters` iterations each; FP32).  On
+    the first channel of the largest size, step 2's time to 1e-5 and 1e-6
+    relative objectives from both starts, read off trajectories of `horizon`
+    iterations (F_ref: the lower of the two runs' lowest objectives)."""
+    import synth
+    from paper_2406_18356_amd import Batch, UNet, warmstart as ws
+
+    cfgs = synth.channel_set(count, sizes=sizes, seed=seed, cut=0.10, n_ant=512, hours=4.0, dt_s=10.0)
+    if not any(c.n == max(sizes) for c in cfgs):
+        raise ValueError(f"seed {seed} draws no channel of {max(sizes)}^2")
+    t = time.perf_counter()
+    prs = synth.make_problems(cfgs, workers=workers, verbose=True,
+                              progress=lambda i, p: log(f"pipeline: channel {i} ({p.n}^2) generated, "
+                                                        f"{time.perf_counter() - t:.0f} s"))
+    gen_s = time.perf_counter() - t
+    sz = [int(p.n) for p in prs]
+    log(f"pipeline: {count} channels {sz} generated in {gen_s:.1f} s")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
+    b = Batch(sz, positivity=True)
+    dhs = []
+    for pr, ch in zip(prs, b.channels):
+        ch.set_dirty_psf(1, T(pr.dirty_L), T(pr.psf_L))
+        dh = T(pr.dirty_H)
+        ch.set_dirty_psf(2, dh, T(pr.psf_H))
+        sig2 = ch.estimate_sigma2(dh)
+        ch.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        dhs.append(dh)
+    b.autotune(reps=5)
+    out = {"channels": count, "sizes": sz, "iters": iters, "generate_s": gen_s,
+           "workspace_gib": b.workspace_bytes / 2**30}
+    # step 1, then each channel's low-resolution image
+    lam1 = [ch.default_lambda(1, 1, 0.05) for ch in b.channels]
+    b.solve(1, lam1, iters, image=True)  # theta, graph capture
+    torch.cuda.synchronize()
+    _, imgs, res1 = b.solve(1, lam1, iters, image=True)
+    out["step1_channel_iters_per_s"] = count * iters / (res1[0].elapsed_ms * 1e-3)
+    log(f"pipeline: step 1 {res1[0].elapsed_ms / iters * 1e3:.1f} us per iteration of all channels")
+    low = [im.contiguous() for im in imgs]
+    lam2 = [ch.default_lambda(2, 1, 0.05) for ch in b.channels]
+    # the network's prediction of every channel (one network per image size)
+    params, meta = ws.load_weights()
+    x_net, fwd_ms = [None] * count, [0.0] * count
+    for n in sorted(set(sz)):
+        net = UNet(1, n)
+        net.set_params(params)
+        for c in range(count):
+            if sz[c] == n:
+                x, ms = ws.timed_forward(net, dhs[c][None].contiguous(), low[c][None].contiguous())
+                x_net[c], fwd_ms[c] = x[0].contiguous(), ms
+        del net
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log(f"pipeline: network predictions at {n}^2 done")
+    out["network_forward_ms"] = fwd_ms
+    # step 2 from zero and from the predictions
+    b.solve(2, lam2, iters, low_res=low)  # theta, graph capture
+    torch.cuda.synchronize()
+    m_cold, r_cold = b.solve(2, lam2, iters, low_res=low)
+    m_warm, r_warm = b.solve(2, lam2, iters, low_res=low, x0=x_net)
+    out["step2_channel_iters_per_s"] = count * iters / (r_cold[0].elapsed_ms * 1e-3)
+    out["step2_warm_channel_iters_per_s"] = count * iters / (r_warm[0].elapsed_ms * 1e-3)
+    log(f"pipeline: step 2 {r_cold[0].elapsed_ms / iters * 1e3:.1f} us per iteration of all channels")
+    per = []
+    for c, ch in enumerate(b.channels):
+        f0 = ch.objective(2, lam2[c], torch.zeros_like(low[c]), low[c])[0]
+        fn = ch.objective(2, lam2[c], x_net[c], low[c])[0]
+        per.append({"n": sz[c], "F_cold_at_K": r_cold[c].objective, "F_warm_at_K": r_warm[c].objective,
+                    "warm_minus_cold_rel": (r_warm[c].objective - r_cold[c].objective) / abs(r_cold[c].objective),
+                    "F_zero": f0, "F_network": fn})
+    out["per_channel"] = per
+    # time to tolerance on the first channel of the largest size
+    c8 = sz.index(max(sizes))
+    ch = b.channels[c8]
+    ch.set_lipschitz(2, r_cold[c8].theta)
+    trajs = {}
+    for name, x0 in (("cold", None), ("network", x_net[c8])):
+        trajs[name] = ws.trajectory(ch, lam2[c8], low[c8], x0=x0, iters=horizon, every=every)
+        log(f"pipeline: {sz[c8]}^2 trajectory from {name} done, F = {trajs[name]['F'][-1]:.12g}")
+    f_ref = min(min(t_["F"]) for t_ in trajs.values())
+    ttt = {"channel": c8, "n": sz[c8], "horizon": horizon, "every": every, "f_ref": f_ref,
+           "ms_per_iter": trajs["cold"]["ms"][-1] / trajs["cold"]["k"][-1]}
+    for name, warm_ms in (("cold", 0.0), ("network", fwd_ms[c8])):
+        ttt[name] = {f"{tol:g}": ws.crossing(trajs[name], f_ref, tol, warm_ms) for tol in (1e-6, 1e-5)}
+    out["time_to_tol"] = ttt
+    out["workload"] = (f"{count} frequency channels 350-1050 MHz, sizes drawn from "
+                       f"{'/'.join(str(x) for x in sizes)} (seed {seed}), 512 antennas 4 h at 10 s, cut 10%, "
+                       f"positivity on; {iters} iterations per step batched; the packaged 1024^2-trained "
+                       f"network as the step-2 start")
+    return out
+
+
 def batch_replicas(torch, pr, tensors, iL, count, iters=20):
     """`count` copies of the workload's problem as the channels of one batch
     (the kernels' work does not depend on the data, so this measures the
@@ -389,6 +488,9 @@ def main(argv=None):
     ap.add_argument("--psnr-iters", type=int, default=100,
                     help="FISTA iterations per major cycle and step in the partition study")
     ap.add_argument("--psnr-only", action="store_true", help="run only the partition study and print it")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="run only the whole method on 16 channels of uneven sizes up to 8192^2 (512 antennas, "
+                         "4 h at 10 s, cut 10%%) with the network's warm start, and print it")
     ap.add_argument("--no-dict", action="store_true")
     ap.add_argument("--batch-channels", type=int, default=8)
     ap.add_argument("--batch-sizes", type=int, nargs="+", default=[512, 1024, 2048, 4096],
@@ -424,6 +526,11 @@ def main(argv=None):
     import torch
     import synth
     from paper_2406_18356_amd import Solver
+
+    if args.pipeline:
+        rep = pipeline_bench(torch, torch.device("cuda:0"), horizon=args.ttt_horizon, every=args.ttt_every)
+        print(json.dumps({"pipeline": rep}), flush=True)
+        return 0
 
     if args.psnr_only:
         t = time.perf_counter()

@@ -23,6 +23,7 @@ from .generator import (
     grid_weights,
     partition_counts,
     make_problem,
+    make_problems,
     preset,
     PRESETS,
     tiny,
@@ -43,6 +44,7 @@ __all__ = [
     "grid_weights",
     "partition_counts",
     "make_problem",
+    "make_problems",
     "preset",
     "PRESETS",
     "tiny",

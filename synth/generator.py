@@ -168,7 +168,7 @@ def _hour_angles(arr: ArrayConfig) -> np.ndarray:
     return h_hours * (2.0 * np.pi / 24.0)
 
 
-def uv_tracks(xyz: np.ndarray, arr: ArrayConfig, chunk: int = 4096):
+def uv_tracks(xyz: np.ndarray, arr: ArrayConfig, chunk: int = 16384):
     """Yield (u, v) arrays (metres) for chunks of baselines over all hour angles."""
     b = _baselines(xyz)
     ha = _hour_angles(arr)
@@ -187,16 +187,23 @@ def uv_tracks(xyz: np.ndarray, arr: ArrayConfig, chunk: int = 4096):
 def _max_radius(xyz, arr):
     m = 0.0
     for u, v in uv_tracks(xyz, arr):
-        m = max(m, float(np.sqrt(np.max(u * u + v * v))))
-    return m
+        m = max(m, float(np.max(u * u + v * v)))
+    return float(np.sqrt(m))  # sqrt is monotone: the largest radius of the samples
+
+
+def _reflect(w: np.ndarray) -> np.ndarray:
+    """w[(-ky) mod P, (-kx) mod P]: the grid of the conjugate visibilities."""
+    return np.roll(w[::-1, ::-1], 1, axis=(0, 1))
 
 
 def grid_weights(xyz, arr: ArrayConfig, P: int, uv_fill: float, ell: float, delta: float, progress=None):
     """Natural-weight grids of the full set and of the L / H splits.
 
     Returns (w_full, w_L, w_H, counts).  Grids are P x P float64 in FFT order
-    (row = v cell, column = u cell, index k mod P).  `progress(message)`, if
-    given, is called every 8 chunks of baselines.
+    (row = v cell, column = u cell, index k mod P).  Every visibility and its
+    conjugate land on the grid: the visibilities are counted per cell, and the
+    conjugates are that count reflected through the origin.  `progress(message)`,
+    if given, is called for every chunk of baselines.
     """
     rmax = _max_radius(xyz, arr)
     scale = uv_fill * P / rmax
@@ -205,27 +212,28 @@ def grid_weights(xyz, arr: ArrayConfig, P: int, uv_fill: float, ell: float, delt
     w_H = np.zeros(P * P, dtype=np.float64)
     n_all = n_L = n_H = n_LH = 0
     for chunk, (u, v) in enumerate(uv_tracks(xyz, arr)):
-        if progress is not None and chunk % 8 == 0:
+        if progress is not None:
             progress(f"gridding baseline chunk {chunk}")
         uc, vc = u * scale, v * scale
         r = np.sqrt(uc * uc + vc * vc)
         iu = np.rint(uc).astype(np.int64)
         iv = np.rint(vc).astype(np.int64)
         idx = (iv % P) * P + (iu % P)
-        idx_h = ((-iv) % P) * P + ((-iu) % P)
         in_L = r <= ell + delta
         in_H = r >= ell - delta
-        for w, mask in ((w_full, None), (w_L, in_L), (w_H, in_H)):
-            a = idx if mask is None else idx[mask]
-            bh = idx_h if mask is None else idx_h[mask]
-            w += np.bincount(a, minlength=P * P)
-            w += np.bincount(bh, minlength=P * P)
+        w_full += np.bincount(idx, minlength=P * P)
+        w_L += np.bincount(idx[in_L], minlength=P * P)
+        w_H += np.bincount(idx[in_H], minlength=P * P)
         n_all += r.size
         n_L += int(in_L.sum())
         n_H += int(in_H.sum())
         n_LH += int((in_L & in_H).sum())
     counts = {"V": n_all, "V_L": n_L, "V_H": n_H, "V_LH": n_LH}
-    return w_full.reshape(P, P), w_L.reshape(P, P), w_H.reshape(P, P), counts
+    grids = []
+    for w in (w_full, w_L, w_H):
+        w = w.reshape(P, P)
+        grids.append(w + _reflect(w))
+    return grids[0], grids[1], grids[2], counts
 
 
 def partition_counts(radius: np.ndarray, ell: float, delta: float) -> dict:
@@ -365,6 +373,36 @@ def sky_set(base: Problem, count: int, seed: int, workers: int = 1) -> list:
         members = [_sky_member(base, seed, i) for i in range(count)]
     return [dataclasses.replace(base, sky=sky, psf_full=None, dirty_full=None, dirty_L=dl, dirty_H=dh)
             for sky, dl, dh in members]
+
+
+def _make_problem_of(args):
+    i, cfg, verbose = args
+    stage = (lambda msg: print(f"channel {i} ({cfg.n}^2): {msg}", flush=True)) if verbose else None
+    return i, make_problem(cfg, with_full=False, progress=stage)
+
+
+def make_problems(cfgs, workers: int = 1, progress=None, verbose: bool = False) -> list:
+    """make_problem(cfg, with_full=False) for every configuration, in order,
+    in forked worker processes when workers > 1 (a problem depends on its
+    configuration alone).  `progress(i, problem)` is called as each finishes;
+    with `verbose` every problem prints its stages as they start."""
+    cfgs = list(cfgs)
+    out = [None] * len(cfgs)
+    jobs = [(i, c, verbose) for i, c in enumerate(cfgs)]
+    if workers > 1 and len(cfgs) > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(min(workers, len(cfgs))) as pool:
+            for i, pr in pool.imap_unordered(_make_problem_of, jobs, chunksize=1):
+                out[i] = pr
+                if progress is not None:
+                    progress(i, pr)
+    else:
+        for job in jobs:
+            i, out[i] = _make_problem_of(job)
+            if progress is not None:
+                progress(i, out[i])
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -81,3 +81,39 @@ def test_sky_set_does_not_depend_on_workers():
         assert np.array_equal(x.sky, y.sky)
         assert np.array_equal(x.dirty_L, y.dirty_L) and np.array_equal(x.dirty_H, y.dirty_H)
     assert not np.array_equal(a[0].sky, a[1].sky)
+
+
+def test_grid_weights_counts_every_visibility_and_its_conjugate():
+    """The grids against a direct count: every sample (u, v) and its
+    conjugate (-u, -v) add one to their nearest cells, for the full set and
+    for the L and H splits, whatever the chunking of the baselines."""
+    from synth.generator import grid_weights
+
+    arr = ArrayConfig(n_ant=12, hours=2.0, dt_s=900.0)
+    xyz = make_antennas(arr, np.random.default_rng(5))
+    P, fill, ell, delta = 48, 0.25, 6.0, 2.0
+    wf, wl, wh, counts = grid_weights(xyz, arr, P, fill, ell, delta)
+    u = np.concatenate([a for a, _ in uv_tracks(xyz, arr, chunk=7)])
+    v = np.concatenate([b for _, b in uv_tracks(xyz, arr, chunk=7)])
+    scale = fill * P / np.sqrt(np.max(u * u + v * v))
+    ref = {k: np.zeros((P, P)) for k in "flh"}
+    for uu, vv in zip(u * scale, v * scale):
+        r = np.hypot(uu, vv)
+        iu, iv = int(np.rint(uu)), int(np.rint(vv))
+        for k, keep in (("f", True), ("l", r <= ell + delta), ("h", r >= ell - delta)):
+            if keep:
+                ref[k][iv % P, iu % P] += 1
+                ref[k][-iv % P, -iu % P] += 1
+    np.testing.assert_array_equal(wf, ref["f"])
+    np.testing.assert_array_equal(wl, ref["l"])
+    np.testing.assert_array_equal(wh, ref["h"])
+    assert counts["V"] == u.size and wf.sum() == 2 * u.size
+
+
+def test_make_problems_does_not_depend_on_workers():
+    cfgs = synth.channel_set(3, sizes=(16, 32), seed=2, n_ant=12, dt_s=1800.0)
+    a = synth.make_problems(cfgs)
+    b = synth.make_problems(cfgs, workers=3)
+    for x, y, c in zip(a, b, cfgs):
+        assert x.n == c.n
+        assert np.array_equal(x.dirty_H, y.dirty_H) and np.array_equal(x.psf_L, y.psf_L)
