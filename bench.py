@@ -138,6 +138,76 @@ def batch_bench(torch, dev, count, iters, seed=4, sizes=(512, 1024, 2048, 4096))
     return out
 
 
+def frequency_bench(torch, dev, count=64, iters=500, workers=16, nu_lo=350.0, nu_hi=1050.0):
+    """One sky, the 4096^2 workload's, observed in `count` frequency channels
+    across nu_lo-nu_hi MHz with the same array: channel c's baselines scale
+    with nu_c, so its longest one lands at (nu_c / nu_hi) P/4 cells and its
+    cut (15 %) is taken from that radius.  Both steps batched (`iters`
+    iterations each, i_L from the batched step 1) against the channels solved
+    one after the other by one context of the same size."""
+    import synth
+    from paper_2406_18356_amd import Batch, Solver
+
+    base = synth.preset("sky4096")
+    cfgs = [base.replace(uv_fill=0.25 * (nu_lo + (nu_hi - nu_lo) * c / max(count - 1, 1)) / nu_hi)
+            for c in range(count)]
+    t = time.perf_counter()
+    prs = synth.make_problems(cfgs, workers=workers,
+                              progress=lambda i, p: log(f"frequency channels: {i} generated, "
+                                                        f"{time.perf_counter() - t:.0f} s"))
+    gen_s = time.perf_counter() - t
+    n = base.n
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
+    b = Batch([n] * count, positivity=True)
+    for pr, ch in zip(prs, b.channels):
+        ch.set_dirty_psf(1, T(pr.dirty_L), T(pr.psf_L))
+        dh = T(pr.dirty_H)
+        ch.set_dirty_psf(2, dh, T(pr.psf_H))
+        sig2 = ch.estimate_sigma2(dh)
+        ch.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+    b.autotune(reps=5)
+    out = {"channels": count, "n": n, "iters": iters, "generate_s": gen_s,
+           "workspace_gib": b.workspace_bytes / 2**30}
+    lam1 = [ch.default_lambda(1, 1, 0.05) for ch in b.channels]
+    b.solve(1, lam1, iters, image=True)  # theta, graph capture
+    torch.cuda.synchronize()
+    _, imgs, r1 = b.solve(1, lam1, iters, image=True)
+    low = [im.contiguous() for im in imgs]
+    lam2 = [ch.default_lambda(2, 1, 0.05) for ch in b.channels]
+    b.solve(2, lam2, iters, low_res=low)
+    torch.cuda.synchronize()
+    _, r2 = b.solve(2, lam2, iters, low_res=low)
+    out["batched_step1_channel_iters_per_s"] = count * iters / (r1[0].elapsed_ms * 1e-3)
+    out["batched_step2_channel_iters_per_s"] = count * iters / (r2[0].elapsed_ms * 1e-3)
+    log(f"frequency channels: batched step 1 {r1[0].elapsed_ms / iters * 1e3:.1f} us, "
+        f"step 2 {r2[0].elapsed_ms / iters * 1e3:.1f} us per iteration of all channels")
+    # one context, the channels one after the other (iteration loops timed)
+    s = Solver(n, positivity=True)
+    ms1 = ms2 = 0.0
+    for c, pr in enumerate(prs):
+        s.set_dirty_psf(1, T(pr.dirty_L), T(pr.psf_L))
+        dh = T(pr.dirty_H)
+        s.set_dirty_psf(2, dh, T(pr.psf_H))
+        sig2 = s.estimate_sigma2(dh)
+        s.set_filters(pr.ell, pr.delta, sig2, 1e-3 * sig2)
+        if c == 0:
+            s.autotune(reps=5)
+        s.set_lipschitz(1, r1[c].theta)
+        s.set_lipschitz(2, r2[c].theta)
+        _, q1 = s.step1(lam1[c], iters)
+        _, q2 = s.step2(lam2[c], low[c], iters)
+        ms1 += q1.elapsed_ms
+        ms2 += q2.elapsed_ms
+        if (c + 1) % 16 == 0:
+            log(f"frequency channels: {c + 1} solved one after the other")
+    out["sequential_step1_channel_iters_per_s"] = count * iters / (ms1 * 1e-3)
+    out["sequential_step2_channel_iters_per_s"] = count * iters / (ms2 * 1e-3)
+    out["workload"] = (f"the 4096x4096 workload's sky in {count} frequency channels {nu_lo:g}-{nu_hi:g} MHz "
+                       f"(197 antennas 8 h at 30 s, longest baseline and cut scaled with frequency, cut 15%), "
+                       f"positivity on, {iters} iterations per step")
+    return out
+
+
 def pipeline_bench(torch, dev, count=16, iters=500, seed=5, sizes=(1024, 2048, 4096, 8192), horizon=24000,
                    every=500, workers=16):
     """The whole method on the frequency channels of one observation with
@@ -488,6 +558,9 @@ def main(argv=None):
     ap.add_argument("--psnr-iters", type=int, default=100,
                     help="FISTA iterations per major cycle and step in the partition study")
     ap.add_argument("--psnr-only", action="store_true", help="run only the partition study and print it")
+    ap.add_argument("--frequency-channels", type=int, default=0, metavar="C",
+                    help="run only the 4096^2 workload's sky in C frequency channels (batched against one after "
+                         "the other) and print it")
     ap.add_argument("--pipeline", action="store_true",
                     help="run only the whole method on 16 channels of uneven sizes up to 8192^2 (512 antennas, "
                          "4 h at 10 s, cut 10%%) with the network's warm start, and print it")
@@ -526,6 +599,11 @@ def main(argv=None):
     import torch
     import synth
     from paper_2406_18356_amd import Solver
+
+    if args.frequency_channels:
+        rep = frequency_bench(torch, torch.device("cuda:0"), count=args.frequency_channels)
+        print(json.dumps({"frequency_channels": rep}), flush=True)
+        return 0
 
     if args.pipeline:
         rep = pipeline_bench(torch, torch.device("cuda:0"), horizon=args.ttt_horizon, every=args.ttt_every)

@@ -2122,10 +2122,11 @@ msr_status msr_time_pass(msr_ctx* c, int step, int which, int reps, double* ms_o
 // Batched solves: many channels (frequency channels of one observation, each
 // its own two-step problem) advanced together.  Channels of equal image size
 // form a group; a group's workspaces are laid out back to back with one
-// stride, so each pass of an iteration is ONE launch for the whole group
-// (grid y = channel).  The fixed-count iteration loop of all groups is
-// captured once into a HIP graph (one branch per group, so groups of
-// different sizes overlap) and replayed.
+// stride.  At each solve a group is split into runs of consecutive members
+// with similar kept columns, and each pass of an iteration is ONE launch for
+// a whole run (grid y = channel).  The fixed-count iteration loop of all
+// runs is captured once into a HIP graph (runs spread over four streams, so
+// runs of different sizes or widths overlap) and replayed.
 // =============================================================================
 struct msr_batch {
     struct Group {
@@ -2135,8 +2136,13 @@ struct msr_batch {
         size_t chan_off = 0;       // ChanScalars[members]
         size_t chanf_off = 0;      // FilterCoef[members]
     };
+    // Members [i0, i1) of a group launched together in one solve (a run).
+    struct Run {
+        int group, i0, i1;
+    };
     std::vector<msr_ctx*> ch;
     std::vector<Group> groups;
+    std::vector<Run> runs;  // the runs of the last solve
     int prec = 32, device = 0;
     size_t total = 0;
     char* ws = nullptr;
@@ -2265,46 +2271,88 @@ template <typename R>
 struct BatchImpl {
     msr_batch* b;
 
-    // Group g's launches: the first member's context, spread over the group.
-    Impl<R> group_impl(const msr_batch::Group& g) const {
-        msr_ctx* c0 = b->ch[g.members[0]];
-        Impl<R> im(c0);
+    // The launches of run r: its first member's context, spread over the
+    // run's members with the run's widest kept columns.
+    Impl<R> run_impl(const msr_batch::Run& r) const {
+        const msr_batch::Group& g = b->groups[r.group];
+        Impl<R> im(b->ch[g.members[r.i0]]);
         int K1 = 0, K2 = 0, KL = 0;
-        for (int m : g.members) {
-            K1 = std::max(K1, b->ch[m]->K[0]);
-            K2 = std::max(K2, b->ch[m]->K[1]);
-            KL = std::max(KL, b->ch[m]->KL);
+        for (int j = r.i0; j < r.i1; ++j) {
+            const msr_ctx* x = b->ch[g.members[j]];
+            K1 = std::max(K1, x->K[0]);
+            K2 = std::max(K2, x->K[1]);
+            KL = std::max(KL, x->KL);
         }
-        im.set_group((int)g.members.size(), (long long)g.stride,
-                     reinterpret_cast<const ChanScalars<R>*>(b->ws + g.chan_off),
-                     reinterpret_cast<const FilterCoef<R>*>(b->ws + g.chanf_off), K1, K2, KL);
+        im.set_group(r.i1 - r.i0, (long long)g.stride,
+                     reinterpret_cast<const ChanScalars<R>*>(b->ws + g.chan_off) + r.i0,
+                     reinterpret_cast<const FilterCoef<R>*>(b->ws + g.chanf_off) + r.i0, K1, K2, KL);
         return im;
+    }
+
+    // Splits every group into runs of consecutive members whose kept columns
+    // in this step (K_L in step 1; K_H and the low band in step 2) stay
+    // within a factor kRunSpread of each other.  A run's launches read its
+    // widest columns for every member, so one launch over channels of
+    // frequency-scaled coverage would pay the highest frequency's width for
+    // all of them; consecutive members, because the launches of a run need
+    // its workspaces at one stride.
+    void plan_runs(int step) {
+        constexpr double kRunSpread = 1.2;
+        b->runs.clear();
+        for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
+            const msr_batch::Group& g = b->groups[gi];
+            auto width = [&](int j, int q) {
+                const msr_ctx* x = b->ch[g.members[j]];
+                return std::max(1, step == 1 ? x->K[0] : (q == 0 ? x->K[1] : x->KL));
+            };
+            int i0 = 0, lo[2] = {width(0, 0), width(0, 1)}, hi[2] = {lo[0], lo[1]};
+            for (int j = 1; j < (int)g.members.size(); ++j) {
+                bool fits = true;
+                for (int q = 0; q < 2; ++q) {
+                    const int w = width(j, q);
+                    fits = fits && std::max(hi[q], w) <= kRunSpread * std::min(lo[q], w);
+                }
+                if (!fits) {
+                    b->runs.push_back({gi, i0, j});
+                    i0 = j;
+                    for (int q = 0; q < 2; ++q) lo[q] = hi[q] = width(j, q);
+                } else {
+                    for (int q = 0; q < 2; ++q) {
+                        lo[q] = std::min(lo[q], width(j, q));
+                        hi[q] = std::max(hi[q], width(j, q));
+                    }
+                }
+            }
+            b->runs.push_back({gi, i0, (int)g.members.size()});
+        }
     }
 
     std::vector<long long> graph_key(int step, int iters) const {
         std::vector<long long> k{step, iters};
-        for (const auto& g : b->groups) {
-            Impl<R> im = group_impl(g);
-            msr_ctx* c0 = b->ch[g.members[0]];
-            k.insert(k.end(), {(long long)g.members.size(), im.Ks(1), im.Ks(2), im.KLs(), c0->var_row[step - 1],
-                               c0->var_col[step - 1], c0->var_filt});
+        for (const auto& r : b->runs) {
+            Impl<R> im = run_impl(r);
+            msr_ctx* c0 = b->ch[b->groups[r.group].members[r.i0]];
+            k.insert(k.end(), {(long long)r.group, (long long)r.i0, (long long)r.i1, im.Ks(1), im.Ks(2), im.KLs(),
+                               c0->var_row[step - 1], c0->var_col[step - 1], c0->var_filt});
         }
         return k;
     }
 
-    // Captures `iters` iterations of every group into b->exec.
+    // Captures `iters` iterations of every run into b->exec.
     msr_status capture(int step, int iters) {
         hipStream_t s0 = b->st[0];
         BHIPCHK(b, hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
         msr_status st = MSR_OK;
-        const int ns = std::min<int>((int)b->groups.size(), msr_batch::kStreams);
+        const int ns = std::min<int>((int)b->runs.size(), msr_batch::kStreams);
         if (hipEventRecord(b->fork, s0) != hipSuccess) st = bfail(b, MSR_ERR_HIP, "fork event");
         for (int i = 1; i < ns && st == MSR_OK; ++i)
             if (hipStreamWaitEvent(b->st[i], b->fork, 0) != hipSuccess) st = bfail(b, MSR_ERR_HIP, "fork wait");
-        for (size_t gi = 0; gi < b->groups.size() && st == MSR_OK; ++gi) {
-            Impl<R> im = group_impl(b->groups[gi]);
-            hipStream_t s = b->st[gi % ns];
-            for (int k = 1; k <= iters && st == MSR_OK; ++k) st = bchan(b, b->groups[gi].members[0], im.iterate(step, k, 0.0, 0.0, s));
+        for (size_t ri = 0; ri < b->runs.size() && st == MSR_OK; ++ri) {
+            const msr_batch::Run& r = b->runs[ri];
+            Impl<R> im = run_impl(r);
+            hipStream_t s = b->st[ri % ns];
+            const int c0 = b->groups[r.group].members[r.i0];
+            for (int k = 1; k <= iters && st == MSR_OK; ++k) st = bchan(b, c0, im.iterate(step, k, 0.0, 0.0, s));
         }
         for (int i = 1; i < ns && st == MSR_OK; ++i) {
             if (hipEventRecord(b->join[i], b->st[i]) != hipSuccess || hipStreamWaitEvent(s0, b->join[i], 0) != hipSuccess)
@@ -2436,7 +2484,7 @@ struct BatchImpl {
             if (!persistent_ok(&why)) return bfail(b, MSR_ERR_UNSUPPORTED, "%s", why.c_str());
         }
         // 1. per channel: theta, beta_0, constraint, spectrum of alpha_0 (on
-        //    every column its group's launches read: nothing unwritten is read,
+        //    every column its run's launches read: nothing unwritten is read,
         //    not even where a zero factor would cancel it)
         std::vector<double> mu(C);
         for (int c = 0; c < C; ++c) {
@@ -2444,13 +2492,15 @@ struct BatchImpl {
                 return bfail(b, MSR_ERR_UNSUPPORTED, "channel %d: batched solves start from x0, not a loaded state", c);
             b->ch[c]->state_step = 0;
         }
-        for (const auto& g : b->groups) {
-            const Impl<R> gi = group_impl(g);
-            for (int c : g.members) {
+        plan_runs(step);
+        for (const auto& r : b->runs) {
+            const Impl<R> ri = run_impl(r);
+            for (int j = r.i0; j < r.i1; ++j) {
+                const int c = b->groups[r.group].members[j];
                 Impl<R> im(b->ch[c]);
-                // the grouped launches read the group's widest columns; the
+                // the launches of a run read its widest columns; the
                 // persistent launch reads each channel's own
-                const int ka = b->mode == 1 ? 0 : gi.KA(step), kl = b->mode == 1 ? 0 : gi.KLs();
+                const int ka = b->mode == 1 ? 0 : ri.KA(step), kl = b->mode == 1 ? 0 : ri.KLs();
                 TRY(bchan(b, c, im.prepare(step, step == 2 ? static_cast<const R*>(low_res[c]) : nullptr,
                                            x0 ? static_cast<const R*>(x0[c]) : nullptr, &mu[c], s, ka, kl)));
             }
@@ -2477,7 +2527,7 @@ struct BatchImpl {
             BHIPCHK(b, hipMemcpyAsync(b->ws + g.chanf_off, cf.data(), m * sizeof(FilterCoef<R>), hipMemcpyHostToDevice, s));
             BHIPCHK(b, hipStreamSynchronize(s));  // the host arrays go out of scope
         }
-        // 3. the iterations: one graph for all groups
+        // 3. the iterations: one graph for all runs
         if (iters > 0) {
             const std::vector<long long> key = graph_key(step, iters);
             if (!b->exec || key != b->key) {

@@ -103,6 +103,40 @@ def test_batch_matches_single_channel_solves(torch_dev, prec, positivity):
             assert float(models2[c].min()) >= 0
 
 
+def test_batch_frequency_channels_match_single_channel_solves(torch_dev):
+    """Channels of one size whose coverage scales with frequency (350-1050
+    MHz): their kept columns span about 3x, so the solve splits the size group
+    into several runs of similar width.  Every channel must still match its
+    single-context solve, in both steps."""
+    from paper_2406_18356_amd import Batch, Solver
+
+    cfgs = synth.channel_set(6, sizes=(64,), seed=3, n_ant=16, dt_s=600.0)
+    prs = [synth.make_problem(c) for c in cfgs]
+    b = Batch([pr.n for pr in prs], positivity=True)
+    singles = [Solver(pr.n, positivity=True) for pr in prs]
+    for x in [b] + singles:
+        _poison(x)
+    for pr, ch, s in zip(prs, b.channels, singles):
+        _setup(torch_dev, ch, pr, 32)
+        _setup(torch_dev, s, pr, 32)
+    K = 20
+    lam1 = [0.05 * np.linalg.norm(pr.dirty_L) for pr in prs]
+    models1, imgs1, res1 = b.solve(1, lam1, K, image=True)
+    for c, s in enumerate(singles):
+        s.set_lipschitz(1, res1[c].theta)
+        bs, ims, rs = s.step1(lam1[c], K, image=True)
+        assert rel(models1[c].cpu().numpy(), bs.cpu().numpy()) <= SAME, c
+        assert rel(imgs1[c].cpu().numpy(), ims.cpu().numpy()) <= SAME, c
+    low = [m.clone() for m in imgs1]
+    lam2 = [0.05 * np.linalg.norm(pr.dirty_H) for pr in prs]
+    models2, res2 = b.solve(2, lam2, K, low_res=low)
+    for c, s in enumerate(singles):
+        s.set_lipschitz(2, res2[c].theta)
+        bs, rs = s.step2(lam2[c], low[c], K)
+        assert rel(models2[c].cpu().numpy(), bs.cpu().numpy()) <= SAME, c
+        assert res2[c].objective == pytest.approx(rs.objective, rel=1e-6)
+
+
 def test_batch_against_oracle_and_graph_replay(torch_dev):
     """FP64 batch vs the FP64 oracle per channel; a second solve with other
     lambdas and warm starts replays the cached graph with new parameters."""
