@@ -91,11 +91,14 @@ def batch_bench(torch, dev, count, iters, seed=4, sizes=(512, 1024, 2048, 4096))
 
     t = time.perf_counter()
     cfgs = synth.channel_set(count, sizes=sizes, seed=seed)
-    prs = []
-    for i, c in enumerate(cfgs):
-        prs.append(synth.make_problem(c, with_full=False))
-        if (i + 1) % 8 == 0 or i + 1 == len(cfgs):
-            log(f"batch: {i + 1}/{len(cfgs)} channels generated")
+    done = []
+
+    def progress(i, p):
+        done.append(i)
+        if len(done) % 8 == 0 or len(done) == len(cfgs):
+            log(f"batch: {len(done)}/{len(cfgs)} channels generated")
+
+    prs = synth.make_problems(cfgs, workers=16, progress=progress)
     log(f"batch: {count} channels {[p.n for p in prs]} generated in {time.perf_counter() - t:.1f} s")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)  # noqa: E731
     b = Batch([p.n for p in prs], positivity=True)

@@ -106,12 +106,14 @@ def test_batch_matches_single_channel_solves(torch_dev, prec, positivity):
 def test_batch_frequency_channels_match_single_channel_solves(torch_dev):
     """Channels of one size whose coverage scales with frequency (350-1050
     MHz): their kept columns span about 3x, so the solve splits the size group
-    into several runs of similar width.  Every channel must still match its
-    single-context solve, in both steps."""
+    (2048^2: groups of 2048^2 and larger are split) into several runs of
+    similar width.  Every channel must still match its single-context solve,
+    in both steps."""
     from paper_2406_18356_amd import Batch, Solver
 
-    cfgs = synth.channel_set(6, sizes=(64,), seed=3, n_ant=16, dt_s=600.0)
-    prs = [synth.make_problem(c) for c in cfgs]
+    cfgs = synth.channel_set(4, sizes=(2048,), seed=3, n_ant=16, dt_s=600.0)
+    print("frequency channels: synthesising 4 x 2048^2", flush=True)
+    prs = [synth.make_problem(c, with_full=False) for c in cfgs]
     b = Batch([pr.n for pr in prs], positivity=True)
     singles = [Solver(pr.n, positivity=True) for pr in prs]
     for x in [b] + singles:
@@ -119,7 +121,7 @@ def test_batch_frequency_channels_match_single_channel_solves(torch_dev):
     for pr, ch, s in zip(prs, b.channels, singles):
         _setup(torch_dev, ch, pr, 32)
         _setup(torch_dev, s, pr, 32)
-    K = 20
+    K = 10
     lam1 = [0.05 * np.linalg.norm(pr.dirty_L) for pr in prs]
     models1, imgs1, res1 = b.solve(1, lam1, K, image=True)
     for c, s in enumerate(singles):
