@@ -211,6 +211,33 @@ def frequency_bench(torch, dev, count=64, iters=500, workers=16, nu_lo=350.0, nu
     return out
 
 
+def unet_forward_roofline(n, base_width=32, levels=4):
+    """The network's forward pass at n^2 against its per-layer roofline: each
+    3x3 convolution takes the longer of its MFMA work (K padded to 32) at the
+    dense bf16 peak and its HBM bytes (bf16 input, the decoder's upsampled
+    half read at quarter resolution, bf16 output) at 8 TB/s; the pooling,
+    head and input kernels their bytes.  Returns (mfma flops, bytes, seconds)."""
+    from paper_2406_18356_amd import unet_layers
+
+    lay = unet_layers(base_width, levels)
+    lvl = [j for j in range(levels) for _ in (0, 1)] + [j for j in range(levels - 2, -1, -1) for _ in (0, 1)]
+    flops = nbytes = secs = 0.0
+    for i, ((ci, co, kpad), j) in enumerate(zip(lay, lvl)):
+        P = (n * n) >> (2 * j)
+        fl = 2.0 * P * co * kpad
+        dec_first = i >= 2 * levels and (i - 2 * levels) % 2 == 0
+        inb = ((P // 4) * (ci - co) + P * co) * 2 if dec_first else P * ci * 2
+        b = inb + P * co * 2
+        flops, nbytes = flops + fl, nbytes + b
+        secs += max(fl / (BF16_MFMA_TFLOPS * 1e12), b / (HBM_PEAK_GBS * 1e9))
+    for j in range(levels - 1):  # 2x2 pooling
+        P, C = (n * n) >> (2 * j), base_width << j
+        b = P * C * 2 + (P // 4) * C * 2
+        nbytes, secs = nbytes + b, secs + b / (HBM_PEAK_GBS * 1e9)
+    b = n * n * (base_width * 2 + 4 + 2 * 4 + 8 * 2)  # head (bf16 in, float out); inputs (float in, bf16 out)
+    return flops, nbytes + b, secs + b / (HBM_PEAK_GBS * 1e9)
+
+
 def pipeline_bench(torch, dev, count=16, iters=500, seed=5, sizes=(1024, 2048, 4096, 8192), horizon=24000,
                    every=500, workers=16):
     """The whole method on the frequency channels of one observation with
@@ -867,8 +894,11 @@ def main(argv=None):
             e1.record()
             e1.synchronize()
             fms5 = e0.elapsed_time(e1) / 5
+            _, rb, rs = unet_forward_roofline(pr.n)
             ttt["unet_forward"] = {"image": pr.n, "ms": fms5, "mfma_tflops": fl / (fms5 * 1e-3) / 1e12,
-                                   "mfma_frac": fl / (fms5 * 1e-3) / 1e12 / BF16_MFMA_TFLOPS}
+                                   "mfma_frac": fl / (fms5 * 1e-3) / 1e12 / BF16_MFMA_TFLOPS,
+                                   "roofline_ms": rs * 1e3, "roofline_bytes": rb,
+                                   "frac_of_roofline": rs * 1e3 / fms5}
             del net
         log("time to tolerance:", json.dumps(ttt))
 
