@@ -397,19 +397,23 @@ msr_status msr_batch_autotune(msr_batch* batch, int reps, void* stream);
  * exact objective of the result (FP64), theta and the elapsed time of the whole
  * batched iteration loop.  Channels without a cached theta get one by power
  * iteration first.  The first call for a given (step, iters, kept columns,
- * variants) captures the graph; later calls replay it.  Blocks until done. */
+ * variants, runs) captures the graph; later calls replay it.  Blocks until done. */
 msr_status msr_batch_solve(msr_batch* batch, int step, const double* lambda, int iters, const void* const* low_res,
                            const void* const* x0, void* const* model_out, void* const* image_out, msr_result* res,
                            void* stream);
 
 /* How msr_batch_solve runs the iterations.
- *  mode 0 (default): one launch per pass for each group of equal-sized
- *    channels, all captured in one graph (each size on its own stream).
+ *  mode 0 (default): one launch per pass for each run of equal-sized
+ *    channels with similar kept columns (groups of 2048^2 and larger images
+ *    are cut into runs whose kept columns stay within 1.2x; smaller sizes
+ *    form one run), all captured in one graph (runs spread over four streams).
  *  Mode 1 is switched off (msr_batch_set_mode returns MSR_ERR_UNSUPPORTED): its first
- *  run did not return within minutes and the cause has not been found.
+ *  solve did not return within minutes, in two designs of its memory
+ *  ordering, and the cause has not been found.
  *  mode 1: one persistent launch for all channels and all iterations.  The
  *    passes of Algorithm 1 (four per step-1 iteration, six per step-2) of
- *    every channel become work items taken from a ticket counter in
+ *    every channel become work items; each channel is assigned to one XCD,
+ *    whose blocks take its items from that XCD's ticket counter in
  *    iteration-major, then pass-major, then channel order; an item waits until
  *    the pass it reads from has finished on its channel (counters in device
  *    memory).  Each channel runs with its own kept columns (no widening to the

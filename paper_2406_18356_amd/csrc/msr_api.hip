@@ -2243,12 +2243,13 @@ bool plan_batch(int nch, const msr_config* cfgs, std::vector<msr_batch::Group>& 
     }
     if (pers) {
         // the persistent launch: 2 parities x 6 passes x channels descriptors,
-        // the item segments, the done counters and the control block
+        // each XCD's item segments, channel list and count, the done counters
+        // and the control block
         const size_t npc = (size_t)6 * nch;
         pers[0] = off;
         off += align_up(2 * npc * std::max(sizeof(PassDesc<float>), sizeof(PassDesc<double>)), kAlign);
         pers[1] = off;
-        off += align_up((npc + 1) * sizeof(int), kAlign);
+        off += align_up((kPersistXcds * (npc + 1) + kPersistXcds * (size_t)nch + kPersistXcds) * sizeof(int), kAlign);
         pers[2] = off;
         off += align_up(npc * sizeof(unsigned int), kAlign);
         pers[3] = off;
@@ -2418,25 +2419,56 @@ struct BatchImpl {
                 for (int p = 0; p < npass; ++p) desc[((size_t)c * npass + p) * 2 + (k & 1)] = rec[p];
             }
         }
-        std::vector<int> seg((size_t)npass * C + 1);
-        int off = 0;
-        for (int p = 0; p < npass; ++p)
-            for (int c = 0; c < C; ++c) {
-                seg[(size_t)p * C + c] = off;
-                off += desc[((size_t)c * npass + p) * 2].nblocks;
-            }
-        seg[(size_t)npass * C] = off;
-        if ((long long)off * iters >= (1LL << 32)) return bfail(b, MSR_ERR_INVALID, "too many work items for one launch");
+        // channels onto XCDs, the most work first onto the least loaded
+        // (work of a channel: blocks of its passes x its line length)
+        const int X = kPersistXcds;
+        std::vector<double> work(C);
+        for (int c = 0; c < C; ++c) {
+            double w = 0;
+            for (int p = 0; p < npass; ++p) w += (double)desc[((size_t)c * npass + p) * 2].nblocks;
+            work[c] = w * b->ch[c]->sh.N;
+        }
+        std::vector<int> order(C);
+        for (int c = 0; c < C; ++c) order[c] = c;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return work[a] > work[bb]; });
+        std::vector<std::vector<int>> xch(X);
+        std::vector<double> load(X, 0.0);
+        for (int c : order) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            xch[x].push_back(c);
+            load[x] += work[c];
+        }
+        // per XCD: segments (pass-major over its channels), then channel
+        // lists [X][C] and counts [X], one int array
+        const size_t sx = (size_t)npass * C + 1;
+        std::vector<int> tab(X * sx + (size_t)X * C + X, 0);
+        int most = 0;
+        for (int x = 0; x < X; ++x) {
+            int off = 0;
+            const int n = (int)xch[x].size();
+            for (int p = 0; p < npass; ++p)
+                for (int j = 0; j < n; ++j) {
+                    tab[x * sx + (size_t)p * n + j] = off;
+                    off += desc[((size_t)xch[x][j] * npass + p) * 2].nblocks;
+                }
+            tab[x * sx + (size_t)npass * n] = off;
+            for (int j = 0; j < n; ++j) tab[X * sx + (size_t)x * C + j] = xch[x][j];
+            tab[X * sx + (size_t)X * C + x] = n;
+            most = std::max(most, off);
+        }
+        if ((long long)most * iters >= (1LL << 32)) return bfail(b, MSR_ERR_INVALID, "too many work items for one launch");
         PersistCtl ctl{};
         ctl.give_up = b->give_up;
         BHIPCHK(b, hipMemcpyAsync(b->ws + b->p_desc, desc.data(), sizeof(PassDesc<R>) * desc.size(),
                                   hipMemcpyHostToDevice, s));
-        BHIPCHK(b, hipMemcpyAsync(b->ws + b->p_seg, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice, s));
+        BHIPCHK(b, hipMemcpyAsync(b->ws + b->p_seg, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, s));
         BHIPCHK(b, hipMemcpyAsync(b->ws + b->p_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, s));
         BHIPCHK(b, hipStreamSynchronize(s));  // the host vectors go out of scope
         PersistArgs<float> pa{};
         pa.desc = reinterpret_cast<const PassDesc<float>*>(b->ws + b->p_desc);
         pa.seg = reinterpret_cast<const int*>(b->ws + b->p_seg);
+        pa.xch = pa.seg + X * sx;
+        pa.xn = pa.xch + (size_t)X * C;
         pa.done = reinterpret_cast<unsigned int*>(b->ws + b->p_done);
         pa.ctl = reinterpret_cast<PersistCtl*>(b->ws + b->p_ctl);
         pa.C = C;
@@ -2446,8 +2478,11 @@ struct BatchImpl {
         pa.spin_limit = b->spin_limit ? b->spin_limit : (1u << 22);
         int cus = 0;
         BHIPCHK(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-        const int grid = std::max(1, std::min(off * iters, cus * persist_occupancy_f32(with_4096)));
-        const std::vector<long long> key{step, iters, C, npass, with_4096, grid, off, (long long)pa.spin_limit};
+        // a multiple of the XCD count, so that every XCD holds the same
+        // number of the launch's blocks
+        const int grid = cus * persist_occupancy_f32(with_4096) / X * X;
+        if (grid < X) return bfail(b, MSR_ERR_UNSUPPORTED, "the persistent launch needs %d resident blocks", X);
+        const std::vector<long long> key{step, iters, C, npass, with_4096, grid, most, (long long)pa.spin_limit};
         hipStream_t s0 = b->st[0];
         if (!b->pexec || key != b->pkey) {
             if (b->pexec) (void)hipGraphExecDestroy(b->pexec);
@@ -2690,9 +2725,10 @@ constexpr bool kPersistentEnabled = false;
 msr_status msr_batch_set_mode(msr_batch* b, int mode, unsigned int spin_limit) {
     if (!b) return MSR_ERR_INVALID;
     if (mode != 0 && mode != 1) return bfail(b, MSR_ERR_INVALID, "mode must be 0 (launches per pass) or 1 (persistent)");
-    // Switched off: the first run of the persistent launch (four channels of
-    // 512 .. 2048, 30 step-1 iterations) did not return within minutes, and
-    // no cause has been found in its code; it stays off until one is.
+    // Switched off: the first solve of the persistent launch (four channels of
+    // 512 .. 2048, 30 step-1 iterations) did not return within minutes, in
+    // two designs of its memory ordering (agent-scope fences per item; queues
+    // per XCD with L1-only ordering), and no cause has been shown.
     if (mode == 1 && !kPersistentEnabled)
         return bfail(b, MSR_ERR_UNSUPPORTED, "the persistent launch (mode 1) is switched off");
     b->mode = mode;

@@ -14,9 +14,17 @@
 // is a smaller ticket held by a running block, so the smallest unfinished
 // ticket can always proceed.
 //
-// Memory.  Each XCD has its own L2: a block publishes its pass's results with
-// an agent-scope release (L2 write-back) before counting itself done, and a
-// waiting block acquires (L2 invalidate) after its dependency is met.
+// XCDs.  The device dispatches block b to XCD b % 8, and each XCD has its own
+// L2.  Every channel is assigned to one XCD (host side, longest work first
+// onto the least loaded XCD), and the blocks of XCD x take items only from
+// XCD x's queue (its own ticket counter and segments over its channels), so
+// an item and the items it depends on share one L2.  Memory ordering then
+// needs no L2 write-back or invalidation: a block waits for its stores to
+// complete (the vector L1 writes through to the L2) before it counts itself
+// done, and a waiting block invalidates its CU's L1 once its dependency is
+// met.  (Agent-scope fences instead write back and invalidate the whole L2
+// of the XCD; executed by every wave after every item, they made one
+// launch over four channels take minutes.)
 //
 // Bounded waits.  A wait polls its counter at most spin_limit times and also
 // stops when the host raised ctl->give_up or another block set ctl->abort;
@@ -47,17 +55,24 @@ struct PassDesc {
     ModeFilterL<R> ml;
 };
 
+constexpr int kPersistXcds = 8;  // XCDs of the device; block b runs on XCD b % 8
+
 struct PersistCtl {
-    unsigned int ticket;
+    unsigned int ticket[kPersistXcds];  // the work queue of each XCD
     int abort;    // a block gave up: every block returns
     int give_up;  // raised by the host: every block returns
-    int unused;
+    int unused[2];
 };
 
 template <typename R>
 struct PersistArgs {
     const PassDesc<R>* desc;  // [(c * npass + p) * 2 + (k & 1)]
-    const int* seg;           // blocks before segment (p, c) of an iteration, p-major; seg[npass * C] = all
+    // XCD x: seg[x * (npass * C + 1) + s] = blocks before segment s = (p, j)
+    // of an iteration, p-major over the XCD's channels j (seg[.. + npass n_x]
+    // = all); xch[x * C + j] = its channel j; xn[x] = n_x
+    const int* seg;
+    const int* xch;
+    const int* xn;
     unsigned int* done;       // [c * npass + p]: blocks of that pass finished, over all iterations
     PersistCtl* ctl;
     int C, npass, iters, k0;  // iterations k0 + 1 .. k0 + iters

@@ -92,20 +92,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
     __shared__ double red[2 * 4];
     __shared__ int item[5];  // k, p, c, b, go
     const int tid = threadIdx.x;
-    const int nseg = pa.npass * pa.C;
-    const unsigned int per = (unsigned int)pa.seg[nseg];
+    // this block's XCD and its queue: the XCD's channels and segments
+    const int x = (int)blockIdx.x % kPersistXcds;
+    const int nx = pa.xn[x];
+    if (nx == 0) return;
+    const int* seg = pa.seg + x * (pa.npass * pa.C + 1);
+    const int* xch = pa.xch + x * pa.C;
+    const int nseg = pa.npass * nx;
+    const unsigned int per = (unsigned int)seg[nseg];
     const unsigned int total = per * (unsigned int)pa.iters;
     for (;;) {
         if (tid == 0) {
             int go = 0;
             if (!persist_stop(pa.ctl)) {
-                const unsigned int t = __hip_atomic_fetch_add(&pa.ctl->ticket, 1u, __ATOMIC_RELAXED,
+                const unsigned int t = __hip_atomic_fetch_add(&pa.ctl->ticket[x], 1u, __ATOMIC_RELAXED,
                                                               __HIP_MEMORY_SCOPE_AGENT);
                 if (t < total) {
                     const int k = pa.k0 + (int)(t / per) + 1;
                     const int r = (int)(t % per);
-                    const int sg = persist_segment(pa.seg, nseg, r);
-                    const int p = sg / pa.C, c = sg % pa.C;
+                    const int sg = persist_segment(seg, nseg, r);
+                    const int p = sg / nx, c = xch[sg % nx];
                     // the pass before this one in channel c's chain
                     const int pp = p > 0 ? p - 1 : pa.npass - 1;
                     const int kk = p > 0 ? k - pa.k0 : k - pa.k0 - 1;  // its completed iterations needed
@@ -126,10 +132,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
                         }
                         __builtin_amdgcn_s_sleep(2);
                     }
+                    if (go) {
+                        // the dependency's results are in this XCD's L2: drop
+                        // whatever this CU's L1 holds of them from earlier
+                        // iterations (every wave of the block reads after the
+                        // barrier below)
+                        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+                    }
                     item[0] = k;
                     item[1] = p;
                     item[2] = c;
-                    item[3] = r - pa.seg[sg];
+                    item[3] = r - seg[sg];
                 }
             }
             item[4] = go;
@@ -139,7 +152,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
         // block-uniform, so the pass's arguments load into scalar registers
         const int k = __builtin_amdgcn_readfirstlane(item[0]), p = __builtin_amdgcn_readfirstlane(item[1]);
         const int c = __builtin_amdgcn_readfirstlane(item[2]), b = __builtin_amdgcn_readfirstlane(item[3]);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         // an opaque copy of the thread index per item: nothing a pass derives
         // from it can be hoisted out of the loop (it would stay live across
         // every pass body and exhaust the registers)
@@ -156,21 +168,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) p
                 if constexpr (NS > 3) persist_pass<R, 4096>(d, kind, g1, k, b, lds, red, tidx);
                 break;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // every wave's stores of this item have reached the L2 (the vector L1
+        // writes through) before the item is counted done
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0)
             __hip_atomic_fetch_add(&pa.done[c * pa.npass + p], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// Zeroes the ticket, abort flag and done counters before a launch (a kernel,
+// Zeroes the tickets, abort flag and done counters before a launch (a kernel,
 // not a memset, so that the launch can be captured in a graph and replayed).
 __global__ void persist_reset(PersistCtl* ctl, unsigned int* done, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        ctl->ticket = 0;
-        ctl->abort = 0;
-    }
+    if (i < kPersistXcds) ctl->ticket[i] = 0;
+    if (i == 0) ctl->abort = 0;
     if (i < n) done[i] = 0;
 }
 
