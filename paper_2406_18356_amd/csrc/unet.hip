@@ -657,18 +657,23 @@ __global__ void __launch_bounds__(256) head_sums_kernel(const float* __restrict_
 // ---------------------------------------------------------------------------
 // 2x2 average pool, NHWC bf16: out (B, H/2, W/2, C).
 __global__ void pool_kernel(const bf16* __restrict__ x, int B, int H, int W, int C, bf16* __restrict__ out) {
-    const size_t n = (size_t)B * (H / 2) * (W / 2) * C;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        size_t r = i / C;
-        const int x2 = (int)(r % (W / 2));
-        r /= (W / 2);
-        const int y2 = (int)(r % (H / 2));
-        const int b = (int)(r / (H / 2));
-        const size_t base = (((size_t)b * H + 2 * y2) * W + 2 * x2) * C + c;
-        const float s = (float)x[base] + (float)x[base + C] + (float)x[base + (size_t)W * C] +
-                        (float)x[base + (size_t)W * C + C];
-        out[i] = (bf16)(0.25f * s);
+    // item: output pixel q / (C / 8), channels 8 (q % (C / 8)); 16-byte loads
+    // and stores, 32-bit index arithmetic (B H W < 2^31, C a multiple of 8)
+    const unsigned G = (unsigned)C / 8, W2 = (unsigned)W / 2, H2 = (unsigned)H / 2;
+    const unsigned n = (unsigned)B * H2 * W2 * G;
+    for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const unsigned p2 = q / G, g = q - p2 * G;
+        const unsigned x2 = p2 % W2, r = p2 / W2, y2 = r % H2, b = r / H2;
+        const size_t base = (((size_t)b * H + 2 * y2) * W + 2 * x2) * C + g * 8;
+        const bf16x8 a = load8(x + base), c = load8(x + base + C);
+        const bf16x8 d = load8(x + base + (size_t)W * C), e = load8(x + base + (size_t)W * C + C);
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float s = (float)a[j] + (float)c[j] + (float)d[j] + (float)e[j];
+            o[j] = (bf16)(0.25f * s);
+        }
+        *reinterpret_cast<bf16x8*>(out + (size_t)p2 * C + g * 8) = o;
     }
 }
 
@@ -751,7 +756,7 @@ __global__ void pack_kernel(const float* __restrict__ dh, const float* __restric
                             const float* __restrict__ scale, int B, int HW, bf16* __restrict__ x) {
     const size_t n = (size_t)B * HW;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const float inv = 1.0f / scale[i / HW];
+        const float inv = 1.0f / scale[(unsigned)i / (unsigned)HW];  // B HW < 2^31
         bf16x8 v = zero8();
         v[0] = (bf16)(dh[i] * inv);
         v[1] = (bf16)(low[i] * inv);
@@ -778,7 +783,7 @@ __global__ void unpack_kernel(const float* __restrict__ out, const float* __rest
                               float* __restrict__ x0) {
     const size_t n = (size_t)B * HW;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        x0[i] = scale[i / HW] * fmaxf(out[i], 0.0f);
+        x0[i] = scale[(unsigned)i / (unsigned)HW] * fmaxf(out[i], 0.0f);  // B HW < 2^31
 }
 
 // Loss partials sum (out - t/s)^2 per block and gout = 2 (out - t/s) / n.
@@ -789,7 +794,7 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ out
     const size_t n = (size_t)B * HW;
     double s = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        const float d = out[i] - target[i] / scale[i / HW];
+        const float d = out[i] - target[i] / scale[(unsigned)i / (unsigned)HW];  // B HW < 2^31
         s += (double)d * d;
         gout[i] = 2.0f * d / (float)n;
     }
