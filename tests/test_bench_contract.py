@@ -47,3 +47,21 @@ def test_json_line_of_a_short_run(capsys):
     assert 0 < ro["frac"] < 1
     assert ro["frac"] == pytest.approx(ro["achieved"] / ro["peak"], rel=1e-12)
     assert d["cpu_baseline"] is None  # --no-cpu
+
+
+def test_unet_forward_roofline_counts_every_layer():
+    """The network's per-layer roofline at 4096^2: the MFMA work is the 14
+    convolutions' 2 P cout kpad (K padded to 32), the bytes at least every
+    convolution's bf16 input and output, and the time at least the larger of
+    the two totals over their peaks."""
+    from paper_2406_18356_amd import unet_layers
+
+    n = 4096
+    flops, nbytes, secs = bench.unet_forward_roofline(n)
+    lay = unet_layers(32, 4)
+    lvl = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0]
+    want = sum(2.0 * ((n * n) >> (2 * j)) * co * kpad for (ci, co, kpad), j in zip(lay, lvl))
+    assert flops == pytest.approx(want, rel=1e-12)
+    outs = sum(((n * n) >> (2 * j)) * co * 2 for (ci, co, kpad), j in zip(lay, lvl))
+    assert nbytes > 2 * outs  # every output written once and read at least once
+    assert secs >= max(flops / (bench.BF16_MFMA_TFLOPS * 1e12), nbytes / (bench.HBM_PEAK_GBS * 1e9))
